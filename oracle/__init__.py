@@ -1,0 +1,154 @@
+"""Plain FP64 CPU oracle of the 3D RSF level-set iteration (arXiv 2404.02813).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package; the HIP product path
+never does, and this package imports nothing from it.
+
+The arithmetic lives in ``rsf_oracle.c`` (plain C, OpenMP over z); this module
+only marshals NumPy arrays through ctypes.  ``real="f32"`` loads the same C
+source compiled with a float working type; it exists to measure how far
+rounding alone moves a trajectory, never as a reference.
+
+Functions (each follows the passage named in ``rsf_oracle.c``):
+    radius(sigma)                     truncation radius ceil(3 sigma)
+    weights(sigma)                    sampled, unit-sum Gaussian taps (Sec. 3)
+    conv3d(u, sigma)                  zero-padded separable Gaussian (Sec. 3)
+    step(I, phi, params, reg)         one iteration + its fields (Eq. 1, Sec. 3)
+    evolve(I, phi, params, iters)     ``iters`` iterations + sum|dphi| history
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rsf_oracle.c")
+_LIBS = {"f64": os.path.join(_HERE, "liboracle_f64.so"),
+         "f32": os.path.join(_HERE, "liboracle_f32.so")}
+_loaded: dict = {}
+
+# Regulariser readings of Sec. 2.1 (see rsf_oracle.c).
+SINGLE_WELL = 0
+DOUBLE_WELL = 1
+
+PROBE_FIELDS = ("H", "f1", "f2", "e1", "e2", "kappa", "lap", "R", "E", "delta")
+
+
+def build(force: bool = True) -> None:
+    """Compile both oracle variants with gcc (plain -O2, OpenMP)."""
+    for real, out in _LIBS.items():
+        if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+            continue
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-o", out + ".tmp", _SRC, "-lm"]
+        if real == "f32":
+            cmd.insert(1, "-DREAL=float")
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+def _lib(real: str = "f64"):
+    if real in _loaded:
+        return _loaded[real]
+    path = _LIBS[real]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=False)
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_longlong
+    lib.oracle_radius.argtypes = [ctypes.c_double]
+    lib.oracle_radius.restype = ctypes.c_int
+    lib.oracle_weights.argtypes = [ctypes.c_double, dp]
+    lib.oracle_weights.restype = None
+    lib.oracle_conv3d.argtypes = [dp, dp, i64, i64, i64, ctypes.c_double]
+    lib.oracle_conv3d.restype = ctypes.c_int
+    lib.oracle_step.argtypes = [dp, dp, dp, i64, i64, i64, dp, ctypes.c_int,
+                                ctypes.POINTER(dp), dp]
+    lib.oracle_step.restype = ctypes.c_int
+    lib.oracle_evolve.argtypes = [dp, dp, i64, i64, i64, dp, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_evolve.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_get_threads.restype = ctypes.c_int
+    lib.oracle_real_type.restype = ctypes.c_char_p
+    _loaded[real] = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    for real in _LIBS:
+        _lib(real).oracle_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_lib().oracle_get_threads())
+
+
+def radius(sigma: float) -> int:
+    return int(_lib().oracle_radius(float(sigma)))
+
+
+def weights(sigma: float) -> np.ndarray:
+    w = np.zeros(2 * radius(sigma) + 1, dtype=np.float64)
+    _lib().oracle_weights(float(sigma), _dptr(w))
+    return w
+
+
+def conv3d(u, sigma: float, real: str = "f64") -> np.ndarray:
+    u = _f64(u)
+    nz, ny, nx = u.shape
+    out = np.empty_like(u)
+    rc = _lib(real).oracle_conv3d(_dptr(u), _dptr(out), nx, ny, nz, float(sigma))
+    if rc != 0:
+        raise ValueError(f"oracle_conv3d failed ({rc})")
+    return out
+
+
+def params_array(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10) -> np.ndarray:
+    return np.array([sigma, lambda1, lambda2, nu, mu, dt, eps, eta], dtype=np.float64)
+
+
+def step(I, phi, params, reg: int = DOUBLE_WELL, real: str = "f64"):
+    """One iteration.  Returns (phi_next, fields dict, sum|dphi|)."""
+    I = _f64(I)
+    phi = _f64(phi)
+    if I.shape != phi.shape or I.ndim != 3:
+        raise ValueError("I and phi must be equal 3D shapes [nz][ny][nx]")
+    nz, ny, nx = phi.shape
+    out = np.empty_like(phi)
+    fields = {k: np.empty_like(phi) for k in PROBE_FIELDS}
+    probe = (ctypes.POINTER(ctypes.c_double) * len(PROBE_FIELDS))(
+        *[_dptr(fields[k]) for k in PROBE_FIELDS])
+    total = ctypes.c_double(0.0)
+    p = _f64(params)
+    rc = _lib(real).oracle_step(_dptr(I), _dptr(phi), _dptr(out), nx, ny, nz, _dptr(p),
+                                int(reg), probe, ctypes.byref(total))
+    if rc != 0:
+        raise ValueError(f"oracle_step failed ({rc})")
+    return out, fields, float(total.value)
+
+
+def evolve(I, phi0, params, iters: int, reg: int = DOUBLE_WELL, real: str = "f64"):
+    """``iters`` iterations of Eq. (1).  Returns (phi_iters, s_hist)."""
+    I = _f64(I)
+    phi = _f64(phi0).copy()
+    if I.shape != phi.shape or I.ndim != 3:
+        raise ValueError("I and phi must be equal 3D shapes [nz][ny][nx]")
+    nz, ny, nx = phi.shape
+    hist = np.zeros(max(int(iters), 1), dtype=np.float64)
+    p = _f64(params)
+    rc = _lib(real).oracle_evolve(_dptr(I), _dptr(phi), nx, ny, nz, _dptr(p), int(reg),
+                                  int(iters), _dptr(hist))
+    if rc != 0:
+        raise ValueError(f"oracle_evolve failed ({rc})")
+    return phi, hist[: int(iters)]

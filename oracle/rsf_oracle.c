@@ -1,0 +1,410 @@
+/*
+ * rsf_oracle.c -- plain, slow CPU oracle of the 3D RSF level-set iteration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or constant with the
+ * HIP library under paper_2404_02813_amd/csrc.
+ *
+ * What it computes (Niger et al., "GPU-Accelerated RSF Level Set Evolution
+ * for Large-Scale Microvascular Segmentation", arXiv 2404.02813):
+ *
+ *   phi_{n+1} = phi_n + dt * E(phi_n, I)                       Eq. (1), Sec. 2
+ *   E = mu * R(phi) + delta(phi) * (nu * kappa - F_d)          Sec. 3, final energy
+ *
+ * written step by step in the paper's order, every term evaluated from
+ * phi_n into a new buffer (explicit Euler).  Readings taken where the paper
+ * is garbled or silent (each listed in the design notes of the repository):
+ *
+ *   - K is the Gaussian of Sec. 3 sampled on the integer grid, truncated to
+ *     the cube |k| <= R = ceil(3 sigma) per axis and normalised so that its
+ *     weights sum to one; it is separable, applied along x, then y, then z,
+ *     with zero padding outside the volume.
+ *   - H_eps and delta_eps are the arctan Heaviside of Sec. 3 and its
+ *     derivative.
+ *   - Region fits r+ = f1 (weights H) and r- = f2 (weights 1 - H) are the
+ *     local intensity ratio of Sec. 3, eq. "local_intensity"; all four
+ *     Gaussian convolutions are computed literally.
+ *   - The data force is the region-scalable fitting energy of the RSF model
+ *     the paper builds on (Li et al. 2008):
+ *       e_i(x) = sum_y K(y - x) |I(x) - f_i(y)|^2
+ *              = I^2 (K*1) - 2 I (K*f_i) + K*(f_i^2),
+ *     again with all four convolutions done literally, and
+ *     F_d = lambda1 e1 - lambda2 e2 (the force of Sec. 3, F = -[F+ - F-],
+ *     with beta carried by lambda1 = lambda2).
+ *   - kappa = div(grad phi / |grad phi|_eta), |g|_eta = sqrt(|g|^2 + eta):
+ *     the smoothing term S of Sec. 2.2 read as mean curvature.
+ *   - R(phi) = lap(phi) + div(D(|grad phi|) grad phi), the distance
+ *     regulariser of Sec. 2.1, in one of two readings:
+ *       single well (RSF 2008): D = -1/|g|_eta, so R = lap(phi) - kappa;
+ *       double well (DRLSE "forward-and-backward" diffusion):
+ *         D(s) = sin(2 pi s)/(2 pi s) - 1 for s <= 1, -1/s for s > 1,
+ *         D(0) = 0.
+ *   - Differences: central first differences, 7-point Laplacian, the
+ *     divergence as central differences of the vector field at the six
+ *     axis neighbours; ghost values by reflection about the boundary voxel
+ *     (phi[-k] = phi[k], phi[n-1+k] = phi[n-1-k]).
+ *
+ * Arrays are [nz][ny][nx], x fastest, passed as double; the working type is
+ * REAL (double by default; the build also makes a float variant used only to
+ * measure how far rounding alone moves the result).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef REAL
+#define REAL double
+#endif
+
+#define ORACLE_PI 3.14159265358979323846
+
+typedef long long i64;
+
+const char *oracle_real_type(void) { return sizeof(REAL) == 8 ? "f64" : "f32"; }
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int oracle_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Truncation radius of the sampled Gaussian: the kernel reaches 3 sigma. */
+int oracle_radius(double sigma) { return (int)ceil(3.0 * sigma - 1e-9); }
+
+/* Sampled, truncated, unit-sum Gaussian weights w[k + R], k = -R..R
+ * (Sec. 3, Gaussian kernel K; normalised on the grid). */
+void oracle_weights(double sigma, double *w)
+{
+    int R = oracle_radius(sigma);
+    double s = 0.0;
+    for (int k = -R; k <= R; ++k) {
+        w[k + R] = exp(-(double)k * k / (2.0 * sigma * sigma));
+        s += w[k + R];
+    }
+    for (int k = -R; k <= R; ++k) w[k + R] /= s;
+}
+
+/* One zero-padded 1D convolution along `axis` (0 = x, 1 = y, 2 = z). */
+static void conv_axis(const REAL *in, REAL *out, i64 nx, i64 ny, i64 nz,
+                      const REAL *w, int R, int axis)
+{
+    i64 n = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    i64 stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+#pragma omp parallel for schedule(static)
+    for (i64 z = 0; z < nz; ++z)
+        for (i64 y = 0; y < ny; ++y)
+            for (i64 x = 0; x < nx; ++x) {
+                i64 i = (z * ny + y) * nx + x;
+                i64 p = axis == 0 ? x : (axis == 1 ? y : z);
+                REAL acc = 0;
+                for (int k = -R; k <= R; ++k) {
+                    i64 j = p + k;
+                    if (j >= 0 && j < n) acc += w[k + R] * in[i + (i64)k * stride];
+                }
+                out[i] = acc;
+            }
+}
+
+/* K * u: x pass, then y, then z.  tmp holds one field. */
+static void conv3d(const REAL *u, REAL *out, REAL *tmp, i64 nx, i64 ny, i64 nz,
+                   const REAL *w, int R)
+{
+    conv_axis(u, out, nx, ny, nz, w, R, 0);
+    conv_axis(out, tmp, nx, ny, nz, w, R, 1);
+    conv_axis(tmp, out, nx, ny, nz, w, R, 2);
+}
+
+static REAL *alloc_field(i64 n) { return (REAL *)malloc(sizeof(REAL) * (size_t)n); }
+
+#define ORACLE_MAX_R 4096
+
+/* Weights in the working type; caller frees. */
+static REAL *make_weights(double sigma, int *R)
+{
+    *R = oracle_radius(sigma);
+    if (*R < 0 || *R > ORACLE_MAX_R) return NULL;
+    double *wd = (double *)malloc(sizeof(double) * (size_t)(2 * *R + 1));
+    REAL *wr = (REAL *)malloc(sizeof(REAL) * (size_t)(2 * *R + 1));
+    if (!wd || !wr) { free(wd); free(wr); return NULL; }
+    oracle_weights(sigma, wd);
+    for (int k = 0; k < 2 * *R + 1; ++k) wr[k] = (REAL)wd[k];
+    free(wd);
+    return wr;
+}
+
+/* Public: one Gaussian convolution of a double field. */
+int oracle_conv3d(const double *in, double *out, i64 nx, i64 ny, i64 nz, double sigma)
+{
+    i64 N = nx * ny * nz;
+    int R;
+    REAL *w = make_weights(sigma, &R);
+    if (!w) return -1;
+    REAL *u = alloc_field(N), *o = alloc_field(N), *t = alloc_field(N);
+    if (!u || !o || !t) { free(u); free(o); free(t); free(w); return -2; }
+    for (i64 i = 0; i < N; ++i) u[i] = (REAL)in[i];
+    conv3d(u, o, t, nx, ny, nz, w, R);
+    for (i64 i = 0; i < N; ++i) out[i] = (double)o[i];
+    free(u); free(o); free(t); free(w);
+    return 0;
+}
+
+/* Heaviside and Dirac of Sec. 3. */
+static REAL heaviside(REAL u, REAL eps)
+{
+    return (REAL)0.5 * ((REAL)1 + ((REAL)2 / (REAL)ORACLE_PI) * atan(u / eps));
+}
+
+static REAL dirac(REAL u, REAL eps)
+{
+    return ((REAL)1 / (REAL)ORACLE_PI) * eps / (eps * eps + u * u);
+}
+
+/* Reflect a coordinate about the boundary voxel. */
+static i64 reflect(i64 i, i64 n)
+{
+    if (i < 0) return -i;
+    if (i > n - 1) return 2 * (n - 1) - i;
+    return i;
+}
+
+static REAL phi_at(const REAL *phi, i64 x, i64 y, i64 z, i64 nx, i64 ny, i64 nz)
+{
+    x = reflect(x, nx); y = reflect(y, ny); z = reflect(z, nz);
+    return phi[(z * ny + y) * nx + x];
+}
+
+/* Central-difference gradient of phi at a (possibly ghost) point. */
+static void grad_at(const REAL *phi, i64 x, i64 y, i64 z, i64 nx, i64 ny, i64 nz, REAL g[3])
+{
+    g[0] = (phi_at(phi, x + 1, y, z, nx, ny, nz) - phi_at(phi, x - 1, y, z, nx, ny, nz)) / 2;
+    g[1] = (phi_at(phi, x, y + 1, z, nx, ny, nz) - phi_at(phi, x, y - 1, z, nx, ny, nz)) / 2;
+    g[2] = (phi_at(phi, x, y, z + 1, nx, ny, nz) - phi_at(phi, x, y, z - 1, nx, ny, nz)) / 2;
+}
+
+/* Diffusion-rate excess D(s) = d_p(s) - 1 of the distance regulariser. */
+static REAL reg_rate(REAL s, REAL s_eta, int reg)
+{
+    if (reg == 0) return -(REAL)1 / s_eta;                 /* single well */
+    if (s == 0) return 0;                                   /* d_p(0) = 1  */
+    if (s <= 1) {
+        REAL a = (REAL)2 * (REAL)ORACLE_PI * s;
+        return sin(a) / a - (REAL)1;
+    }
+    return -(REAL)1 / s;
+}
+
+typedef struct {
+    double sigma, lambda1, lambda2, nu, mu, dt, eps, eta;
+} oracle_params;
+
+static void read_params(const double *p, oracle_params *q)
+{
+    q->sigma = p[0]; q->lambda1 = p[1]; q->lambda2 = p[2]; q->nu = p[3];
+    q->mu = p[4]; q->dt = p[5]; q->eps = p[6]; q->eta = p[7];
+}
+
+/* Scratch for one iteration. */
+typedef struct {
+    REAL *H, *u, *A1, *B1, *A2, *B2, *f1, *f2, *c1, *c2, *e1, *e2, *tmp;
+} work_t;
+
+static int work_alloc(work_t *s, i64 N)
+{
+    REAL **f[] = {&s->H, &s->u, &s->A1, &s->B1, &s->A2, &s->B2, &s->f1, &s->f2,
+                  &s->c1, &s->c2, &s->e1, &s->e2, &s->tmp};
+    int ok = 1;
+    for (size_t i = 0; i < sizeof(f) / sizeof(f[0]); ++i) {
+        *f[i] = alloc_field(N);
+        if (!*f[i]) ok = 0;
+    }
+    return ok;
+}
+
+static void work_free(work_t *s)
+{
+    free(s->H); free(s->u); free(s->A1); free(s->B1); free(s->A2); free(s->B2);
+    free(s->f1); free(s->f2); free(s->c1); free(s->c2); free(s->e1); free(s->e2);
+    free(s->tmp);
+}
+
+/* One RSF iteration: phi -> phi_next.  K1 = K*1.  Optional probe fields
+ * (double, may be NULL) receive this step's intermediate values.
+ * Returns sum |phi_next - phi| in double. */
+static double rsf_step(const REAL *I, const REAL *phi, REAL *phi_next, const REAL *K1,
+                       i64 nx, i64 ny, i64 nz, const oracle_params *p, int reg,
+                       const REAL *w, int R, work_t *s, double **probe)
+{
+    const i64 N = nx * ny * nz;
+    const REAL eps = (REAL)p->eps, l1 = (REAL)p->lambda1, l2 = (REAL)p->lambda2;
+    const REAL eta = (REAL)p->eta;
+
+    /* Region fits (Sec. 3, eq. local_intensity): four literal convolutions. */
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->H[i] = heaviside(phi[i], eps);
+
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->u[i] = s->H[i] * I[i];
+    conv3d(s->u, s->A1, s->tmp, nx, ny, nz, w, R);                 /* K*(H I)     */
+    conv3d(s->H, s->B1, s->tmp, nx, ny, nz, w, R);                 /* K*H         */
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->u[i] = ((REAL)1 - s->H[i]) * I[i];
+    conv3d(s->u, s->A2, s->tmp, nx, ny, nz, w, R);                 /* K*((1-H)I)  */
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->u[i] = (REAL)1 - s->H[i];
+    conv3d(s->u, s->B2, s->tmp, nx, ny, nz, w, R);                 /* K*(1-H)     */
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) {
+        s->f1[i] = s->A1[i] / s->B1[i];
+        s->f2[i] = s->A2[i] / s->B2[i];
+    }
+
+    /* Fitting energies e_i = I^2 K1 - 2 I K*f_i + K*f_i^2: four literal
+     * convolutions. */
+    conv3d(s->f1, s->c1, s->tmp, nx, ny, nz, w, R);
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->u[i] = s->f1[i] * s->f1[i];
+    conv3d(s->u, s->c2, s->tmp, nx, ny, nz, w, R);
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i)
+        s->e1[i] = I[i] * I[i] * K1[i] - (REAL)2 * I[i] * s->c1[i] + s->c2[i];
+    conv3d(s->f2, s->c1, s->tmp, nx, ny, nz, w, R);
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i) s->u[i] = s->f2[i] * s->f2[i];
+    conv3d(s->u, s->c2, s->tmp, nx, ny, nz, w, R);
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < N; ++i)
+        s->e2[i] = I[i] * I[i] * K1[i] - (REAL)2 * I[i] * s->c1[i] + s->c2[i];
+
+    /* Curvature, regulariser, Dirac-weighted update (Sec. 2, Sec. 3). */
+    double *slice_sum = (double *)calloc((size_t)nz, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (i64 z = 0; z < nz; ++z)
+        for (i64 y = 0; y < ny; ++y)
+            for (i64 x = 0; x < nx; ++x) {
+                const i64 i = (z * ny + y) * nx + x;
+                const REAL c = phi[i];
+                REAL kappa = 0, divV = 0, lap = 0;
+                for (int a = 0; a < 3; ++a) {
+                    i64 dx = a == 0, dy = a == 1, dz = a == 2;
+                    REAL gp[3], gm[3];
+                    grad_at(phi, x + dx, y + dy, z + dz, nx, ny, nz, gp);
+                    grad_at(phi, x - dx, y - dy, z - dz, nx, ny, nz, gm);
+                    REAL sp = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2]);
+                    REAL sm = sqrt(gm[0] * gm[0] + gm[1] * gm[1] + gm[2] * gm[2]);
+                    REAL sp_eta = sqrt(gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2] + eta);
+                    REAL sm_eta = sqrt(gm[0] * gm[0] + gm[1] * gm[1] + gm[2] * gm[2] + eta);
+                    kappa += (gp[a] / sp_eta - gm[a] / sm_eta) / 2;
+                    divV += (reg_rate(sp, sp_eta, reg) * gp[a] - reg_rate(sm, sm_eta, reg) * gm[a]) / 2;
+                    lap += phi_at(phi, x + dx, y + dy, z + dz, nx, ny, nz)
+                         + phi_at(phi, x - dx, y - dy, z - dz, nx, ny, nz) - 2 * c;
+                }
+                const REAL regt = lap + divV;
+                const REAL Fd = l1 * s->e1[i] - l2 * s->e2[i];
+                const REAL E = (REAL)p->mu * regt + dirac(c, eps) * ((REAL)p->nu * kappa - Fd);
+                const REAL nxt = c + (REAL)p->dt * E;
+                phi_next[i] = nxt;
+                slice_sum[z] += fabs((double)nxt - (double)c);
+                if (probe) {
+                    if (probe[0]) probe[0][i] = (double)s->H[i];
+                    if (probe[1]) probe[1][i] = (double)s->f1[i];
+                    if (probe[2]) probe[2][i] = (double)s->f2[i];
+                    if (probe[3]) probe[3][i] = (double)s->e1[i];
+                    if (probe[4]) probe[4][i] = (double)s->e2[i];
+                    if (probe[5]) probe[5][i] = (double)kappa;
+                    if (probe[6]) probe[6][i] = (double)lap;
+                    if (probe[7]) probe[7][i] = (double)regt;
+                    if (probe[8]) probe[8][i] = (double)E;
+                    if (probe[9]) probe[9][i] = (double)dirac(c, eps);
+                }
+            }
+    double total = 0.0;               /* fixed order: slice by slice */
+    for (i64 z = 0; z < nz; ++z) total += slice_sum[z];
+    free(slice_sum);
+    return total;
+}
+
+/* K1 = K * 1, the convolution of a field of ones (zero padding makes it fall
+ * below one within R of a face). */
+static void ones_conv(REAL *K1, REAL *tmp, i64 nx, i64 ny, i64 nz, const REAL *w, int R)
+{
+    const i64 N = nx * ny * nz;
+    REAL *one = alloc_field(N);
+    for (i64 i = 0; i < N; ++i) one[i] = 1;
+    conv3d(one, K1, tmp, nx, ny, nz, w, R);
+    free(one);
+}
+
+/* params = {sigma, lambda1, lambda2, nu, mu, dt, eps, eta}; reg 0 = single
+ * well, 1 = double well.  probe[10] = {H, f1, f2, e1, e2, kappa, lap, R, E, delta},
+ * any entry may be NULL.  One iteration from phi into phi_next. */
+int oracle_step(const double *I_in, const double *phi_in, double *phi_out,
+                i64 nx, i64 ny, i64 nz, const double *params, int reg,
+                double **probe, double *sum_abs)
+{
+    oracle_params p;
+    read_params(params, &p);
+    if (nx < 3 || ny < 3 || nz < 3) return -1;
+    const i64 N = nx * ny * nz;
+    int R;
+    REAL *w = make_weights(p.sigma, &R);
+    if (!w) return -1;
+    work_t s;
+    REAL *I = alloc_field(N), *phi = alloc_field(N), *nxt = alloc_field(N), *K1 = alloc_field(N);
+    if (!work_alloc(&s, N) || !I || !phi || !nxt || !K1) {
+        work_free(&s); free(I); free(phi); free(nxt); free(K1); free(w);
+        return -2;
+    }
+    for (i64 i = 0; i < N; ++i) { I[i] = (REAL)I_in[i]; phi[i] = (REAL)phi_in[i]; }
+    ones_conv(K1, s.tmp, nx, ny, nz, w, R);
+    double t = rsf_step(I, phi, nxt, K1, nx, ny, nz, &p, reg, w, R, &s, probe);
+    for (i64 i = 0; i < N; ++i) phi_out[i] = (double)nxt[i];
+    if (sum_abs) *sum_abs = t;
+    work_free(&s); free(I); free(phi); free(nxt); free(K1); free(w);
+    return 0;
+}
+
+/* `iters` iterations of Eq. (1) starting from phi (updated in place).
+ * s_hist (may be NULL) receives sum |phi_{n+1} - phi_n| per iteration. */
+int oracle_evolve(const double *I_in, double *phi_io, i64 nx, i64 ny, i64 nz,
+                  const double *params, int reg, int iters, double *s_hist)
+{
+    oracle_params p;
+    read_params(params, &p);
+    if (nx < 3 || ny < 3 || nz < 3 || iters < 0) return -1;
+    const i64 N = nx * ny * nz;
+    int R;
+    REAL *w = make_weights(p.sigma, &R);
+    if (!w) return -1;
+    work_t s;
+    REAL *I = alloc_field(N), *a = alloc_field(N), *b = alloc_field(N), *K1 = alloc_field(N);
+    if (!work_alloc(&s, N) || !I || !a || !b || !K1) {
+        work_free(&s); free(I); free(a); free(b); free(K1); free(w);
+        return -2;
+    }
+    for (i64 i = 0; i < N; ++i) { I[i] = (REAL)I_in[i]; a[i] = (REAL)phi_io[i]; }
+    ones_conv(K1, s.tmp, nx, ny, nz, w, R);
+    for (int n = 0; n < iters; ++n) {
+        double t = rsf_step(I, a, b, K1, nx, ny, nz, &p, reg, w, R, &s, NULL);
+        if (s_hist) s_hist[n] = t;
+        REAL *q = a; a = b; b = q;
+    }
+    for (i64 i = 0; i < N; ++i) phi_io[i] = (double)a[i];
+    work_free(&s); free(I); free(a); free(b); free(K1); free(w);
+    return 0;
+}

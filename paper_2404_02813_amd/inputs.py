@@ -1,0 +1,133 @@
+"""Seeded synthetic inputs for the RSF level-set path.
+
+This module is shared by the HIP path's tests/benchmark and by the CPU
+oracle's tests; it holds none of the level-set arithmetic.  It draws
+microvessel-like phantoms: straight or curved tubes (quadratic Bezier
+centrelines, radius 1-4 voxels) rendered into a binary mask, mapped to
+intensities 0.1 (background) / 0.8 (vessel), blurred by a Gaussian of sd 1
+(scipy's filter, reflect boundary, truncated at 3 sd) and given additive
+Gaussian noise.  The paper's microscopy volumes (KESM, light-sheet, micro-CT)
+are not available; these phantoms stand in for them with vessel radii of the
+size the paper targets (3-10 um vessels at ~1 um voxels).
+
+phi0 follows the box rule: +2 inside the centred box whose sides are half the
+volume's extents, -2 elsewhere.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def rng_for(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def tube_mask(shape, n_tubes: int, r_min: float, r_max: float,
+              rng: np.random.Generator) -> np.ndarray:
+    """Binary mask [nz][ny][nx] of `n_tubes` random tubes."""
+    nz, ny, nx = shape
+    dims = np.array([nx, ny, nz], dtype=np.float64)
+    mask = np.zeros(shape, dtype=bool)
+    for _ in range(int(n_tubes)):
+        p0 = rng.uniform(0.0, 1.0, 3) * dims
+        p2 = rng.uniform(0.0, 1.0, 3) * dims
+        mid = 0.5 * (p0 + p2)
+        if rng.random() < 0.5:
+            p1 = mid
+        else:
+            p1 = mid + rng.normal(0.0, max(np.linalg.norm(p2 - p0) / 4.0, 1e-6), 3)
+        r = float(rng.uniform(r_min, r_max))
+        # B'(t) is linear in t, so its largest norm is at an end point.
+        speed = max(2.0 * np.linalg.norm(p1 - p0), 2.0 * np.linalg.norm(p2 - p1), 1e-6)
+        m = int(math.ceil(speed / 0.5)) + 1
+        rc = int(math.ceil(r))
+        o = np.arange(-rc, rc + 2)
+        off = np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3)
+        for s0 in range(0, m, 2048):
+            t = np.arange(s0, min(m, s0 + 2048), dtype=np.float64) / max(m - 1, 1)
+            t = t[:, None]
+            c = (1 - t) ** 2 * p0 + 2 * (1 - t) * t * p1 + t ** 2 * p2      # (k, 3) xyz
+            v = np.floor(c).astype(np.int64)[:, None, :] + off[None, :, :]   # (k, K, 3)
+            d2 = ((v - c[:, None, :]) ** 2).sum(-1)
+            keep = d2 <= r * r
+            v = v[keep]
+            ok = ((v >= 0) & (v < np.array([nx, ny, nz]))).all(-1)
+            v = v[ok]
+            mask[v[:, 2], v[:, 1], v[:, 0]] = True
+    return mask
+
+
+def vessel_phantom(shape, n_tubes: int, r_min: float, r_max: float, seed: int,
+                   lo: float = 0.1, hi: float = 0.8, blur_sd: float = 1.0,
+                   noise_sd: float = 0.05) -> np.ndarray:
+    """Float32 phantom [nz][ny][nx]: tubes at `hi`, background `lo`, blurred,
+    plus N(0, noise_sd^2) noise (no clipping)."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = rng_for(seed)
+    m = tube_mask(shape, n_tubes, r_min, r_max, rng)
+    clean = np.where(m, np.float32(hi), np.float32(lo)).astype(np.float32)
+    del m
+    img = gaussian_filter(clean, sigma=blur_sd, truncate=3.0, mode="reflect")
+    del clean
+    img += rng.normal(0.0, noise_sd, size=shape).astype(np.float32)
+    return np.ascontiguousarray(img, dtype=np.float32)
+
+
+def box_phi0(shape, inside: float = 2.0, outside: float = -2.0) -> np.ndarray:
+    """+inside on [n/4, 3n/4) along every axis, `outside` elsewhere."""
+    phi = np.full(shape, outside, dtype=np.float32)
+    sl = tuple(slice(n // 4, n // 4 + n // 2) for n in shape)
+    phi[sl] = inside
+    return phi
+
+
+@dataclass(frozen=True)
+class Workload:
+    """A plain-volume workload: phantom recipe, box phi0 and RSF parameters."""
+    name: str
+    shape: tuple            # (nz, ny, nx)
+    n_tubes: int
+    r_min: float
+    r_max: float
+    seed: int
+    iters: int
+    sigma: float = 3.0
+    lambda1: float = 1.0
+    lambda2: float = 1.0
+    nu: float = 0.001
+    mu: float = 1.0
+    dt: float = 0.1
+    eps: float = 1.0
+
+    def image(self) -> np.ndarray:
+        return vessel_phantom(self.shape, self.n_tubes, self.r_min, self.r_max, self.seed)
+
+    def phi0(self) -> np.ndarray:
+        return box_phi0(self.shape)
+
+    @property
+    def voxels(self) -> int:
+        return int(np.prod(self.shape))
+
+    def params(self) -> dict:
+        return dict(sigma=self.sigma, lambda1=self.lambda1, lambda2=self.lambda2,
+                    nu=self.nu, mu=self.mu, dt=self.dt, eps=self.eps)
+
+
+# 64^3, 12 tubes r 1-3, 20 iterations (small parity case).
+SMALL_64 = Workload("vessel64_s3_it20", (64, 64, 64), 12, 1.0, 3.0, seed=1, iters=20)
+# 512^3, 400 tubes r 1-4, 200 iterations (throughput case).
+LARGE_512 = Workload("vessel512_s3_it200", (512, 512, 512), 400, 1.0, 4.0, seed=2, iters=200)
+
+
+def scaled(w: Workload, n: int, iters: int | None = None, name: str | None = None) -> Workload:
+    """Same recipe on an n^3 volume, tube count scaled by volume."""
+    frac = (n ** 3) / float(np.prod(w.shape))
+    tubes = max(4, int(round(w.n_tubes * frac ** (1.0 / 3.0) * frac ** (1.0 / 3.0))))
+    return Workload(name or f"{w.name}_n{n}", (n, n, n), tubes, w.r_min, w.r_max,
+                    w.seed + 1000 + n, iters if iters is not None else w.iters,
+                    w.sigma, w.lambda1, w.lambda2, w.nu, w.mu, w.dt, w.eps)
