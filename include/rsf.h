@@ -1,0 +1,161 @@
+/*
+ * rsf.h -- C ABI of the MI355X (gfx950) RSF level-set evolution library.
+ *
+ * The library evolves a level-set function phi over a 3D image I by the
+ * region-scalable fitting (RSF) model in the form of Niger et al., arXiv
+ * 2404.02813: explicit time steps phi <- phi + dt * E (Sec. 2, Eq. 1) with
+ *
+ *   E = mu * R(phi) + delta_eps(phi) * (nu * kappa - (lambda1 e1 - lambda2 e2))
+ *
+ * (Sec. 3, final energy), where
+ *   H_eps(u) = 1/2 (1 + (2/pi) atan(u/eps)),  delta_eps = H_eps'      (Sec. 3)
+ *   f1 = K*(H I) / K*H,  f2 = K*((1-H) I) / K*(1-H)    (Sec. 3, local_intensity)
+ *   e_i = I^2 (K*1) - 2 I (K*f_i) + K*(f_i^2)          (fitting energies of the
+ *                                                        RSF model, Sec. 3 force)
+ *   kappa = div(grad phi / sqrt(|grad phi|^2 + eta))   (Sec. 2.2 smoothing)
+ *   R = lap(phi) + div(D(|grad phi|) grad phi)         (Sec. 2.1 regulariser)
+ * K is the Gaussian of Sec. 3 sampled on the grid, truncated at R = ceil(3
+ * sigma) voxels per axis and normalised to unit sum; convolutions use zero
+ * padding.  Differences are central, the Laplacian 7-point, ghost values by
+ * reflection about the boundary voxel.  Sign convention: H weights phi > 0,
+ * so f1 is the fit of the phi > 0 region.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are dense [nz][ny][nx] with x fastest.  Pointers named "device"
+ *     are HIP device pointers on the context's device; the library never
+ *     frees or retains them beyond the call's stream work.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously; device faults surface at the next synchronising call.
+ *   - Every entry validates its arguments before enqueuing anything and leaves
+ *     its outputs untouched on a validation error.  No C++ exception crosses
+ *     the ABI.  rsf_last_error() describes the last failure on a context.
+ *   - A context is not thread-safe: use one per host thread.
+ */
+#ifndef RSF_H
+#define RSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsf_context rsf_context;
+
+typedef enum {
+    RSF_OK = 0,
+    RSF_ERR_INVALID_ARG = -1,
+    RSF_ERR_OUT_OF_MEMORY = -2,
+    RSF_ERR_DEVICE = -3,
+    RSF_ERR_NONFINITE = -4,
+    RSF_ERR_BUDGET = -5,
+    RSF_ERR_INTERNAL = -6
+} rsf_status;
+
+/* Element type of the input image. */
+typedef enum {
+    RSF_F32 = 0
+} rsf_dtype;
+
+/* Distance-regulariser reading (Sec. 2.1).  The paper names "forward and
+ * backward (FAB) diffusion" and prints a garbled single-well formula:
+ *   RSF_REG_DOUBLE_WELL (default): D(s) = sin(2 pi s)/(2 pi s) - 1 for
+ *       s <= 1, -1/s for s > 1 (the double-well potential of distance-
+ *       regularised level sets, whose diffusion is forward-and-backward);
+ *   RSF_REG_SINGLE_WELL: D = -1/sqrt(s^2 + eta), i.e. R = lap(phi) - kappa.
+ *       Backward diffusion where |grad phi| < 1 makes this reading amplify
+ *       rounding; it is provided for comparison. */
+typedef enum {
+    RSF_REG_DOUBLE_WELL = 0,
+    RSF_REG_SINGLE_WELL = 1
+} rsf_regulariser;
+
+/* Parameters of one evolution (Sec. 2-3 notation: alpha = nu, beta carried
+ * by lambda1 = lambda2, mu weighs the regulariser). */
+typedef struct {
+    float sigma;      /* Gaussian scale, voxels; R = ceil(3 sigma) <= 16     */
+    float lambda1;    /* weight of e1 (phi > 0 region)                        */
+    float lambda2;    /* weight of e2 (phi < 0 region)                        */
+    float nu;         /* curvature (smoothing) weight, >= 0                   */
+    float mu;         /* regulariser weight, >= 0                             */
+    float dt;         /* time step, > 0                                       */
+    float eps;        /* Heaviside / Dirac width, > 0                         */
+    float eta;        /* floor inside |grad phi| of the normal; <= 0 -> 1e-10 */
+    int regulariser;  /* rsf_regulariser                                      */
+} rsf_params;
+
+/* Results of the last evolution on a context. */
+typedef struct {
+    int iters_requested;
+    int iters_run;        /* < iters_requested only when tol stopped it early */
+    double last_sum_abs;  /* sum |phi_{n+1} - phi_n| of the last iteration run */
+} rsf_stats;
+
+/* Create a context bound to HIP device `device_ordinal`.  *out is NULL on
+ * failure. */
+rsf_status rsf_create(rsf_context **out, int device_ordinal);
+
+/* Destroy a context and the device memory it owns.  NULL is a no-op. */
+void rsf_destroy(rsf_context *ctx);
+
+/* Text of the last error on `ctx` ("" if none; a static message if ctx is
+ * NULL).  Valid until the next call on the context. */
+const char *rsf_last_error(const rsf_context *ctx);
+
+/* Bytes of device workspace an evolution of an nx*ny*nz volume over `iters`
+ * iterations needs (six float fields plus small tables). */
+size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters);
+
+/* Evolve phi in place for `iters` iterations of Eq. (1) with the default
+ * (double-well) regulariser and eta = 1e-10.
+ *   volume : device, const, nx*ny*nz elements of `volume_dtype` (the image I)
+ *   phi    : device, nx*ny*nz floats; phi_0 on entry, phi_iters on return
+ *   nx,ny,nz >= 3; sigma > 0 with ceil(3 sigma) <= 16; eps > 0; dt > 0;
+ *   nu, mu >= 0; lambda1, lambda2 finite; iters >= 0 (0 is a no-op).
+ * The workspace is allocated by the context (grown on demand, kept). */
+rsf_status rsf_evolve(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                      int64_t nx, int64_t ny, int64_t nz,
+                      float sigma, float lambda1, float lambda2, float nu, float mu,
+                      float dt, float eps, int iters, void *stream);
+
+/* As rsf_evolve with explicit parameters and options.
+ *   params    : host, read during the call only.
+ *   tol       : > 0 stops early (on the device) once sum|dphi| / voxels < tol;
+ *               the remaining iterations leave phi unchanged.  0 = fixed count.
+ *   workspace : device buffer of >= rsf_workspace_bytes(...) bytes owned by the
+ *               caller, or NULL to use the context's own allocation.
+ * The per-iteration sums are kept on the device; rsf_get_stats() reads them. */
+rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                         int64_t nx, int64_t ny, int64_t nz, const rsf_params *params,
+                         int iters, double tol, void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Synchronise the stream of the last evolution and report its statistics.
+ * s_hist (host, may be NULL) receives up to `cap` per-iteration sums
+ * sum|phi_{n+1} - phi_n| in double (the convergence reduction). */
+rsf_status rsf_get_stats(rsf_context *ctx, rsf_stats *out, double *s_hist, int cap);
+
+/* One zero-padded Gaussian convolution out = K * in (Sec. 3 kernel), the
+ * separable passes the evolution uses.  in, out: device floats, distinct. */
+rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out,
+                       int64_t nx, int64_t ny, int64_t nz, float sigma, void *stream);
+
+/* Intermediate fields of ONE iteration from (volume, phi), for parity checks.
+ * Each non-NULL pointer is a device buffer of nx*ny*nz floats that receives:
+ *   H = H_eps(phi), f1, f2 (region fits), Fd = lambda1 e1 - lambda2 e2,
+ *   kappa, lap (7-point Laplacian), R (regulariser), E (the update rate)
+ * and phi_next = phi + dt E.  phi is not modified. */
+typedef struct {
+    float *H, *f1, *f2, *Fd, *kappa, *lap, *R, *E, *phi_next;
+} rsf_probe_fields;
+
+rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, const float *phi,
+                     int64_t nx, int64_t ny, int64_t nz, const rsf_params *params,
+                     const rsf_probe_fields *fields, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSF_H */

@@ -1,0 +1,77 @@
+// Internal declarations shared by the kernels (rsf_kernels.hip) and the
+// C-ABI host code (rsf_api.hip).  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rsf {
+
+constexpr int kMaxR = 16;          // largest Gaussian radius (sigma <= 16/3)
+constexpr int kXyTx = 64;          // xy pass: outputs per tile along x
+constexpr int kXyTy = 32;          // xy pass: outputs per tile along y
+constexpr int kZx = 64;            // z pass: columns per block along x
+constexpr int kZy = 4;             // z pass: columns per block along y
+constexpr int kThreads = 256;
+
+// Sampled, truncated, unit-sum Gaussian taps w[k + R], k = -R..R.
+struct Taps {
+    float w[2 * kMaxR + 1];
+};
+
+struct Grid3 {
+    int nx, ny, nz;
+    int64_t sxy;  // nx * ny
+};
+
+// Epilogue of the first z pass: region fits and the two force-convolution
+// inputs g1 = l1 f1 - l2 f2, g2 = l1 f1^2 - l2 f2^2.
+struct FitArgs {
+    const float *KI;              // K * I
+    const float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
+    float l1, l2;
+    float *probe_f1, *probe_f2;   // optional
+};
+
+// Epilogue of the second z pass: force, curvature, regulariser, update.
+struct UpdArgs {
+    const float *I;               // image
+    const float *phi;             // phi_n
+    float *phi_out;               // phi_{n+1}
+    const float *cx, *cy, *cz;
+    float l1, l2, nu, mu, dt;
+    float eps_over_pi, eps2;      // delta = eps_over_pi / (eps2 + phi^2)
+    float eta;
+    int reg;                      // 0 double well, 1 single well
+    double *partials;             // one sum|dphi| per block
+    float *probe_Fd, *probe_kappa, *probe_lap, *probe_R, *probe_E;
+};
+
+// Number of z chunks a z pass splits the volume into (also sizes the
+// per-block partial sums of the update pass).
+int z_chunks(const Grid3 &g);
+int64_t z_blocks(const Grid3 &g);
+
+hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,
+                        hipStream_t s);
+hipError_t launch_flags_init(int *flags, hipStream_t s);
+
+// xy pass modes: one field; (phi, I) -> (H I, H); two fields.
+enum XyMode { XY_ONE = 0, XY_HEAVISIDE = 1, XY_TWO = 2 };
+hipError_t launch_xy(int R, int mode, const float *a, const float *b, float *oa, float *ob,
+                     Grid3 g, const Taps &t, float eps, float *probeH, const int *done,
+                     hipStream_t s);
+
+hipError_t launch_z_plain(int R, const float *in, float *out, Grid3 g, const Taps &t,
+                          hipStream_t s);
+hipError_t launch_z_fits(int R, const float *t1, const float *t2, float *g1, float *g2,
+                         Grid3 g, const Taps &t, const FitArgs &fa, const int *done,
+                         hipStream_t s);
+hipError_t launch_z_update(int R, const float *t1, const float *t2, Grid3 g, const Taps &t,
+                           const UpdArgs &ua, const int *done, hipStream_t s);
+hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,
+                         double tol_total, hipStream_t s);
+
+}  // namespace rsf

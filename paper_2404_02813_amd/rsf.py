@@ -1,0 +1,251 @@
+"""Thin ctypes binding of the C ABI in include/rsf.h (same names).
+
+Argument marshalling only: every step of the evolution runs in the HIP
+kernels of librsf.so.  PyTorch supplies device memory (tensors) and streams;
+the library never sees a torch type.  If librsf.so is missing or cannot be
+loaded this module raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsf.so")
+
+RSF_OK = 0
+RSF_ERR_INVALID_ARG = -1
+RSF_ERR_OUT_OF_MEMORY = -2
+RSF_ERR_DEVICE = -3
+RSF_ERR_NONFINITE = -4
+RSF_ERR_BUDGET = -5
+RSF_ERR_INTERNAL = -6
+
+RSF_F32 = 0
+
+RSF_REG_DOUBLE_WELL = 0
+RSF_REG_SINGLE_WELL = 1
+
+EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
+           "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe")
+
+
+class RsfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rsf status {status}: {msg}")
+        self.status = status
+
+
+class rsf_params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float), ("lambda1", ctypes.c_float),
+                ("lambda2", ctypes.c_float), ("nu", ctypes.c_float), ("mu", ctypes.c_float),
+                ("dt", ctypes.c_float), ("eps", ctypes.c_float), ("eta", ctypes.c_float),
+                ("regulariser", ctypes.c_int)]
+
+
+class rsf_stats(ctypes.Structure):
+    _fields_ = [("iters_requested", ctypes.c_int), ("iters_run", ctypes.c_int),
+                ("last_sum_abs", ctypes.c_double)]
+
+
+PROBE_NAMES = ("H", "f1", "f2", "Fd", "kappa", "lap", "R", "E", "phi_next")
+
+
+class rsf_probe_fields(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in PROBE_NAMES]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librsf.so (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2404_02813_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, f, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_int
+    L.rsf_create.argtypes = [ctypes.POINTER(vp), i]
+    L.rsf_create.restype = i
+    L.rsf_destroy.argtypes = [vp]
+    L.rsf_destroy.restype = None
+    L.rsf_last_error.argtypes = [vp]
+    L.rsf_last_error.restype = ctypes.c_char_p
+    L.rsf_workspace_bytes.argtypes = [i64, i64, i64, i]
+    L.rsf_workspace_bytes.restype = ctypes.c_size_t
+    L.rsf_evolve.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, f, f, f, f, i, vp]
+    L.rsf_evolve.restype = i
+    L.rsf_evolve_ex.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params), i,
+                                ctypes.c_double, vp, ctypes.c_size_t, vp]
+    L.rsf_evolve_ex.restype = i
+    L.rsf_get_stats.argtypes = [vp, ctypes.POINTER(rsf_stats), ctypes.POINTER(ctypes.c_double), i]
+    L.rsf_get_stats.restype = i
+    L.rsf_gauss3d.argtypes = [vp, vp, vp, i64, i64, i64, f, vp]
+    L.rsf_gauss3d.restype = i
+    L.rsf_probe.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params),
+                            ctypes.POINTER(rsf_probe_fields), vp]
+    L.rsf_probe.restype = i
+    _lib = L
+    return L
+
+
+def _check(ctx, status: int) -> None:
+    if status != RSF_OK:
+        msg = lib().rsf_last_error(ctx).decode(errors="replace") if ctx else ""
+        raise RsfError(status, msg)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _field(t: torch.Tensor, name: str, dtype=torch.float32) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if t.dim() != 3 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 3D tensor [nz][ny][nx]")
+    return t
+
+
+def make_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10,
+                regulariser=RSF_REG_DOUBLE_WELL) -> rsf_params:
+    return rsf_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta, regulariser)
+
+
+def rsf_create(device: int = 0) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    st = lib().rsf_create(ctypes.byref(ctx), int(device))
+    if st != RSF_OK:
+        raise RsfError(st, f"rsf_create(device={device}) failed")
+    return ctx
+
+
+def rsf_destroy(ctx) -> None:
+    if ctx:
+        lib().rsf_destroy(ctx)
+
+
+def rsf_last_error(ctx) -> str:
+    return lib().rsf_last_error(ctx).decode(errors="replace")
+
+
+def rsf_workspace_bytes(nx: int, ny: int, nz: int, iters: int) -> int:
+    return int(lib().rsf_workspace_bytes(nx, ny, nz, iters))
+
+
+def rsf_evolve(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma: float, lambda1: float,
+               lambda2: float, nu: float, mu: float, dt: float, eps: float, iters: int,
+               stream=None) -> None:
+    """Evolve `phi` in place (default double-well regulariser)."""
+    _field(volume, "volume")
+    _field(phi, "phi")
+    if volume.shape != phi.shape or volume.device != phi.device:
+        raise ValueError("volume and phi must have the same shape and device")
+    nz, ny, nx = phi.shape
+    _check(ctx, lib().rsf_evolve(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+                                 sigma, lambda1, lambda2, nu, mu, dt, eps, int(iters),
+                                 _stream(stream)))
+
+
+def rsf_evolve_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params, iters: int,
+                  tol: float = 0.0, workspace: torch.Tensor | None = None, stream=None) -> None:
+    _field(volume, "volume")
+    _field(phi, "phi")
+    if volume.shape != phi.shape or volume.device != phi.device:
+        raise ValueError("volume and phi must have the same shape and device")
+    nz, ny, nx = phi.shape
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous CUDA tensor")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    _check(ctx, lib().rsf_evolve_ex(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+                                    ctypes.byref(params), int(iters), float(tol), ws_ptr,
+                                    ws_bytes, _stream(stream)))
+
+
+def rsf_get_stats(ctx, cap: int = 0):
+    """Returns (iters_requested, iters_run, last_sum_abs, history list)."""
+    st = rsf_stats()
+    hist = (ctypes.c_double * max(cap, 1))()
+    status = lib().rsf_get_stats(ctx, ctypes.byref(st), hist if cap > 0 else None, int(cap))
+    _check(ctx, status)
+    n = min(cap, st.iters_run)
+    return st.iters_requested, st.iters_run, st.last_sum_abs, [hist[i] for i in range(n)]
+
+
+def rsf_gauss3d(ctx, inp: torch.Tensor, out: torch.Tensor, sigma: float, stream=None) -> None:
+    _field(inp, "in")
+    _field(out, "out")
+    if inp.shape != out.shape:
+        raise ValueError("in and out must have the same shape")
+    nz, ny, nx = inp.shape
+    _check(ctx, lib().rsf_gauss3d(ctx, inp.data_ptr(), out.data_ptr(), nx, ny, nz, float(sigma),
+                                  _stream(stream)))
+
+
+def rsf_probe(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
+              stream=None) -> dict:
+    """One iteration's intermediate fields as new tensors (see rsf.h)."""
+    _field(volume, "volume")
+    _field(phi, "phi")
+    nz, ny, nx = phi.shape
+    out = {n: torch.empty_like(phi) for n in PROBE_NAMES}
+    pf = rsf_probe_fields(*[out[n].data_ptr() for n in PROBE_NAMES])
+    _check(ctx, lib().rsf_probe(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+                                ctypes.byref(params), ctypes.byref(pf), _stream(stream)))
+    return out
+
+
+class Context:
+    """Owns an rsf_context for one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        self.handle = rsf_create(self.device)
+
+    def close(self) -> None:
+        if self.handle:
+            rsf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def evolve(self, volume, phi, iters, sigma=3.0, lambda1=1.0, lambda2=1.0, nu=0.001, mu=1.0,
+               dt=0.1, eps=1.0, stream=None):
+        rsf_evolve(self.handle, volume, phi, sigma, lambda1, lambda2, nu, mu, dt, eps, iters,
+                   stream)
+
+    def evolve_ex(self, volume, phi, params, iters, tol=0.0, workspace=None, stream=None):
+        rsf_evolve_ex(self.handle, volume, phi, params, iters, tol, workspace, stream)
+
+    def stats(self, cap=0):
+        return rsf_get_stats(self.handle, cap)
+
+    def gauss3d(self, inp, sigma, out=None, stream=None):
+        out = torch.empty_like(inp) if out is None else out
+        rsf_gauss3d(self.handle, inp, out, sigma, stream)
+        return out
+
+    def probe(self, volume, phi, params, stream=None):
+        return rsf_probe(self.handle, volume, phi, params, stream)

@@ -1,0 +1,171 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bar (FP32 on the GPU vs FP64 oracle on the same seeded inputs):
+  - single passes and one-step fields: close to FP32 rounding of the value,
+    tolerances stated per test;
+  - after N iterations: max|dphi| <= 1e-3 and >= 99.99 % agreement of phi > 0.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2404_02813_amd import inputs  # noqa: E402
+
+PHI_TOL = 1e-3
+SIGN_AGREE = 0.9999
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rsf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_02813_amd import rsf as mod
+    ctx = mod.Context(0)
+    yield mod, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def smooth(shape, seed, amp=3.0):
+    from scipy.ndimage import gaussian_filter
+    r = np.random.default_rng(seed)
+    return (amp * 4.0 * gaussian_filter(r.normal(size=shape), 1.5, mode="reflect")).astype(np.float32)
+
+
+def params(mod, sigma=3.0, lambda1=1.0, lambda2=1.0, nu=0.001, mu=1.0, dt=0.1, eps=1.0,
+           reg=0):
+    return mod.make_params(sigma, lambda1, lambda2, nu, mu, dt, eps, 1e-10, reg)
+
+
+def oparams(sigma=3.0, lambda1=1.0, lambda2=1.0, nu=0.001, mu=1.0, dt=0.1, eps=1.0):
+    return oracle.params_array(sigma, lambda1, lambda2, nu, mu, dt, eps, 1e-10)
+
+
+# --- one Gaussian convolution ---------------------------------------------------
+
+@pytest.mark.parametrize("shape,sigma", [((33, 45, 67), 1.5), ((33, 45, 67), 3.0),
+                                         ((7, 4, 5), 3.0), ((3, 3, 3), 1.0),
+                                         ((20, 130, 70), 4.0), ((17, 19, 200), 5.0)])
+def test_gauss3d_matches_oracle(rsf, shape, sigma):
+    mod, ctx = rsf
+    say(f"gauss3d shape={shape} sigma={sigma}")
+    u = np.random.default_rng(1).uniform(-1, 1, size=shape).astype(np.float32)
+    got = host(ctx.gauss3d(dev(u), sigma))
+    want = oracle.conv3d(u.astype(np.float64), sigma)
+    assert np.max(np.abs(got - want)) < 2e-6
+
+
+# --- one iteration's fields -------------------------------------------------------
+
+FIELD_TOL = {"H": 1e-6, "f1": 2e-5, "f2": 2e-5, "Fd": 2e-5, "kappa": 2e-5, "lap": 2e-5,
+             "R": 2e-5, "E": 2e-5, "phi_next": 2e-6}
+
+
+@pytest.mark.parametrize("shape,sigma,reg", [((35, 37, 40), 3.0, 0), ((35, 37, 40), 3.0, 1),
+                                             ((21, 19, 70), 2.0, 0), ((9, 8, 7), 3.0, 0)])
+def test_probe_fields_match_oracle(rsf, shape, sigma, reg):
+    mod, ctx = rsf
+    say(f"probe shape={shape} sigma={sigma} reg={reg}")
+    I = inputs.vessel_phantom(shape, 6, 1.0, 3.0, seed=3)
+    phi = smooth(shape, 4)
+    got = {k: host(v) for k, v in ctx.probe(dev(I), dev(phi),
+                                               params(mod, sigma=sigma, lambda1=2.0,
+                                                      lambda2=1.5, nu=0.2, reg=reg)).items()}
+    nxt, f, _ = oracle.step(I, phi, oparams(sigma=sigma, lambda1=2.0, lambda2=1.5, nu=0.2),
+                            reg=1 - reg)
+    want = dict(f)
+    want["Fd"] = 2.0 * f["e1"] - 1.5 * f["e2"]
+    want["phi_next"] = nxt
+    for k, tol in FIELD_TOL.items():
+        scale = max(1.0, float(np.max(np.abs(want[k]))))
+        err = float(np.max(np.abs(got[k] - want[k])))
+        assert err < tol * scale, (k, err, scale)
+
+
+# --- multi-iteration evolution ------------------------------------------------------
+
+def parity(got, want):
+    d = np.abs(got - want)
+    agree = float(np.mean((got > 0) == (want > 0)))
+    return float(d.max()), agree
+
+
+def run_gpu(ctx, I, phi0, w, iters=None):
+    phi = dev(phi0)
+    ctx.evolve(dev(I), phi, w.iters if iters is None else iters, **w.params())
+    return host(phi)
+
+
+def test_evolve_small_vessel_volume(rsf):
+    mod, ctx = rsf
+    w = inputs.SMALL_64
+    say(f"evolve {w.name}")
+    I, phi0 = w.image(), w.phi0()
+    got = run_gpu(ctx, I, phi0, w)
+    _, _, _, hist = ctx.stats(cap=w.iters)
+    want, whist = oracle.evolve(I, phi0, oracle.params_array(**w.params(), eta=1e-10), w.iters)
+    dmax, agree = parity(got, want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.6f}")
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+    assert np.max(np.abs(np.array(hist) / whist - 1.0)) < 1e-3
+
+
+def test_evolve_odd_shape_many_iterations(rsf):
+    mod, ctx = rsf
+    w = inputs.Workload("odd", (45, 71, 67), 10, 1.0, 4.0, seed=7, iters=60)
+    say(f"evolve {w.name} {w.shape}")
+    I, phi0 = w.image(), w.phi0()
+    got = run_gpu(ctx, I, phi0, w)
+    want, _ = oracle.evolve(I, phi0, oracle.params_array(**w.params(), eta=1e-10), w.iters)
+    dmax, agree = parity(got, want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.6f}")
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+
+
+def test_zero_iterations_is_a_no_op(rsf):
+    mod, ctx = rsf
+    say("iters=0")
+    phi0 = inputs.box_phi0((16, 16, 16))
+    phi = dev(phi0)
+    ctx.evolve(dev(np.ones((16, 16, 16), np.float32)), phi, 0)
+    assert np.array_equal(host(phi), phi0)
+
+
+def test_invalid_arguments_leave_phi_untouched(rsf):
+    mod, ctx = rsf
+    say("invalid args")
+    phi0 = inputs.box_phi0((8, 8, 8))
+    phi = dev(phi0)
+    I = dev(np.ones((8, 8, 8), np.float32))
+    for kw in (dict(sigma=-1.0), dict(sigma=6.0), dict(eps=0.0), dict(dt=0.0),
+               dict(nu=-1.0), dict(sigma=float("nan"))):
+        with pytest.raises(mod.RsfError) as e:
+            ctx.evolve(I, phi, 3, **kw)
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
+    with pytest.raises(mod.RsfError):
+        ctx.evolve(I, phi, -1)
+    small = dev(np.ones((2, 8, 8), np.float32))
+    with pytest.raises(mod.RsfError):
+        ctx.evolve(small, dev(np.ones((2, 8, 8), np.float32)), 1)
+    assert np.array_equal(host(phi), phi0)
