@@ -1,0 +1,210 @@
+"""Throughput benchmark of the RSF level-set evolution on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one whole evolution (rsf_evolve through the C ABI): the per-volume
+set-up (K*1 tables, K*I) and `iters` RSF iterations over the workload's
+volume, starting from phi0, with the image and phi0 already resident in HBM.
+Prints ONE JSON line with Gvoxel-iter/s, the roofline of the dominant kernel
+(timed live with HIP events recorded by the library on the stream it launches
+on), and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gvoxel-iter/s at 512^3 sigma=3 (% HBM peak); p50/p99 tile latency"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+# Algorithmic HBM bytes per voxel for one launch of each pass (FP32 fields):
+# reads + writes that the pass must make, each field once.
+PASS_BYTES = {
+    "z_heaviside": 16,    # phi, I -> Kz*(HI), Kz*H
+    "xy_fits": 20,        # Kz*(HI), Kz*H, K*I -> g1, g2
+    "xy_force": 16,       # g1, g2 -> Kxy*g1, Kxy*g2
+    "z_update": 20,       # Kxy*g1, Kxy*g2, I, phi -> phi'
+}
+ITER_BYTES = sum(PASS_BYTES.values())   # 72 B per voxel-iteration
+
+KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
+                  "paper_2404_02813_amd/csrc/rsf_kernels.hpp",
+                  "paper_2404_02813_amd/csrc/rsf_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    rec = data.get(f"{kernel}@{workload}")
+    if not rec or rec.get("source_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0):
+    """The FP64 oracle on a centred crop of the same phantom (bounded sample)."""
+    import numpy as np
+
+    import oracle
+
+    n = 192 if w.shape[0] >= 192 else w.shape[0]
+    sl = tuple(slice((s - n) // 2, (s - n) // 2 + n) for s in w.shape)
+    Ic = np.ascontiguousarray(I[sl], dtype=np.float64)
+    pc = np.ascontiguousarray(phi0[sl], dtype=np.float64)
+    p = oracle.params_array(**w.params(), eta=1e-10)
+    t0 = time.perf_counter()
+    oracle.evolve(Ic, pc, p, 1)
+    t1 = time.perf_counter()
+    iters = max(1, min(50, int(seconds_hint / max(t1 - t0, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.evolve(Ic, pc, p, iters)
+    dt = time.perf_counter() - t0
+    vox_iters = float(n ** 3) * iters
+    return {"value": vox_iters / dt / 1e9, "unit": "Gvoxel-iter/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{n}^3 centre crop of the {w.name} phantom and phi0, {iters} iterations, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="vessel512_s3_it200")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2404_02813_amd import inputs, rsf
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    workloads = {w.name: w for w in (inputs.SMALL_64, inputs.LARGE_512)}
+    w = workloads[args.workload]
+    K, W = max(1, args.steps), max(0, args.warmup)
+
+    t_gen = time.perf_counter()
+    I_host, phi0_host = w.image(), w.phi0()
+    vol = torch.from_numpy(I_host).cuda()
+    phi0 = torch.from_numpy(phi0_host).cuda()
+    t_gen = time.perf_counter() - t_gen
+    phis = [torch.empty_like(phi0) for _ in range(K)]
+    ctx = rsf.Context(0)
+    scratch = torch.empty_like(phi0)
+    p = w.params()
+
+    for _ in range(W):
+        scratch.copy_(phi0)
+        ctx.evolve(vol, scratch, w.iters, **p)
+    for ph in phis:
+        ph.copy_(phi0)
+    torch.cuda.synchronize()
+
+    # HBM copy bandwidth of a plain device copy, for context.
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ph in phis:
+        ctx.evolve(vol, ph, w.iters, **p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    prof = ctx.profile_read()
+    _, iters_run, last_s, _ = ctx.stats(cap=0)
+    ok = bool(torch.isfinite(phis[-1]).all().item()) and bool(np.isfinite(last_s))
+
+    elapsed = t1 - t0
+    vox = w.voxels
+    value = vox * w.iters * K / elapsed / 1e9
+    hot = {k: v for k, v in prof.items() if k in PASS_BYTES}
+    dom = max(hot, key=lambda k: hot[k][1])
+    launches, total_ms = hot[dom]
+    avg_s = total_ms / launches * 1e-3
+    achieved = PASS_BYTES[dom] * vox / avg_s / 1e9
+    traffic = traffic_for(dom, w.name)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gvoxel-iter/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shape_zyx": list(w.shape), "sigma": w.sigma,
+                   "iters": w.iters, "n_tubes": w.n_tubes, "lambda1": w.lambda1,
+                   "lambda2": w.lambda2, "nu": w.nu, "mu": w.mu, "dt": w.dt, "eps": w.eps,
+                   "regulariser": "double_well", "parallelism": "single_gpu"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_voxel": PASS_BYTES[dom],
+                     "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches},
+        "hbm_frac_path": round(value * ITER_BYTES / HBM_PEAK_GBS, 4),
+        "path_bytes_per_voxel_iter": ITER_BYTES,
+        "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
+        "copy_gbs": round(copy_gbs, 1),
+        "iters_run": iters_run,
+        "finite": ok,
+        "input_gen_s": round(t_gen, 1),
+    }
+    ctx.close()
+    del phis, vol, phi0, scratch
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, I_host, phi0_host, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -154,6 +154,30 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
                      int64_t nx, int64_t ny, int64_t nz, const rsf_params *params,
                      const rsf_probe_fields *fields, void *stream);
 
+/* Per-pass timing with HIP events recorded around every launch on the
+ * caller's stream (tracing support; the paper profiles per kernel in
+ * Table 1).  Passes of one iteration: */
+typedef enum {
+    RSF_PASS_SETUP = 0,        /* edge tables of K*1 and K*I, once per call   */
+    RSF_PASS_Z_HEAVISIDE = 1,  /* z Gaussian of (H I, H)                      */
+    RSF_PASS_XY_FITS = 2,      /* xy Gaussian + region fits -> g1, g2         */
+    RSF_PASS_XY_FORCE = 3,     /* xy Gaussian of (g1, g2)                     */
+    RSF_PASS_Z_UPDATE = 4,     /* z Gaussian + force, curvature, update       */
+    RSF_PASS_REDUCE = 5,       /* FP64 sum |dphi|                             */
+    RSF_PASS_COUNT = 6
+} rsf_pass;
+
+typedef struct {
+    int launches[RSF_PASS_COUNT];
+    double ms[RSF_PASS_COUNT];      /* summed event time per pass */
+} rsf_profile;
+
+/* Start (on != 0) or stop recording events on later launches. */
+rsf_status rsf_profile_enable(rsf_context *ctx, int on);
+
+/* Wait for the recorded launches, return their totals and clear them. */
+rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

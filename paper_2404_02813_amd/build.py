@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsf.so")
-SOURCES = ["rsf_kernels.hip", "rsf_api.hip"]
+SOURCES = ["rsf_kernels.hip", "rsf_api.hip", "rsf_inst_a.hip", "rsf_inst_b.hip",
+           "rsf_inst_c.hip", "rsf_inst_d.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -8,6 +8,7 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rsf.h"
 #include "rsf_internal.hpp"
@@ -23,6 +24,15 @@ struct rsf_context {
     const int *last_flags = nullptr;
     int last_iters = 0;
     bool has_last = false;
+    // per-pass event timing
+    bool prof = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<Rec> recs;
 };
 
 namespace {
@@ -93,6 +103,32 @@ rsf_status hip_fail(rsf_context *ctx, hipError_t e, const char *what)
         hipError_t e_ = (expr);                          \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
+
+hipEvent_t take_event(rsf_context *ctx)
+{
+    if (ctx->ev_used < ctx->ev_pool.size()) return ctx->ev_pool[ctx->ev_used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+    ctx->ev_used = ctx->ev_pool.size();
+    return e;
+}
+
+// Launch through `fn`, bracketed by events on `s` while profiling is on.
+template <class F>
+hipError_t timed(rsf_context *ctx, int kind, hipStream_t s, F &&fn)
+{
+    if (!ctx->prof) return fn();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e == hipSuccess) ctx->recs.push_back({kind, a, b});
+    return e;
+}
 
 bool finite(float v) { return std::isfinite(v); }
 
@@ -177,12 +213,16 @@ Plan make_plan(int64_t nx, int64_t ny, int64_t nz, float sigma, int iters, char 
 // Per-volume set-up: edge tables of K*1, flags, and K*I.
 rsf_status prologue(rsf_context *ctx, const Plan &P, const float *I, hipStream_t s)
 {
-    HIP_TRY(rsf::launch_flags_init(P.flags, s), "flags_init");
-    HIP_TRY(rsf::launch_edges(P.cx, P.cy, P.cz, P.g, P.taps, P.R, s), "edges");
-    HIP_TRY(rsf::launch_xy(P.R, rsf::XY_ONE, I, nullptr, P.T1, nullptr, P.g, P.taps, 1.f,
-                           nullptr, nullptr, s),
-            "xy(K*I)");
-    HIP_TRY(rsf::launch_z_plain(P.R, P.T1, P.KI, P.g, P.taps, s), "z(K*I)");
+    HIP_TRY(timed(ctx, RSF_PASS_SETUP, s, [&] {
+                hipError_t e = rsf::launch_flags_init(P.flags, s);
+                if (e == hipSuccess) e = rsf::launch_edges(P.cx, P.cy, P.cz, P.g, P.taps, P.R, s);
+                if (e == hipSuccess)
+                    e = rsf::launch_xy(P.R, rsf::XY_ONE, I, nullptr, P.T1, nullptr, P.g, P.taps,
+                                       nullptr, nullptr, s);
+                if (e == hipSuccess) e = rsf::launch_z_plain(P.R, P.T1, P.KI, P.g, P.taps, s);
+                return e;
+            }),
+            "setup (K*1 tables, K*I)");
     return RSF_OK;
 }
 
@@ -197,14 +237,21 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, const float *I, const floa
                      const Probe &pr, hipStream_t s)
 {
     const int *done = P.flags;
-    HIP_TRY(rsf::launch_xy(P.R, rsf::XY_HEAVISIDE, cur, I, P.T1, P.T2, P.g, P.taps, p.eps, pr.H,
-                           done, s),
-            "xy(H)");
+    HIP_TRY(timed(ctx, RSF_PASS_Z_HEAVISIDE, s, [&] {
+                return rsf::launch_z_heaviside(P.R, cur, I, P.T1, P.T2, P.g, P.taps, p.eps, pr.H,
+                                               done, s);
+            }),
+            "z(H)");
     rsf::FitArgs fa{P.KI, P.cx, P.cy, P.cz, p.lambda1, p.lambda2, pr.f1, pr.f2};
-    HIP_TRY(rsf::launch_z_fits(P.R, P.T1, P.T2, P.G1, P.G2, P.g, P.taps, fa, done, s),
-            "z(fits)");
-    HIP_TRY(rsf::launch_xy(P.R, rsf::XY_TWO, P.G1, P.G2, P.T1, P.T2, P.g, P.taps, p.eps,
-                           nullptr, done, s),
+    HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
+                return rsf::launch_xy(P.R, rsf::XY_FITS, P.T1, P.T2, P.G1, P.G2, P.g, P.taps, &fa,
+                                      done, s);
+            }),
+            "xy(fits)");
+    HIP_TRY(timed(ctx, RSF_PASS_XY_FORCE, s, [&] {
+                return rsf::launch_xy(P.R, rsf::XY_TWO, P.G1, P.G2, P.T1, P.T2, P.g, P.taps,
+                                      nullptr, done, s);
+            }),
             "xy(g)");
     rsf::UpdArgs ua{};
     ua.I = I;
@@ -219,8 +266,13 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, const float *I, const floa
     ua.partials = P.partials;
     ua.probe_Fd = pr.Fd; ua.probe_kappa = pr.kappa; ua.probe_lap = pr.lap;
     ua.probe_R = pr.R; ua.probe_E = pr.E;
-    HIP_TRY(rsf::launch_z_update(P.R, P.T1, P.T2, P.g, P.taps, ua, done, s), "z(update)");
-    HIP_TRY(rsf::launch_reduce(P.partials, rsf::z_blocks(P.g), hist_slot, P.flags, tol_total, s),
+    HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s,
+                  [&] { return rsf::launch_z_update(P.R, P.T1, P.T2, P.g, P.taps, ua, done, s); }),
+            "z(update)");
+    HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] {
+                return rsf::launch_reduce(P.partials, rsf::z_blocks(P.g), hist_slot, P.flags,
+                                          tol_total, s);
+            }),
             "reduce");
     return RSF_OK;
 }
@@ -313,14 +365,44 @@ void rsf_destroy(rsf_context *ctx)
 {
     if (!ctx) return;
     try {
-        if (ctx->ws) {
-            (void)hipSetDevice(ctx->device);
-            (void)hipDeviceSynchronize();
-            (void)hipFree(ctx->ws);
-        }
+        (void)hipSetDevice(ctx->device);
+        if (ctx->ws || !ctx->ev_pool.empty()) (void)hipDeviceSynchronize();
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     } catch (...) {
     }
     delete ctx;
+}
+
+rsf_status rsf_profile_enable(rsf_context *ctx, int on)
+{
+    if (!ctx) return RSF_ERR_INVALID_ARG;
+    ctx->prof = on != 0;
+    return RSF_OK;
+}
+
+rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out)
+{
+    try {
+        if (!ctx || !out) return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
+        std::memset(out, 0, sizeof(*out));
+        rsf_status st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        for (const auto &r : ctx->recs) {
+            HIP_TRY(hipEventSynchronize(r.b), "hipEventSynchronize");
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+            if (r.kind >= 0 && r.kind < RSF_PASS_COUNT) {
+                out->launches[r.kind] += 1;
+                out->ms[r.kind] += ms;
+            }
+        }
+        ctx->recs.clear();
+        ctx->ev_used = 0;
+        return RSF_OK;
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
 }
 
 const char *rsf_last_error(const rsf_context *ctx)
@@ -421,8 +503,8 @@ rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx
         const Taps t = make_taps(sigma, R);
         float *tmp = static_cast<float *>(ctx->ws);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        HIP_TRY(rsf::launch_xy(R, rsf::XY_ONE, in, nullptr, tmp, nullptr, g, t, 1.f, nullptr,
-                               nullptr, s),
+        HIP_TRY(rsf::launch_xy(R, rsf::XY_ONE, in, nullptr, tmp, nullptr, g, t, nullptr, nullptr,
+                               s),
                 "xy");
         HIP_TRY(rsf::launch_z_plain(R, tmp, out, g, t, s), "z");
         return RSF_OK;

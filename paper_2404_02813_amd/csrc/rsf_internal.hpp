@@ -26,7 +26,7 @@ struct Grid3 {
     int64_t sxy;  // nx * ny
 };
 
-// Epilogue of the first z pass: region fits and the two force-convolution
+// Epilogue of the stage-1 xy pass: region fits and the two force-convolution
 // inputs g1 = l1 f1 - l2 f2, g2 = l1 f1^2 - l2 f2^2.
 struct FitArgs {
     const float *KI;              // K * I
@@ -35,7 +35,7 @@ struct FitArgs {
     float *probe_f1, *probe_f2;   // optional
 };
 
-// Epilogue of the second z pass: force, curvature, regulariser, update.
+// Epilogue of the stage-2 z pass: force, curvature, regulariser, update.
 struct UpdArgs {
     const float *I;               // image
     const float *phi;             // phi_n
@@ -53,25 +53,40 @@ struct UpdArgs {
 // per-block partial sums of the update pass).
 int z_chunks(const Grid3 &g);
 int64_t z_blocks(const Grid3 &g);
+int xy_blocks(const Grid3 &g);
 
 hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,
                         hipStream_t s);
 hipError_t launch_flags_init(int *flags, hipStream_t s);
 
-// xy pass modes: one field; (phi, I) -> (H I, H); two fields.
-enum XyMode { XY_ONE = 0, XY_HEAVISIDE = 1, XY_TWO = 2 };
+// xy pass modes: one field; two fields; two fields + region-fit epilogue.
+enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2 };
 hipError_t launch_xy(int R, int mode, const float *a, const float *b, float *oa, float *ob,
-                     Grid3 g, const Taps &t, float eps, float *probeH, const int *done,
-                     hipStream_t s);
+                     Grid3 g, const Taps &t, const FitArgs *fa, const int *done, hipStream_t s);
 
 hipError_t launch_z_plain(int R, const float *in, float *out, Grid3 g, const Taps &t,
                           hipStream_t s);
-hipError_t launch_z_fits(int R, const float *t1, const float *t2, float *g1, float *g2,
-                         Grid3 g, const Taps &t, const FitArgs &fa, const int *done,
-                         hipStream_t s);
+// Stage-1 z pass: (phi, I) -> Kz*(H I), Kz*H.
+hipError_t launch_z_heaviside(int R, const float *phi, const float *I, float *t1, float *t2,
+                              Grid3 g, const Taps &t, float eps, float *probeH, const int *done,
+                              hipStream_t s);
 hipError_t launch_z_update(int R, const float *t1, const float *t2, Grid3 g, const Taps &t,
                            const UpdArgs &ua, const int *done, hipStream_t s);
 hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,
                          double tol_total, hipStream_t s);
+
+// Per-radius launchers behind the dispatchers above (rsf_kernels.hpp).
+template <int R>
+hipError_t launch_xy_r(int mode, const float *a, const float *b, float *oa, float *ob, Grid3 g,
+                       const Taps &t, const FitArgs *fa, const int *done, hipStream_t s);
+template <int R>
+hipError_t launch_z_plain_r(const float *in, float *out, Grid3 g, const Taps &t, hipStream_t s);
+template <int R>
+hipError_t launch_z_heaviside_r(const float *phi, const float *I, float *t1, float *t2, Grid3 g,
+                                const Taps &t, float eps, float *probeH, const int *done,
+                                hipStream_t s);
+template <int R>
+hipError_t launch_z_update_r(const float *t1, const float *t2, Grid3 g, const Taps &t,
+                             const UpdArgs &ua, const int *done, hipStream_t s);
 
 }  // namespace rsf

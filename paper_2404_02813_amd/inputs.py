@@ -46,15 +46,16 @@ def tube_mask(shape, n_tubes: int, r_min: float, r_max: float,
         rc = int(math.ceil(r))
         o = np.arange(-rc, rc + 2)
         off = np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3)
+        # offsets that can lie within r of a centre in [0, 1)^3 around the base voxel
+        off = off[(((off - 0.5) ** 2).sum(-1)) <= (r + 0.87) ** 2].astype(np.int32)
         for s0 in range(0, m, 2048):
             t = np.arange(s0, min(m, s0 + 2048), dtype=np.float64) / max(m - 1, 1)
             t = t[:, None]
-            c = (1 - t) ** 2 * p0 + 2 * (1 - t) * t * p1 + t ** 2 * p2      # (k, 3) xyz
-            v = np.floor(c).astype(np.int64)[:, None, :] + off[None, :, :]   # (k, K, 3)
+            c = ((1 - t) ** 2 * p0 + 2 * (1 - t) * t * p1 + t ** 2 * p2).astype(np.float32)
+            v = np.floor(c).astype(np.int32)[:, None, :] + off[None, :, :]   # (k, K, 3)
             d2 = ((v - c[:, None, :]) ** 2).sum(-1)
-            keep = d2 <= r * r
-            v = v[keep]
-            ok = ((v >= 0) & (v < np.array([nx, ny, nz]))).all(-1)
+            v = v[d2 <= r * r]
+            ok = ((v >= 0) & (v < np.array([nx, ny, nz], dtype=np.int32))).all(-1)
             v = v[ok]
             mask[v[:, 2], v[:, 1], v[:, 0]] = True
     return mask
@@ -73,7 +74,7 @@ def vessel_phantom(shape, n_tubes: int, r_min: float, r_max: float, seed: int,
     del m
     img = gaussian_filter(clean, sigma=blur_sd, truncate=3.0, mode="reflect")
     del clean
-    img += rng.normal(0.0, noise_sd, size=shape).astype(np.float32)
+    img += np.float32(noise_sd) * rng.standard_normal(size=shape, dtype=np.float32)
     return np.ascontiguousarray(img, dtype=np.float32)
 
 

@@ -29,7 +29,10 @@ RSF_REG_DOUBLE_WELL = 0
 RSF_REG_SINGLE_WELL = 1
 
 EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
-           "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe")
+           "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
+           "rsf_profile_enable", "rsf_profile_read")
+
+PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce")
 
 
 class RsfError(RuntimeError):
@@ -48,6 +51,10 @@ class rsf_params(ctypes.Structure):
 class rsf_stats(ctypes.Structure):
     _fields_ = [("iters_requested", ctypes.c_int), ("iters_run", ctypes.c_int),
                 ("last_sum_abs", ctypes.c_double)]
+
+
+class rsf_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int * 6), ("ms", ctypes.c_double * 6)]
 
 
 PROBE_NAMES = ("H", "f1", "f2", "Fd", "kappa", "lap", "R", "E", "phi_next")
@@ -89,6 +96,10 @@ def lib() -> ctypes.CDLL:
     L.rsf_probe.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params),
                             ctypes.POINTER(rsf_probe_fields), vp]
     L.rsf_probe.restype = i
+    L.rsf_profile_enable.argtypes = [vp, i]
+    L.rsf_profile_enable.restype = i
+    L.rsf_profile_read.argtypes = [vp, ctypes.POINTER(rsf_profile)]
+    L.rsf_profile_read.restype = i
     _lib = L
     return L
 
@@ -207,6 +218,17 @@ def rsf_probe(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
     return out
 
 
+def rsf_profile_enable(ctx, on: bool) -> None:
+    _check(ctx, lib().rsf_profile_enable(ctx, 1 if on else 0))
+
+
+def rsf_profile_read(ctx) -> dict:
+    """{pass name: (launches, total ms)} since profiling was enabled."""
+    pr = rsf_profile()
+    _check(ctx, lib().rsf_profile_read(ctx, ctypes.byref(pr)))
+    return {n: (pr.launches[i], pr.ms[i]) for i, n in enumerate(PASS_NAMES)}
+
+
 class Context:
     """Owns an rsf_context for one device."""
 
@@ -249,3 +271,9 @@ class Context:
 
     def probe(self, volume, phi, params, stream=None):
         return rsf_probe(self.handle, volume, phi, params, stream)
+
+    def profile(self, on: bool) -> None:
+        rsf_profile_enable(self.handle, on)
+
+    def profile_read(self) -> dict:
+        return rsf_profile_read(self.handle)
