@@ -63,7 +63,7 @@ Layout layout(int64_t nx, int64_t ny, int64_t nz, int iters)
     L.cy = off; off += align_up((size_t)ny * sizeof(float));
     L.cz = off; off += align_up((size_t)nz * sizeof(float));
     Grid3 g{(int)nx, (int)ny, (int)nz, nx * ny};
-    L.partials = off; off += align_up((size_t)rsf::z_blocks(g) * sizeof(double));
+    L.partials = off; off += align_up((size_t)rsf::u_blocks(g) * sizeof(double));
     L.hist = off; off += align_up((size_t)(iters > 0 ? iters : 1) * sizeof(double));
     L.flags = off; off += align_up(4 * sizeof(int));
     L.total = off;
@@ -270,7 +270,7 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, const float *I, const floa
                   [&] { return rsf::launch_z_update(P.R, P.T1, P.T2, P.g, P.taps, ua, done, s); }),
             "z(update)");
     HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] {
-                return rsf::launch_reduce(P.partials, rsf::z_blocks(P.g), hist_slot, P.flags,
+                return rsf::launch_reduce(P.partials, rsf::u_blocks(P.g), hist_slot, P.flags,
                                           tol_total, s);
             }),
             "reduce");

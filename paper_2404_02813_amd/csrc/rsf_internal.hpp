@@ -10,11 +10,12 @@
 namespace rsf {
 
 constexpr int kMaxR = 16;          // largest Gaussian radius (sigma <= 16/3)
-constexpr int kXyTx = 64;          // xy pass: outputs per tile along x
-constexpr int kXyTy = 32;          // xy pass: outputs per tile along y
 constexpr int kZx = 64;            // z pass: columns per block along x
 constexpr int kZy = 4;             // z pass: columns per block along y
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // z pass block
+constexpr int kUx = 64;            // update pass: columns per block along x
+constexpr int kUy = 8;             // update pass: columns per block along y
+constexpr int kUThreads = kUx * kUy;
 
 // Sampled, truncated, unit-sum Gaussian taps w[k + R], k = -R..R.
 struct Taps {
@@ -53,6 +54,9 @@ struct UpdArgs {
 // per-block partial sums of the update pass).
 int z_chunks(const Grid3 &g);
 int64_t z_blocks(const Grid3 &g);
+int u_chunks(const Grid3 &g);
+int64_t u_blocks(const Grid3 &g);   // blocks (and partial sums) of the update pass
+int xy_chunks(const Grid3 &g);
 int xy_blocks(const Grid3 &g);
 
 hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,

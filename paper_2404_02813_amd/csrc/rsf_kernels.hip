@@ -79,16 +79,22 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double *__restri
 // Launchers
 // ---------------------------------------------------------------------------
 
+// Split n into the fewest chunks giving at least `want` blocks over `cols`
+// columns, each chunk at least `least` long; every chunk is non-empty.
+static int chunks(int64_t n, int64_t cols, int64_t want_blocks, int64_t least)
+{
+    int64_t want = (want_blocks + cols - 1) / cols;
+    const int64_t most = (n + least - 1) / least;
+    if (want > most) want = most;
+    if (want < 1) want = 1;
+    const int64_t len = (n + want - 1) / want;
+    return (int)((n + len - 1) / len);
+}
+
 int z_chunks(const Grid3 &g)
 {
     const int64_t cols = (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy);
-    int64_t want = (2048 + cols - 1) / cols;
-    const int64_t most = (g.nz + 7) / 8;   // chunks of at least 8 slices
-    if (want > most) want = most;
-    if (want < 1) want = 1;
-    // re-derive so that every chunk is non-empty
-    const int lz = (int)((g.nz + want - 1) / want);
-    return (g.nz + lz - 1) / lz;
+    return chunks(g.nz, cols, 2048, 8);
 }
 
 int64_t z_blocks(const Grid3 &g)
@@ -96,10 +102,30 @@ int64_t z_blocks(const Grid3 &g)
     return (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy) * z_chunks(g);
 }
 
-int xy_blocks(const Grid3 &g)
+int u_chunks(const Grid3 &g)
 {
-    return ((g.nx + kXyTx - 1) / kXyTx) * ((g.ny + kXyTy - 1) / kXyTy) * g.nz;
+    const int64_t cols = (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy);
+    return chunks(g.nz, cols, 1024, 8);
 }
+
+int64_t u_blocks(const Grid3 &g)
+{
+    return (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy) * u_chunks(g);
+}
+
+// xy pass: one wave per (64-wide strip, row chunk, slice); rows per chunk
+// >= 8, enough chunks for ~16K waves, no more than needed for 128-row chunks.
+int xy_chunks(const Grid3 &g)
+{
+    const int64_t strips = (g.nx + 63) / 64;
+    const int64_t base = (g.ny + 127) / 128;
+    int64_t c = chunks(g.ny, strips * g.nz, 16384, 8);
+    if (c < base) c = base;
+    const int64_t len = (g.ny + c - 1) / c;
+    return (int)((g.ny + len - 1) / len);
+}
+
+int xy_blocks(const Grid3 &g) { return (int)(((g.nx + 63) / 64) * xy_chunks(g) * g.nz); }
 
 hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,
                         hipStream_t s)

@@ -23,6 +23,11 @@ __device__ __forceinline__ float heaviside(float phi, float eps)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Make `v` opaque to the optimiser: it must be computed here, so a sum that
+// feeds a register ring is not sunk to its distant use (which would keep all
+// of its inputs live instead of one value).
+__device__ __forceinline__ void pin(float &v) { __asm__ volatile("" : "+v"(v)); }
+
 __device__ __forceinline__ int reflect(int i, int n)
 {
     return i < 0 ? -i : (i > n - 1 ? 2 * (n - 1) - i : i);
@@ -38,151 +43,136 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 // ---------------------------------------------------------------------------
-// xy pass: LDS tile (kXyTy + 2R) rows x (kXyTx + 2HL) columns (HL = R rounded
-// up to 4 so rows load as float4), x convolution into registers, back to
-// LDS, y convolution, then the mode's epilogue and a coalesced store.
+// xy pass as a march along y.  One wave owns a 64-wide strip of one z slice
+// and a chunk of rows.  Each incoming row (with an R halo in x) is staged in
+// LDS, convolved along x (one output per lane), and pushed into a per-lane
+// register ring of 2R+1 rows, from which the y convolution is taken; x halo
+// work is paid only on the chunk's 2R extra rows, never per row.
 // ---------------------------------------------------------------------------
 
 template <int R, int MODE>
-__global__ __launch_bounds__(kThreads) void xy_kernel(const float *__restrict__ a,
-                                                      const float *__restrict__ b,
-                                                      float *__restrict__ oa,
-                                                      float *__restrict__ ob, Grid3 g, Taps t,
-                                                      FitArgs fa, const int *__restrict__ done)
+__global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
+                                                const float *__restrict__ b,
+                                                float *__restrict__ oa, float *__restrict__ ob,
+                                                Grid3 g, Taps t, FitArgs fa, int nyc,
+                                                const int *__restrict__ done)
 {
     if (done && *done) return;
     constexpr int NF = MODE == XY_ONE ? 1 : 2;
-    constexpr int TX = kXyTx, TY = kXyTy;
-    constexpr int HL = 4 * ((R + 3) / 4);
-    constexpr int LW = TX + 2 * HL;          // loaded columns
-    constexpr int PITCH = LW + 4;            // + one float4 the x windows may over-read
-    constexpr int OFF = HL - R;
-    constexpr int ROWS = TY + 2 * R;
     constexpr int W = 2 * R + 1;
-    constexpr int NQ = LW / 4;
-    __shared__ __align__(16) float s[NF][ROWS][PITCH];
+    constexpr int RW = 64 + 2 * R;
+    __shared__ float row[2][NF][RW];
 
-    const int nbx = (g.nx + TX - 1) / TX, nby = (g.ny + TY - 1) / TY;
+    const int nbx = (g.nx + 63) / 64;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int bxi = tile % nbx, rest = tile / nbx;
-    const int x0 = bxi * TX, y0 = (rest % nby) * TY, z = rest / nby;
+    const int xs = tile % nbx, rest = tile / nbx;
+    const int yc = rest % nyc, z = rest / nyc;
+    const int ly = (g.ny + nyc - 1) / nyc;
+    const int y0 = yc * ly, y1 = min(y0 + ly, g.ny);
+    const int lane = threadIdx.x;
+    const int x0 = xs * 64, x = x0 + lane;
     const int64_t zb = (int64_t)z * g.sxy;
-    const int tid = threadIdx.x;
-    const bool vec = (g.nx & 3) == 0;
 
-    for (int i = tid; i < ROWS * NQ; i += kThreads) {
-        const int r = i / NQ, q = i - r * NQ;
-        const int gy = y0 + r - R;
-        const int gx = x0 - HL + 4 * q;
-        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
-        if (gy >= 0 && gy < g.ny) {
-            const float *ra = a + zb + (int64_t)gy * g.nx;
-            const float *rb = NF == 2 ? b + zb + (int64_t)gy * g.nx : nullptr;
-            if (vec && gx >= 0 && gx + 3 < g.nx) {
-                va = *reinterpret_cast<const float4 *>(ra + gx);
-                if (NF == 2) vb = *reinterpret_cast<const float4 *>(rb + gx);
-            } else {
-                float ea[4] = {0.f, 0.f, 0.f, 0.f}, eb[4] = {0.f, 0.f, 0.f, 0.f};
+    // A row's loads are issued one step before the row is staged, so the
+    // global latency overlaps the previous row's arithmetic.
+    struct Raw {
+        float a[2], b[2];
+    };
+    auto fetch = [&](int y) {
+        Raw r;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int xx = gx + e;
-                    if (xx >= 0 && xx < g.nx) {
-                        ea[e] = ra[xx];
-                        if (NF == 2) eb[e] = rb[xx];
-                    }
-                }
-                va = make_float4(ea[0], ea[1], ea[2], ea[3]);
-                vb = make_float4(eb[0], eb[1], eb[2], eb[3]);
+        for (int h = 0; h < 2; ++h) {
+            r.a[h] = 0.f;
+            r.b[h] = 0.f;
+            const int j = lane + 64 * h;
+            const int gx = x0 - R + j;
+            if (j < RW && y >= 0 && y < g.ny && gx >= 0 && gx < g.nx) {
+                const int64_t i = zb + (int64_t)y * g.nx + gx;
+                r.a[h] = a[i];
+                if (NF == 2) r.b[h] = b[i];
             }
         }
-        *reinterpret_cast<float4 *>(&s[0][r][4 * q]) = va;
-        if (NF == 2) *reinterpret_cast<float4 *>(&s[NF - 1][r][4 * q]) = vb;
-    }
-    __syncthreads();
-
-    // x convolution: each lane makes 4 consecutive outputs of one row from a
-    // window read with 16-byte LDS loads.
-    const int lane = tid & 63, wave = tid >> 6;
-    const int xg = lane & 15, rsub = lane >> 4;
-    constexpr int NPASS = (ROWS + 15) / 16;
-    constexpr int NV = (OFF + 4 + 2 * R + 3) / 4;
-    float xr[NF][NPASS][4];
+        return r;
+    };
+    // stage a fetched row into LDS slot `slot`, x-convolve it, return the lane's value
+    auto xrow = [&](const Raw &r, int slot) -> float2 {
 #pragma unroll
-    for (int j = 0; j < NPASS; ++j) {
-        const int r = wave * 4 + rsub + 16 * j;
-        if (r < ROWS) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                float win[4 * NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const float4 q = *reinterpret_cast<const float4 *>(&s[f][r][4 * xg + 4 * v]);
-                    win[4 * v + 0] = q.x;
-                    win[4 * v + 1] = q.y;
-                    win[4 * v + 2] = q.z;
-                    win[4 * v + 3] = q.w;
-                }
-#pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int k = 0; k < W; ++k) acc = fmaf(t.w[k], win[OFF + o + k], acc);
-                    xr[f][j][o] = acc;
-                }
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * h;
+            if (j < RW) {
+                row[slot][0][j] = r.a[h];
+                if (NF == 2) row[slot][NF - 1][j] = r.b[h];
             }
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NPASS; ++j) {
-        const int r = wave * 4 + rsub + 16 * j;
-        if (r < ROWS) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-                *reinterpret_cast<float4 *>(&s[f][r][4 * xg]) =
-                    make_float4(xr[f][j][0], xr[f][j][1], xr[f][j][2], xr[f][j][3]);
-        }
-    }
-    __syncthreads();
-
-    // y convolution: lane = column, each wave makes TY/4 consecutive rows.
-    constexpr int RPW = TY / 4;
-    const int gx = x0 + lane;
-    const int rbase = wave * RPW;
-    float wa[RPW + 2 * R], wb[RPW + 2 * R];
-#pragma unroll
-    for (int i = 0; i < RPW + 2 * R; ++i) {
-        wa[i] = s[0][rbase + i][lane];
-        if (NF == 2) wb[i] = s[NF - 1][rbase + i][lane];
-    }
-    float cxv = 0.f;
-    if (MODE == XY_FITS && gx < g.nx) cxv = fa.cx[gx] * fa.cz[z];
-#pragma unroll
-    for (int o = 0; o < RPW; ++o) {
-        float acc_a = 0.f, acc_b = 0.f;
+        __syncthreads();
+        float ca = 0.f, cb = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            acc_a = fmaf(t.w[k], wa[o + k], acc_a);
-            if (NF == 2) acc_b = fmaf(t.w[k], wb[o + k], acc_b);
+            ca = fmaf(t.w[k], row[slot][0][lane + k], ca);
+            if (NF == 2) cb = fmaf(t.w[k], row[slot][NF - 1][lane + k], cb);
         }
-        const int gy = y0 + rbase + o;
-        if (gx < g.nx && gy < g.ny) {
-            const int64_t v = zb + (int64_t)gy * g.nx + gx;
-            if (MODE == XY_FITS) {
-                // region fits (Sec. 3 local_intensity) and force-convolution inputs
-                const float K1 = cxv * fa.cy[gy];
-                const float A2 = fa.KI[v] - acc_a;
-                const float B2 = K1 - acc_b;
-                const float f1 = acc_a * rcp(acc_b);
-                const float f2 = A2 * rcp(B2);
-                oa[v] = fa.l1 * f1 - fa.l2 * f2;
-                ob[v] = fa.l1 * f1 * f1 - fa.l2 * f2 * f2;
-                if (fa.probe_f1) fa.probe_f1[v] = f1;
-                if (fa.probe_f2) fa.probe_f2[v] = f2;
-            } else {
-                oa[v] = acc_a;
-                if (NF == 2) ob[v] = acc_b;
+        pin(ca);
+        if (NF == 2) pin(cb);
+        return make_float2(ca, cb);
+    };
+
+    float ra[W], rb[W];
+    Raw nxt = fetch(y0 - R);
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+        const Raw cur = nxt;
+        nxt = fetch(y0 - R + j + 1);
+        const float2 v = xrow(cur, j & 1);
+        ra[j] = v.x;
+        rb[j] = v.y;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    float cxz = 0.f;
+    const int xc = min(x, g.nx - 1);
+    if (MODE == XY_FITS) cxz = fa.cx[xc] * fa.cz[z];
+    float ki_next = MODE == XY_FITS ? fa.KI[zb + (int64_t)y0 * g.nx + xc] : 0.f;
+    for (int yb = y0; yb < y1; yb += W) {
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            const int y = yb + s;
+            if (y < y1) {
+                const Raw cur = nxt;
+                nxt = fetch(y + R + 1);
+                float ki = 0.f;
+                if (MODE == XY_FITS) {
+                    ki = ki_next;
+                    if (y + 1 < y1) ki_next = fa.KI[zb + (int64_t)(y + 1) * g.nx + xc];
+                }
+                // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
+                const float2 v = xrow(cur, (y - y0) & 1);
+                ra[(s + 2 * R) % W] = v.x;
+                rb[(s + 2 * R) % W] = v.y;
+                float acc_a = 0.f, acc_b = 0.f;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    acc_a = fmaf(t.w[k], ra[(s + k) % W], acc_a);
+                    if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % W], acc_b);
+                }
+                if (x < g.nx) {
+                    const int64_t v = zb + (int64_t)y * g.nx + x;
+                    if (MODE == XY_FITS) {
+                        // region fits (Sec. 3 local_intensity), force-convolution inputs
+                        const float K1 = cxz * fa.cy[y];
+                        const float A2 = ki - acc_a;
+                        const float B2 = K1 - acc_b;
+                        const float f1 = acc_a * rcp(acc_b);
+                        const float f2 = A2 * rcp(B2);
+                        oa[v] = fa.l1 * f1 - fa.l2 * f2;
+                        ob[v] = fa.l1 * f1 * f1 - fa.l2 * f2 * f2;
+                        if (fa.probe_f1) fa.probe_f1[v] = f1;
+                        if (fa.probe_f2) fa.probe_f2[v] = f2;
+                    } else {
+                        oa[v] = acc_a;
+                        if (NF == 2) ob[v] = acc_b;
+                    }
+                }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -198,16 +188,17 @@ struct ZTile {
     bool active;
 };
 
-// Tiles are (kZx x kZy columns) x (one z chunk), z chunk fastest.
-__device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc)
+// Tiles are (TX x TY columns) x (one z chunk), z chunk fastest.
+template <int TX, int TY>
+__device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc)
 {
     ZTile zt;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int nbx = (g.nx + kZx - 1) / kZx;
+    const int nbx = (g.nx + TX - 1) / TX;
     const int zc = tile % nzc, col = tile / nzc;
     const int lz = (g.nz + nzc - 1) / nzc;
-    zt.x = (col % nbx) * kZx + (threadIdx.x & (kZx - 1));
-    zt.y = (col / nbx) * kZy + (threadIdx.x / kZx);
+    zt.x = (col % nbx) * TX + (threadIdx.x & (TX - 1));
+    zt.y = (col / nbx) * TY + (threadIdx.x / TX);
     zt.z0 = zc * lz;
     zt.z1 = min(zt.z0 + lz, g.nz);
     zt.tile = tile;
@@ -215,19 +206,34 @@ __device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc)
     return zt;
 }
 
-// Conv ring: ld(z) returns slice z (0 <= z < nz) of the two inputs.
-template <int R, int NF, typename Ld, typename Epi>
-__device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, Ld &&ld,
-                                        Epi &&epi)
+__device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc) { return z_tile_t<kZx, kZy>(g, nzc); }
+
+// Conv ring.  fetch(z) loads the raw inputs of slice z (0 <= z < nz) and
+// cook(raw, z) turns them into the two convolved quantities; each slice is
+// fetched one step before it is cooked so the load latency overlaps the
+// previous step's arithmetic.
+template <int R, int NF, typename Fetch, typename Cook, typename Epi>
+__device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, Fetch &&fetch,
+                                        Cook &&cook, Epi &&epi)
 {
     constexpr int W = 2 * R + 1;
     float ra[W], rb[W];
+    auto get = [&](int z) { return (z >= 0 && z < nz) ? fetch(z) : make_float2(0.f, 0.f); };
+    auto use = [&](float2 raw, int z) {
+        float2 v = (z >= 0 && z < nz) ? cook(raw, z) : make_float2(0.f, 0.f);
+        pin(v.x);
+        if (NF == 2) pin(v.y);
+        return v;
+    };
+    float2 nxt = get(z0 - R);
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) {
-        const int z = z0 - R + j;
-        const float2 v = (z >= 0 && z < nz) ? ld(z) : make_float2(0.f, 0.f);
+        const float2 cur = nxt;
+        nxt = get(z0 - R + j + 1);
+        const float2 v = use(cur, z0 - R + j);
         ra[j] = v.x;
         rb[j] = v.y;
+        __builtin_amdgcn_sched_barrier(0);
     }
     for (int zb = z0; zb < z1; zb += W) {
 #pragma unroll
@@ -235,7 +241,9 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, L
             const int z = zb + s;
             if (z < z1) {
                 const int zn = z + R;
-                const float2 v = zn < nz ? ld(zn) : make_float2(0.f, 0.f);
+                const float2 cur = nxt;
+                nxt = get(zn + 1);
+                const float2 v = use(cur, zn);
                 ra[(s + 2 * R) % W] = v.x;
                 rb[(s + 2 * R) % W] = v.y;
                 float acc_a = 0.f, acc_b = 0.f;
@@ -246,8 +254,8 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, L
                 }
                 epi(z, acc_a, acc_b);
             }
-            // keep each step's loads and math inside the step: occupancy,
-            // not hoisting, hides the latency
+            // keep each step's work inside the step; the one-step prefetch and
+            // occupancy hide the latency
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -264,6 +272,7 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(const float *__restri
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) { return make_float2(in[col + (int64_t)z * g.sxy], 0.f); },
+        [&](float2 raw, int) { return raw; },
         [&](int z, float va, float) { out[col + (int64_t)z * g.sxy] = va; });
 }
 
@@ -282,9 +291,12 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
             const int64_t v = col + (int64_t)z * g.sxy;
-            const float H = heaviside(phi[v], eps);
-            if (PROBE && probeH) probeH[v] = H;
-            return make_float2(H * I[v], H);
+            return make_float2(phi[v], I[v]);
+        },
+        [&](float2 raw, int z) {
+            const float H = heaviside(raw.x, eps);
+            if (PROBE && probeH) probeH[col + (int64_t)z * g.sxy] = H;
+            return make_float2(H * raw.y, H);
         },
         [&](int z, float va, float vb) {
             const int64_t v = col + (int64_t)z * g.sxy;
@@ -293,13 +305,27 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
         });
 }
 
-// Diffusion-rate excess D(s) = d_p(s) - 1 of the distance regulariser.
+// Unit normal n = g / sqrt(|g|^2 + eta) and regulariser flux V = D(|g|) g,
+// D(s) = d_p(s) - 1.  Double well: D = sin(2 pi s)/(2 pi s) - 1 for s <= 1,
+// -1/s for s > 1, 0 at s = 0; single well: D = -1/sqrt(|g|^2 + eta).
 // v_sin_f32 takes its argument in turns, so it returns sin(2 pi s).
-__device__ __forceinline__ float reg_rate(float s, float s_eta, int reg)
+__device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float eta, int reg,
+                                            float &nx_, float &ny_, float &nz_, float &vx_,
+                                            float &vy_, float &vz_)
 {
-    if (reg != 0) return -rcp(s_eta);                       // single well
-    const float dw = __builtin_amdgcn_sinf(s) * rcp(kTwoPi * s) - 1.f;
-    return s > 1.f ? -rcp(s) : (s > 0.f ? dw : 0.f);
+    const float s2 = gx * gx + gy * gy + gz * gz;
+    const float inv_eta = __builtin_amdgcn_rsqf(s2 + eta);
+    float D;
+    if (reg != 0) {
+        D = -inv_eta;
+    } else {
+        const float rs = __builtin_amdgcn_rsqf(s2);        // inf at s2 = 0
+        const float sv = s2 * rs;                           // |g| (NaN at 0)
+        const float dw = __builtin_amdgcn_sinf(sv) * rs * (1.f / kTwoPi) - 1.f;
+        D = sv > 1.f ? -rs : (s2 > 0.f ? dw : 0.f);
+    }
+    nx_ = gx * inv_eta; ny_ = gy * inv_eta; nz_ = gz * inv_eta;
+    vx_ = D * gx; vy_ = D * gy; vz_ = D * gz;
 }
 
 // Stage-2 z pass with the update.  The block's tile is kZx x kZy columns.
@@ -310,21 +336,21 @@ __device__ __forceinline__ float reg_rate(float s, float s_eta, int reg)
 // registers.  Each point's gradient, n and V are computed once and shared by
 // the six neighbours whose divergence needs them.
 template <int R, bool PROBE>
-__global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restrict__ t1,
-                                                            const float *__restrict__ t2,
-                                                            Grid3 g, Taps t, UpdArgs ua,
-                                                            int nzc, const int *__restrict__ done)
+__global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__restrict__ t1,
+                                                             const float *__restrict__ t2,
+                                                             Grid3 g, Taps t, UpdArgs ua,
+                                                             int nzc, const int *__restrict__ done)
 {
-    constexpr int TX = kZx, TY = kZy;
+    constexpr int TX = kUx, TY = kUy, NT = kUThreads;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int QX = TX + 2, QY = TY + 2;
     constexpr int NSLOT = 5;
-    constexpr int NLD = (PX * PY + kThreads - 1) / kThreads;
+    constexpr int NLD = (PX * PY + NT - 1) / NT;
     __shared__ float sphi[NSLOT][PY * PX];
     __shared__ float sq[2][4][QY * QX];   // n_x, V_x, n_y, V_y
-    __shared__ double wsum[kThreads / 64];
+    __shared__ double wsum[NT / 64];
 
-    const ZTile zt = z_tile(g, nzc);
+    const ZTile zt = z_tile_t<TX, TY>(g, nzc);
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1), ty = tid / TX;
     const int x0 = zt.x - tx, y0 = zt.y - ty;
@@ -344,19 +370,29 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
         bool lok[NLD];
 #pragma unroll
         for (int r = 0; r < NLD; ++r) {
-            const int i = tid + r * kThreads;
+            const int i = tid + r * NT;
             lok[r] = i < PX * PY;
             const int px = i % PX, py = i / PX;
             const int gx = reflect(min(x0 - 2 + px, g.nx + 1), g.nx);
             const int gy = reflect(min(y0 - 2 + py, g.ny + 1), g.ny);
             loff[r] = gy * g.nx + gx;
         }
-        auto load_phi = [&](int j) {
+        // a slice's tile is fetched into registers one step before it is stored
+        struct PhiRaw {
+            float v[NLD];
+        };
+        auto fetch_phi = [&](int j) {
+            PhiRaw r;
             const float *base = phi + (int64_t)reflect(j, g.nz) * g.sxy;
+#pragma unroll
+            for (int k = 0; k < NLD; ++k) r.v[k] = lok[k] ? base[loff[k]] : 0.f;
+            return r;
+        };
+        auto store_phi = [&](const PhiRaw &r, int j) {
             float *dst = sphi[(j + 2 * NSLOT) % NSLOT];
 #pragma unroll
-            for (int r = 0; r < NLD; ++r)
-                if (lok[r]) dst[tid + r * kThreads] = base[loff[r]];
+            for (int k = 0; k < NLD; ++k)
+                if (lok[k]) dst[tid + k * NT] = r.v[k];
         };
         // n and V at phi-tile point (cx, cy) of slice j
         auto qcalc = [&](int j, int cx, int cy, float &nx_, float &vx_, float &ny_, float &vy_,
@@ -368,15 +404,10 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
             const float gx = 0.5f * (p0[c + 1] - p0[c - 1]);
             const float gy = 0.5f * (p0[c + PX] - p0[c - PX]);
             const float gz = 0.5f * (pp[c] - pm[c]);
-            const float s2 = gx * gx + gy * gy + gz * gz;
-            const float s_eta = __builtin_amdgcn_sqrtf(s2 + ua.eta);
-            const float inv = rcp(s_eta);
-            const float D = reg_rate(__builtin_amdgcn_sqrtf(s2), s_eta, ua.reg);
-            nx_ = gx * inv; ny_ = gy * inv; nz_ = gz * inv;
-            vx_ = D * gx; vy_ = D * gy; vz_ = D * gz;
+            normal_flux(gx, gy, gz, ua.eta, ua.reg, nx_, ny_, nz_, vx_, vy_, vz_);
         };
-        // halo points of the normal/flux tile: y halo rows (threads 0..127),
-        // x halo columns (threads 128..135)
+        // halo points of the normal/flux tile: y halo rows (threads 0..2TX-1),
+        // x halo columns (the next 2TY threads)
         int hq = -1;
         if (tid < 2 * TX) hq = (tid < TX ? 0 : QY - 1) * QX + (tid % TX) + 1;
         else if (tid < 2 * TX + 2 * TY) {
@@ -406,10 +437,10 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
 
         const int64_t col = (int64_t)min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
         const float cxy = ua.cx[min(zt.x, g.nx - 1)] * ua.cy[min(zt.y, g.ny - 1)];
-        load_phi(zt.z0 - 2);
-        load_phi(zt.z0 - 1);
+        store_phi(fetch_phi(zt.z0 - 2), zt.z0 - 2);
+        store_phi(fetch_phi(zt.z0 - 1), zt.z0 - 1);
         for (int j = zt.z0 - 2; j < zt.z0; ++j) {
-            load_phi(j + 2);
+            store_phi(fetch_phi(j + 2), j + 2);
             __syncthreads();
             q_phase(j + 1);
             __syncthreads();
@@ -424,16 +455,26 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
             ra[j] = ok ? t1[col + (int64_t)z * g.sxy] : 0.f;
             rb[j] = ok ? t2[col + (int64_t)z * g.sxy] : 0.f;
         }
+        __builtin_amdgcn_sched_barrier(0);
+        // one-step-ahead prefetch of the next phi slice, conv inputs and image
+        PhiRaw phi_nxt = fetch_phi(zt.z0 + 2);
+        float t1_nxt = zt.z0 + R < g.nz ? t1[col + (int64_t)(zt.z0 + R) * g.sxy] : 0.f;
+        float t2_nxt = zt.z0 + R < g.nz ? t2[col + (int64_t)(zt.z0 + R) * g.sxy] : 0.f;
+        float I_nxt = ua.I[col + (int64_t)zt.z0 * g.sxy];
         for (int zb = zt.z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
-                    load_phi(z + 2);
-                    const int zn = z + R;
-                    const bool ok = zn < g.nz;
-                    ra[(s + 2 * R) % W] = ok ? t1[col + (int64_t)zn * g.sxy] : 0.f;
-                    rb[(s + 2 * R) % W] = ok ? t2[col + (int64_t)zn * g.sxy] : 0.f;
+                    store_phi(phi_nxt, z + 2);
+                    ra[(s + 2 * R) % W] = t1_nxt;
+                    rb[(s + 2 * R) % W] = t2_nxt;
+                    const float Iv = I_nxt;
+                    phi_nxt = fetch_phi(z + 3);
+                    const int zn = z + R + 1;
+                    t1_nxt = zn < g.nz ? t1[col + (int64_t)zn * g.sxy] : 0.f;
+                    t2_nxt = zn < g.nz ? t2[col + (int64_t)zn * g.sxy] : 0.f;
+                    if (z + 1 < zt.z1) I_nxt = ua.I[col + (int64_t)(z + 1) * g.sxy];
                     __syncthreads();
                     q_phase(z + 1);
                     __syncthreads();
@@ -460,7 +501,6 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
                         const float divV = 0.5f * (q[QY * QX + o + 1] - q[QY * QX + o - 1]) +
                                            0.5f * (q[3 * QY * QX + o + QX] - q[3 * QY * QX + o - QX]) +
                                            0.5f * (vzp - vzm);
-                        const float Iv = ua.I[v];
                         const float K1 = cxy * ua.cz[z];
                         const float Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
                         const float Rt = lap + divV;
@@ -478,16 +518,22 @@ __global__ __launch_bounds__(kThreads) void z_update_kernel(const float *__restr
                         }
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    // Block sum of |dphi| in a fixed order: wave tree, then the four waves.
+    // Block sum of |dphi| in a fixed order: wave tree, then the waves in order.
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if (lane == 0) wsum[wave] = acc;
     __syncthreads();
-    if (tid == 0) ua.partials[zt.tile] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    if (tid == 0) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) sum += wsum[w];
+        ua.partials[zt.tile] = sum;
+    }
 }
 
 }  // namespace
@@ -502,18 +548,19 @@ hipError_t launch_xy_r(int mode, const float *a, const float *b, float *oa, floa
 {
     const dim3 grid(xy_blocks(g));
     const FitArgs f = fa ? *fa : FitArgs{};
+    const int nyc = xy_chunks(g);
     switch (mode) {
     case XY_ONE:
-        hipLaunchKernelGGL((xy_kernel<R, XY_ONE>), grid, dim3(kThreads), 0, s, a, b, oa, ob, g, t,
-                           f, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_ONE>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
+                           nyc, done);
         break;
     case XY_TWO:
-        hipLaunchKernelGGL((xy_kernel<R, XY_TWO>), grid, dim3(kThreads), 0, s, a, b, oa, ob, g, t,
-                           f, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_TWO>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
+                           nyc, done);
         break;
     case XY_FITS:
-        hipLaunchKernelGGL((xy_kernel<R, XY_FITS>), grid, dim3(kThreads), 0, s, a, b, oa, ob, g,
-                           t, f, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_FITS>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
+                           nyc, done);
         break;
     default:
         return hipErrorInvalidValue;
@@ -548,14 +595,14 @@ template <int R>
 hipError_t launch_z_update_r(const float *t1, const float *t2, Grid3 g, const Taps &t,
                              const UpdArgs &ua, const int *done, hipStream_t s)
 {
-    const dim3 grid((unsigned)z_blocks(g));
+    const dim3 grid((unsigned)u_blocks(g));
     const bool probe = ua.probe_Fd || ua.probe_kappa || ua.probe_lap || ua.probe_R || ua.probe_E;
     if (probe)
-        hipLaunchKernelGGL((z_update_kernel<R, true>), grid, dim3(kThreads), 0, s, t1, t2, g, t, ua,
-                           z_chunks(g), done);
+        hipLaunchKernelGGL((z_update_kernel<R, true>), grid, dim3(kUThreads), 0, s, t1, t2, g, t,
+                           ua, u_chunks(g), done);
     else
-        hipLaunchKernelGGL((z_update_kernel<R, false>), grid, dim3(kThreads), 0, s, t1, t2, g, t,
-                           ua, z_chunks(g), done);
+        hipLaunchKernelGGL((z_update_kernel<R, false>), grid, dim3(kUThreads), 0, s, t1, t2, g, t,
+                           ua, u_chunks(g), done);
     return hipGetLastError();
 }
 

@@ -169,3 +169,157 @@ def test_invalid_arguments_leave_phi_untouched(rsf):
     with pytest.raises(mod.RsfError):
         ctx.evolve(small, dev(np.ones((2, 8, 8), np.float32)), 1)
     assert np.array_equal(host(phi), phi0)
+
+
+def test_evolve_vessel_recipe_200_iterations(rsf):
+    """The throughput workload's recipe (tubes r 1-4, sigma 3) at 96^3, same
+    200 iterations, against the oracle element by element."""
+    mod, ctx = rsf
+    w = inputs.scaled(inputs.LARGE_512, 96, iters=200)
+    say(f"evolve {w.name} {w.shape} x {w.iters}")
+    I, phi0 = w.image(), w.phi0()
+    got = run_gpu(ctx, I, phi0, w)
+    _, _, _, hist = ctx.stats(cap=w.iters)
+    want, whist = oracle.evolve(I, phi0, oracle.params_array(**w.params(), eta=1e-10), w.iters)
+    dmax, agree = parity(got, want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.7f}")
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+    assert np.max(np.abs(np.array(hist) / whist - 1.0)) < 1e-2
+
+
+def test_largest_radius(rsf):
+    mod, ctx = rsf
+    sigma = 5.33          # ceil(3 sigma) = 16, the largest radius
+    say("sigma=5.33 (R=16)")
+    w = inputs.Workload("r16", (40, 36, 70), 6, 1.0, 3.0, seed=21, iters=6, sigma=sigma)
+    I, phi0 = w.image(), w.phi0()
+    got = run_gpu(ctx, I, phi0, w)
+    want, _ = oracle.evolve(I, phi0, oracle.params_array(**w.params(), eta=1e-10), w.iters)
+    dmax, agree = parity(got, want)
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+
+
+def test_deterministic_and_resumable(rsf):
+    mod, ctx = rsf
+    say("determinism / resume")
+    w = inputs.Workload("det", (48, 50, 52), 8, 1.0, 3.0, seed=5, iters=25)
+    I, phi0 = w.image(), w.phi0()
+    vol = dev(I)
+    a = dev(phi0)
+    ctx.evolve(vol, a, 25, **w.params())
+    b = dev(phi0)
+    ctx.evolve(vol, b, 25, **w.params())
+    c = dev(phi0)
+    ctx.evolve(vol, c, 10, **w.params())
+    ctx.evolve(vol, c, 15, **w.params())
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+
+
+def test_caller_workspace_matches_own(rsf):
+    mod, ctx = rsf
+    say("caller workspace")
+    w = inputs.Workload("ws", (33, 47, 61), 8, 1.0, 3.0, seed=6, iters=7)
+    I, phi0 = w.image(), w.phi0()
+    vol = dev(I)
+    a = dev(phi0)
+    ctx.evolve(vol, a, w.iters, **w.params())
+    nb = mod.rsf_workspace_bytes(61, 47, 33, w.iters)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    b = dev(phi0)
+    ctx.evolve_ex(vol, b, params(mod, **w.params()), w.iters, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(mod.RsfError):
+        ctx.evolve_ex(vol, b, params(mod, **w.params()), w.iters, workspace=ws[: nb // 2])
+
+
+def test_tolerance_stops_early_and_freezes_phi(rsf):
+    mod, ctx = rsf
+    say("tol early stop")
+    w = inputs.Workload("tol", (40, 40, 40), 6, 1.0, 3.0, seed=8, iters=60)
+    I, phi0 = w.image(), w.phi0()
+    vol = dev(I)
+    # sum|dphi|/N falls 0.030, 0.019, ... 0.00186 (it 18), 0.00172 (it 19) in the
+    # oracle; a tolerance midway between those stops after 20 iterations
+    tol = 1.79e-3
+    a = dev(phi0)
+    ctx.evolve_ex(vol, a, params(mod, **w.params()), 60, tol=tol)
+    req, run, last, hist = ctx.stats(cap=60)
+    assert req == 60 and run == 20
+    assert last / (40 ** 3) < tol and all(h / 40 ** 3 >= tol for h in hist[:-1])
+    b = dev(phi0)
+    ctx.evolve(vol, b, run, **w.params())
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("perm", [(2, 0, 1), (1, 2, 0)])
+def test_axis_permutation_equivariance(rsf, perm):
+    mod, ctx = rsf
+    say(f"axis permutation {perm}")
+    w = inputs.Workload("perm", (30, 38, 46), 6, 1.0, 3.0, seed=9, iters=10)
+    I, phi0 = w.image(), w.phi0()
+    a = run_gpu(ctx, I, phi0, w)
+    Ip, pp = np.ascontiguousarray(np.transpose(I, perm)), np.ascontiguousarray(np.transpose(phi0, perm))
+    b = run_gpu(ctx, Ip, pp, w)
+    assert np.max(np.abs(np.transpose(a, perm) - b)) < 1e-4
+
+
+# --- the throughput workload at full size -----------------------------------------
+
+@pytest.fixture(scope="module")
+def large(rsf):
+    w = inputs.LARGE_512
+    say(f"generating {w.name}")
+    return w, w.image(), w.phi0()
+
+
+def crop_step(I, phi, center, margin, p):
+    """Oracle step on a crop; exact at `center` when every crop face that is
+    not a volume face lies >= margin voxels away."""
+    sl = tuple(slice(max(0, c - margin), min(n, c + margin + 1)) for c, n in zip(center, I.shape))
+    nxt, _, _ = oracle.step(I[sl], phi[sl], p)
+    local = tuple(c - s.start for c, s in zip(center, sl))
+    return nxt[local]
+
+
+def test_full_size_one_iteration_sampled(rsf, large):
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name}: one iteration, sampled voxels")
+    got = run_gpu(ctx, I, phi0, w, iters=1)
+    R = oracle.radius(w.sigma)
+    margin = 2 * R + 3
+    r = np.random.default_rng(12)
+    n = np.array(w.shape)
+    centers = [tuple(int(v) for v in r.integers(0, n)) for _ in range(10)]
+    centers += [(0, 0, 0), (511, 511, 511), (0, 255, 511), (128, 128, 128), (383, 127, 256),
+                (256, 256, 256), (5, 300, 2)]
+    p = oracle.params_array(**w.params(), eta=1e-10)
+    for c in centers:
+        want = crop_step(I, phi0, c, margin, p)
+        assert abs(got[c] - want) < 2e-6, (c, got[c], want)
+
+
+def test_full_size_200_iterations_properties(rsf, large):
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name}: 200 iterations, determinism and resume")
+    vol = dev(I)
+    a = dev(phi0)
+    ctx.evolve(vol, a, w.iters, **w.params())
+    _, run, last, hist = ctx.stats(cap=w.iters)
+    b = dev(phi0)
+    ctx.evolve(vol, b, 120, **w.params())
+    ctx.evolve(vol, b, w.iters - 120, **w.params())
+    torch.cuda.synchronize()
+    assert run == w.iters and np.isfinite(last)
+    assert torch.equal(a, b)
+    assert bool(torch.isfinite(a).all())
+    # the front moved but stayed a front: |phi| bounded, box region mostly kept
+    frac0 = float(np.mean(phi0 > 0))
+    frac = float((a > 0).float().mean())
+    assert 0.5 * frac0 < frac < 1.5 * frac0
+    assert hist[-1] < hist[0]
