@@ -96,6 +96,8 @@ def main() -> int:
     ap.add_argument("--workload", default="vessel512_s3_it200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--iters", type=int, default=0,
+                    help="override the workload's iteration count (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -113,6 +115,9 @@ def main() -> int:
         return 1
     workloads = {w.name: w for w in (inputs.SMALL_64, inputs.LARGE_512)}
     w = workloads[args.workload]
+    if args.iters > 0:
+        import dataclasses
+        w = dataclasses.replace(w, iters=args.iters)
     K, W = max(1, args.steps), max(0, args.warmup)
 
     t_gen = time.perf_counter()

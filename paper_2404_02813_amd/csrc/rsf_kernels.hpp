@@ -328,13 +328,20 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
     vx_ = D * gx; vy_ = D * gy; vz_ = D * gz;
 }
 
-// Stage-2 z pass with the update.  The block's tile is kZx x kZy columns.
+// Stage-2 z pass with the update.  The block's tile is kUx x kUy columns.
 // Alongside the per-thread conv ring it keeps in LDS a ring of phi slices
-// (tile + 2 halo, 5 slots) and, per slice, the x/y components of the unit
+// (tile + 2 halo, 6 slots) and, per slice, the x/y components of the unit
 // normal n and of the regulariser flux V = D(|grad phi|) grad phi at the tile
-// + 1 halo (2 slots); the z components of the thread's own column stay in
+// + 1 halo (3 slots); the z components of the thread's own column stay in
 // registers.  Each point's gradient, n and V are computed once and shared by
 // the six neighbours whose divergence needs them.
+//
+// Step z of the march (one barrier per step):
+//   store phi(z+3) (fetched one step earlier); barrier;
+//   n, V of slice z+2; update of slice z (reads n, V of slices z-1..z+1).
+// Slot reuse is safe: phi(z+3) overwrites phi(z-3), last read in step z-2;
+// n, V of z+2 overwrite those of z-1, last read in step z-1; a barrier
+// separates each pair.
 template <int R, bool PROBE>
 __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__restrict__ t1,
                                                              const float *__restrict__ t2,
@@ -344,10 +351,11 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
     constexpr int TX = kUx, TY = kUy, NT = kUThreads;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int QX = TX + 2, QY = TY + 2;
-    constexpr int NSLOT = 5;
+    constexpr int QS = QY * QX;
+    constexpr int NPHI = 6, NQ = 3;
     constexpr int NLD = (PX * PY + NT - 1) / NT;
-    __shared__ float sphi[NSLOT][PY * PX];
-    __shared__ float sq[2][4][QY * QX];   // n_x, V_x, n_y, V_y
+    __shared__ float sphi[NPHI][PY * PX];
+    __shared__ float sq[NQ][4][QS];   // n_x, V_x, n_y, V_y
     __shared__ double wsum[NT / 64];
 
     const ZTile zt = z_tile_t<TX, TY>(g, nzc);
@@ -377,19 +385,22 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
             const int gy = reflect(min(y0 - 2 + py, g.ny + 1), g.ny);
             loff[r] = gy * g.nx + gx;
         }
-        // a slice's tile is fetched into registers one step before it is stored
         struct PhiRaw {
             float v[NLD];
         };
+        // Slices used for outputs lie in [-2, nz + 1]; the march also touches
+        // up to nz + 3 (prefetch and n, V past the chunk end, never used), so
+        // clamp before reflecting to keep every address inside the volume.
         auto fetch_phi = [&](int j) {
             PhiRaw r;
-            const float *base = phi + (int64_t)reflect(j, g.nz) * g.sxy;
+            const float *base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) r.v[k] = lok[k] ? base[loff[k]] : 0.f;
             return r;
         };
+        auto phi_slot = [&](int j) { return sphi[(j + 2 * NPHI) % NPHI]; };
         auto store_phi = [&](const PhiRaw &r, int j) {
-            float *dst = sphi[(j + 2 * NSLOT) % NSLOT];
+            float *dst = phi_slot(j);
 #pragma unroll
             for (int k = 0; k < NLD; ++k)
                 if (lok[k]) dst[tid + k * NT] = r.v[k];
@@ -397,9 +408,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
         // n and V at phi-tile point (cx, cy) of slice j
         auto qcalc = [&](int j, int cx, int cy, float &nx_, float &vx_, float &ny_, float &vy_,
                          float &nz_, float &vz_) {
-            const float *p0 = sphi[(j + 2 * NSLOT) % NSLOT];
-            const float *pm = sphi[(j - 1 + 2 * NSLOT) % NSLOT];
-            const float *pp = sphi[(j + 1 + 2 * NSLOT) % NSLOT];
+            const float *p0 = phi_slot(j), *pm = phi_slot(j - 1), *pp = phi_slot(j + 1);
             const int c = cy * PX + cx;
             const float gx = 0.5f * (p0[c + 1] - p0[c - 1]);
             const float gy = 0.5f * (p0[c + PX] - p0[c - PX]);
@@ -415,69 +424,69 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
             hq = (k % TY + 1) * QX + (k < TY ? 0 : QX - 1);
         }
         const int own_q = (ty + 1) * QX + tx + 1;
-        float nzm = 0.f, vzm = 0.f, nz0 = 0.f, vz0 = 0.f, nzp = 0.f, vzp = 0.f;
-        auto q_phase = [&](int j) {
-            float qnx, qvx, qny, qvy, qnz, qvz;
+        // n, V of slice j for the own point (z components returned) and halo
+        auto q_phase = [&](int j, float &qnz, float &qvz) {
+            float qnx, qvx, qny, qvy;
             qcalc(j, tx + 2, ty + 2, qnx, qvx, qny, qvy, qnz, qvz);
-            float *q = &sq[j & 1][0][0];
-            q[0 * QY * QX + own_q] = qnx;
-            q[1 * QY * QX + own_q] = qvx;
-            q[2 * QY * QX + own_q] = qny;
-            q[3 * QY * QX + own_q] = qvy;
-            nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = qnz; vzp = qvz;
+            float *q = &sq[(j + 2 * NQ) % NQ][0][0];
+            q[0 * QS + own_q] = qnx;
+            q[1 * QS + own_q] = qvx;
+            q[2 * QS + own_q] = qny;
+            q[3 * QS + own_q] = qvy;
             if (hq >= 0) {
                 float a0, a1, a2, a3, a4, a5;
                 qcalc(j, hq % QX + 1, hq / QX + 1, a0, a1, a2, a3, a4, a5);
-                q[0 * QY * QX + hq] = a0;
-                q[1 * QY * QX + hq] = a1;
-                q[2 * QY * QX + hq] = a2;
-                q[3 * QY * QX + hq] = a3;
+                q[0 * QS + hq] = a0;
+                q[1 * QS + hq] = a1;
+                q[2 * QS + hq] = a2;
+                q[3 * QS + hq] = a3;
             }
         };
 
         const int64_t col = (int64_t)min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
         const float cxy = ua.cx[min(zt.x, g.nx - 1)] * ua.cy[min(zt.y, g.ny - 1)];
-        store_phi(fetch_phi(zt.z0 - 2), zt.z0 - 2);
-        store_phi(fetch_phi(zt.z0 - 1), zt.z0 - 1);
-        for (int j = zt.z0 - 2; j < zt.z0; ++j) {
-            store_phi(fetch_phi(j + 2), j + 2);
-            __syncthreads();
-            q_phase(j + 1);
-            __syncthreads();
-        }
+        const int z0 = zt.z0;
+        // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
+#pragma unroll
+        for (int j = -2; j <= 2; ++j) store_phi(fetch_phi(z0 + j), z0 + j);
+        __syncthreads();
+        float nzm, vzm, nz0, vz0, nzp, vzp;
+        q_phase(z0 - 1, nzm, vzm);
+        q_phase(z0, nz0, vz0);
+        q_phase(z0 + 1, nzp, vzp);
 
         constexpr int W = 2 * R + 1;
         float ra[W], rb[W];
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
-            const int z = zt.z0 - R + j;
+            const int z = z0 - R + j;
             const bool ok = z >= 0 && z < g.nz;
             ra[j] = ok ? t1[col + (int64_t)z * g.sxy] : 0.f;
             rb[j] = ok ? t2[col + (int64_t)z * g.sxy] : 0.f;
         }
         __builtin_amdgcn_sched_barrier(0);
         // one-step-ahead prefetch of the next phi slice, conv inputs and image
-        PhiRaw phi_nxt = fetch_phi(zt.z0 + 2);
-        float t1_nxt = zt.z0 + R < g.nz ? t1[col + (int64_t)(zt.z0 + R) * g.sxy] : 0.f;
-        float t2_nxt = zt.z0 + R < g.nz ? t2[col + (int64_t)(zt.z0 + R) * g.sxy] : 0.f;
-        float I_nxt = ua.I[col + (int64_t)zt.z0 * g.sxy];
-        for (int zb = zt.z0; zb < zt.z1; zb += W) {
+        PhiRaw phi_nxt = fetch_phi(z0 + 3);
+        float t1_nxt = z0 + R < g.nz ? t1[col + (int64_t)(z0 + R) * g.sxy] : 0.f;
+        float t2_nxt = z0 + R < g.nz ? t2[col + (int64_t)(z0 + R) * g.sxy] : 0.f;
+        float I_nxt = z0 < zt.z1 ? ua.I[col + (int64_t)z0 * g.sxy] : 0.f;
+        for (int zb = z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
-                    store_phi(phi_nxt, z + 2);
+                    store_phi(phi_nxt, z + 3);
                     ra[(s + 2 * R) % W] = t1_nxt;
                     rb[(s + 2 * R) % W] = t2_nxt;
                     const float Iv = I_nxt;
-                    phi_nxt = fetch_phi(z + 3);
+                    phi_nxt = fetch_phi(z + 4);
                     const int zn = z + R + 1;
                     t1_nxt = zn < g.nz ? t1[col + (int64_t)zn * g.sxy] : 0.f;
                     t2_nxt = zn < g.nz ? t2[col + (int64_t)zn * g.sxy] : 0.f;
                     if (z + 1 < zt.z1) I_nxt = ua.I[col + (int64_t)(z + 1) * g.sxy];
                     __syncthreads();
-                    q_phase(z + 1);
-                    __syncthreads();
+                    float nzpp, vzpp;
+                    q_phase(z + 2, nzpp, vzpp);
                     float KG1 = 0.f, KG2 = 0.f;
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
@@ -486,20 +495,18 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
                     }
                     if (zt.active) {
                         const int64_t v = col + (int64_t)z * g.sxy;
-                        const float *p0 = sphi[(z + 2 * NSLOT) % NSLOT];
-                        const float *pm = sphi[(z - 1 + 2 * NSLOT) % NSLOT];
-                        const float *pp = sphi[(z + 1 + 2 * NSLOT) % NSLOT];
+                        const float *p0 = phi_slot(z), *pm = phi_slot(z - 1), *pp = phi_slot(z + 1);
                         const int c = (ty + 2) * PX + tx + 2;
                         const float cphi = p0[c];
                         const float lap = p0[c + 1] + p0[c - 1] + p0[c + PX] + p0[c - PX] +
                                           pp[c] + pm[c] - 6.f * cphi;
-                        const float *q = &sq[z & 1][0][0];
+                        const float *q = &sq[(z + 2 * NQ) % NQ][0][0];
                         const int o = own_q;
                         const float kappa = 0.5f * (q[o + 1] - q[o - 1]) +
-                                            0.5f * (q[2 * QY * QX + o + QX] - q[2 * QY * QX + o - QX]) +
+                                            0.5f * (q[2 * QS + o + QX] - q[2 * QS + o - QX]) +
                                             0.5f * (nzp - nzm);
-                        const float divV = 0.5f * (q[QY * QX + o + 1] - q[QY * QX + o - 1]) +
-                                           0.5f * (q[3 * QY * QX + o + QX] - q[3 * QY * QX + o - QX]) +
+                        const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
+                                           0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
                                            0.5f * (vzp - vzm);
                         const float K1 = cxy * ua.cz[z];
                         const float Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
@@ -517,6 +524,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
                             if (ua.probe_E) ua.probe_E[v] = E;
                         }
                     }
+                    nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }

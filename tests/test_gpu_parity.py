@@ -143,6 +143,24 @@ def test_evolve_odd_shape_many_iterations(rsf):
     assert dmax <= PHI_TOL and agree >= SIGN_AGREE
 
 
+@pytest.mark.parametrize("shape,sigma", [((3, 3, 3), 1.0), ((4, 5, 3), 1.5), ((3, 7, 66), 2.0),
+                                         ((5, 4, 130), 3.0), ((66, 3, 4), 1.0)])
+def test_evolve_tiny_and_thin_volumes(rsf, shape, sigma):
+    """Every axis at its minimum of 3 (or 4, 5) voxels, dims below R, and a
+    tile's worth plus a ragged tail along the long axis."""
+    mod, ctx = rsf
+    say(f"evolve tiny {shape} sigma={sigma}")
+    r = np.random.default_rng(17)
+    I = r.uniform(0, 1, size=shape).astype(np.float32)
+    phi0 = smooth(shape, 18)
+    w = inputs.Workload("tiny", shape, 1, 1.0, 1.0, seed=0, iters=5, sigma=sigma,
+                        lambda1=2.0, lambda2=2.0, nu=0.1)
+    got = run_gpu(ctx, I, phi0, w)
+    want, _ = oracle.evolve(I, phi0, oracle.params_array(**w.params(), eta=1e-10), w.iters)
+    dmax, agree = parity(got, want)
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE, (dmax, agree)
+
+
 def test_zero_iterations_is_a_no_op(rsf):
     mod, ctx = rsf
     say("iters=0")
