@@ -33,6 +33,7 @@ PASS_BYTES = {
     "z_update": 20,       # Kxy*g1, Kxy*g2, I, phi -> phi'
 }
 ITER_BYTES = sum(PASS_BYTES.values())   # 72 B per voxel-iteration
+COPY_BYTES = 1 << 30
 
 KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
                   "paper_2404_02813_amd/csrc/rsf_kernels.hpp",
@@ -61,6 +62,67 @@ def traffic_for(kernel: str, workload: str):
     if not rec or rec.get("source_sha") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+KERNEL_PASS = (("z_heaviside_kernel<", "z_heaviside"), ("xy_kernel<", None),
+               ("z_update_kernel<", "z_update"))
+
+
+def _pass_of(kernel_name: str):
+    """Map a device kernel name to its pass (xy mode 1 = force, 2 = fits)."""
+    import re
+    m = re.search(r"xy_kernel<\d+, (\d)>", kernel_name)
+    if m:
+        return {"1": "xy_force", "2": "xy_fits"}.get(m.group(1))
+    for key, name in KERNEL_PASS:
+        if key in kernel_name and "true" not in kernel_name.split(key, 1)[1][:12]:
+            return name
+    return None
+
+
+def ingest_counters(fetch_dir: str, write_dir: str, workload: str, copy_bytes: int) -> dict:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch) into HBM bytes per launch of each pass, each counter scaled by
+    what it reads for the plain device copy of `copy_bytes` in the same run,
+    and record them in profiles/traffic.json with the kernel source hash."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per, copies = {}, []
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0
+                if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"):
+                    copies.append(v)
+                    continue
+                name = _pass_of(r["Kernel_Name"])
+                if name:
+                    per.setdefault(name, []).append(v)
+        return per, copies
+
+    fetch, fcopy = load(fetch_dir, "FETCH_SIZE")
+    write, wcopy = load(write_dir, "WRITE_SIZE")
+    # the copy of known size: its counters land nearest to copy_bytes / factor
+    f_fac = max(fcopy) / copy_bytes
+    w_fac = max(wcopy) / copy_bytes
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    sha = kernel_source_hash()
+    for name in sorted(set(fetch) & set(write)):
+        fb = sum(fetch[name]) / len(fetch[name]) / f_fac
+        wb = sum(write[name]) / len(write[name]) / w_fac
+        data[f"{name}@{workload}"] = {
+            "source_sha": sha, "bytes_per_launch": round(fb + wb),
+            "fetch_bytes": round(fb), "write_bytes": round(wb),
+            "fetch_factor": round(f_fac, 4), "write_factor": round(w_fac, 4),
+            "dispatches": len(fetch[name])}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    return data
 
 
 def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0):
@@ -98,7 +160,14 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--iters", type=int, default=0,
                     help="override the workload's iteration count (profiling runs)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="record rocprofv3 FETCH_SIZE / WRITE_SIZE runs in profiles/traffic.json")
     args = ap.parse_args()
+
+    if args.ingest_counters:
+        data = ingest_counters(*args.ingest_counters, args.workload, COPY_BYTES)
+        print(json.dumps(data, indent=1))
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -137,8 +206,9 @@ def main() -> int:
         ph.copy_(phi0)
     torch.cuda.synchronize()
 
-    # HBM copy bandwidth of a plain device copy, for context.
-    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    # HBM copy bandwidth of a plain device copy, for context (and the known-size
+    # copy the rocprofv3 counter runs are calibrated against).
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()

@@ -80,16 +80,20 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
     };
     auto fetch = [&](int y) {
         Raw r;
+        // uniform row bases, 32-bit lane offsets
+        const int yy = min(max(y, 0), g.ny - 1);
+        const float *ra = a + zb + (int64_t)yy * g.nx;
+        const float *rb = NF == 2 ? b + zb + (int64_t)yy * g.nx : nullptr;
+        const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             r.a[h] = 0.f;
             r.b[h] = 0.f;
             const int j = lane + 64 * h;
             const int gx = x0 - R + j;
-            if (j < RW && y >= 0 && y < g.ny && gx >= 0 && gx < g.nx) {
-                const int64_t i = zb + (int64_t)y * g.nx + gx;
-                r.a[h] = a[i];
-                if (NF == 2) r.b[h] = b[i];
+            if (yok && j < RW && gx >= 0 && gx < g.nx) {
+                r.a[h] = ra[gx];
+                if (NF == 2) r.b[h] = rb[gx];
             }
         }
         return r;
@@ -129,8 +133,12 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
     }
     float cxz = 0.f;
     const int xc = min(x, g.nx - 1);
+    const float *ki_slice = MODE == XY_FITS ? fa.KI + zb : nullptr;
     if (MODE == XY_FITS) cxz = fa.cx[xc] * fa.cz[z];
-    float ki_next = MODE == XY_FITS ? fa.KI[zb + (int64_t)y0 * g.nx + xc] : 0.f;
+    float ki_next = MODE == XY_FITS ? ki_slice[y0 * g.nx + xc] : 0.f;
+    float cy_next = MODE == XY_FITS ? fa.cy[y0] : 0.f;
+    float *oa_s = oa + zb;
+    float *ob_s = NF == 2 ? ob + zb : nullptr;
     for (int yb = y0; yb < y1; yb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -138,10 +146,14 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
             if (y < y1) {
                 const Raw cur = nxt;
                 nxt = fetch(y + R + 1);
-                float ki = 0.f;
+                float ki = 0.f, cyv = 0.f;
                 if (MODE == XY_FITS) {
                     ki = ki_next;
-                    if (y + 1 < y1) ki_next = fa.KI[zb + (int64_t)(y + 1) * g.nx + xc];
+                    cyv = cy_next;
+                    if (y + 1 < y1) {
+                        ki_next = ki_slice[(y + 1) * g.nx + xc];
+                        cy_next = fa.cy[y + 1];
+                    }
                 }
                 // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
                 const float2 v = xrow(cur, (y - y0) & 1);
@@ -154,21 +166,21 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
                     if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % W], acc_b);
                 }
                 if (x < g.nx) {
-                    const int64_t v = zb + (int64_t)y * g.nx + x;
+                    const int v = y * g.nx + x;      // offset within the slice
                     if (MODE == XY_FITS) {
                         // region fits (Sec. 3 local_intensity), force-convolution inputs
-                        const float K1 = cxz * fa.cy[y];
+                        const float K1 = cxz * cyv;
                         const float A2 = ki - acc_a;
                         const float B2 = K1 - acc_b;
                         const float f1 = acc_a * rcp(acc_b);
                         const float f2 = A2 * rcp(B2);
-                        oa[v] = fa.l1 * f1 - fa.l2 * f2;
-                        ob[v] = fa.l1 * f1 * f1 - fa.l2 * f2 * f2;
-                        if (fa.probe_f1) fa.probe_f1[v] = f1;
-                        if (fa.probe_f2) fa.probe_f2[v] = f2;
+                        oa_s[v] = fa.l1 * f1 - fa.l2 * f2;
+                        ob_s[v] = fa.l1 * f1 * f1 - fa.l2 * f2 * f2;
+                        if (fa.probe_f1) fa.probe_f1[zb + v] = f1;
+                        if (fa.probe_f2) fa.probe_f2[zb + v] = f2;
                     } else {
-                        oa[v] = acc_a;
-                        if (NF == 2) ob[v] = acc_b;
+                        oa_s[v] = acc_a;
+                        if (NF == 2) ob_s[v] = acc_b;
                     }
                 }
             }
@@ -268,12 +280,12 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(const float *__restri
 {
     const ZTile zt = z_tile(g, nzc);
     if (!zt.active) return;
-    const int64_t col = (int64_t)zt.y * g.nx + zt.x;
+    const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
-        [&](int z) { return make_float2(in[col + (int64_t)z * g.sxy], 0.f); },
+        [&](int z) { return make_float2((in + (int64_t)z * g.sxy)[col], 0.f); },
         [&](float2 raw, int) { return raw; },
-        [&](int z, float va, float) { out[col + (int64_t)z * g.sxy] = va; });
+        [&](int z, float va, float) { (out + (int64_t)z * g.sxy)[col] = va; });
 }
 
 // Stage-1 z pass: H_eps(phi) and H I formed as slices enter the ring.
@@ -286,22 +298,22 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
     if (done && *done) return;
     const ZTile zt = z_tile(g, nzc);
     if (!zt.active) return;
-    const int64_t col = (int64_t)zt.y * g.nx + zt.x;
+    const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
     z_march<R, 2>(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
-            const int64_t v = col + (int64_t)z * g.sxy;
-            return make_float2(phi[v], I[v]);
+            const int64_t zo = (int64_t)z * g.sxy;
+            return make_float2((phi + zo)[col], (I + zo)[col]);
         },
         [&](float2 raw, int z) {
             const float H = heaviside(raw.x, eps);
-            if (PROBE && probeH) probeH[col + (int64_t)z * g.sxy] = H;
+            if (PROBE && probeH) (probeH + (int64_t)z * g.sxy)[col] = H;
             return make_float2(H * raw.y, H);
         },
         [&](int z, float va, float vb) {
-            const int64_t v = col + (int64_t)z * g.sxy;
-            t1[v] = va;
-            t2[v] = vb;
+            const int64_t zo = (int64_t)z * g.sxy;
+            (t1 + zo)[col] = va;
+            (t2 + zo)[col] = vb;
         });
 }
 
@@ -368,9 +380,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
 
     if (stopped) {
         if (zt.active) {
-            const int64_t col = (int64_t)zt.y * g.nx + zt.x;
+            const int col = zt.y * g.nx + zt.x;
             for (int z = zt.z0; z < zt.z1; ++z)
-                ua.phi_out[col + (int64_t)z * g.sxy] = phi[col + (int64_t)z * g.sxy];
+                (ua.phi_out + (int64_t)z * g.sxy)[col] = (phi + (int64_t)z * g.sxy)[col];
         }
     } else {
         // phi tile loads: reflected in-slice offsets of this thread's points
@@ -443,8 +455,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
             }
         };
 
-        const int64_t col = (int64_t)min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
+        const int col = min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
         const float cxy = ua.cx[min(zt.x, g.nx - 1)] * ua.cy[min(zt.y, g.ny - 1)];
+        auto at = [&](const float *base, int z) { return (base + (int64_t)z * g.sxy)[col]; };
         const int z0 = zt.z0;
         // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
 #pragma unroll
@@ -461,15 +474,15 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
         for (int j = 0; j < 2 * R; ++j) {
             const int z = z0 - R + j;
             const bool ok = z >= 0 && z < g.nz;
-            ra[j] = ok ? t1[col + (int64_t)z * g.sxy] : 0.f;
-            rb[j] = ok ? t2[col + (int64_t)z * g.sxy] : 0.f;
+            ra[j] = ok ? at(t1, z) : 0.f;
+            rb[j] = ok ? at(t2, z) : 0.f;
         }
         __builtin_amdgcn_sched_barrier(0);
         // one-step-ahead prefetch of the next phi slice, conv inputs and image
         PhiRaw phi_nxt = fetch_phi(z0 + 3);
-        float t1_nxt = z0 + R < g.nz ? t1[col + (int64_t)(z0 + R) * g.sxy] : 0.f;
-        float t2_nxt = z0 + R < g.nz ? t2[col + (int64_t)(z0 + R) * g.sxy] : 0.f;
-        float I_nxt = z0 < zt.z1 ? ua.I[col + (int64_t)z0 * g.sxy] : 0.f;
+        float t1_nxt = z0 + R < g.nz ? at(t1, z0 + R) : 0.f;
+        float t2_nxt = z0 + R < g.nz ? at(t2, z0 + R) : 0.f;
+        float I_nxt = z0 < zt.z1 ? at(ua.I, z0) : 0.f;
         for (int zb = z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
@@ -481,9 +494,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
                     const float Iv = I_nxt;
                     phi_nxt = fetch_phi(z + 4);
                     const int zn = z + R + 1;
-                    t1_nxt = zn < g.nz ? t1[col + (int64_t)zn * g.sxy] : 0.f;
-                    t2_nxt = zn < g.nz ? t2[col + (int64_t)zn * g.sxy] : 0.f;
-                    if (z + 1 < zt.z1) I_nxt = ua.I[col + (int64_t)(z + 1) * g.sxy];
+                    t1_nxt = zn < g.nz ? at(t1, zn) : 0.f;
+                    t2_nxt = zn < g.nz ? at(t2, zn) : 0.f;
+                    if (z + 1 < zt.z1) I_nxt = at(ua.I, z + 1);
                     __syncthreads();
                     float nzpp, vzpp;
                     q_phase(z + 2, nzpp, vzpp);
@@ -494,7 +507,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
                         KG2 = fmaf(t.w[k], rb[(s + k) % W], KG2);
                     }
                     if (zt.active) {
-                        const int64_t v = col + (int64_t)z * g.sxy;
+                        const int64_t zo = (int64_t)z * g.sxy;
                         const float *p0 = phi_slot(z), *pm = phi_slot(z - 1), *pp = phi_slot(z + 1);
                         const int c = (ty + 2) * PX + tx + 2;
                         const float cphi = p0[c];
@@ -514,14 +527,14 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
                         const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                         const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
                         const float nxt = cphi + ua.dt * E;
-                        ua.phi_out[v] = nxt;
+                        (ua.phi_out + zo)[col] = nxt;
                         acc += fabs((double)nxt - (double)cphi);
                         if (PROBE) {
-                            if (ua.probe_Fd) ua.probe_Fd[v] = Fd;
-                            if (ua.probe_kappa) ua.probe_kappa[v] = kappa;
-                            if (ua.probe_lap) ua.probe_lap[v] = lap;
-                            if (ua.probe_R) ua.probe_R[v] = Rt;
-                            if (ua.probe_E) ua.probe_E[v] = E;
+                            if (ua.probe_Fd) (ua.probe_Fd + zo)[col] = Fd;
+                            if (ua.probe_kappa) (ua.probe_kappa + zo)[col] = kappa;
+                            if (ua.probe_lap) (ua.probe_lap + zo)[col] = lap;
+                            if (ua.probe_R) (ua.probe_R + zo)[col] = Rt;
+                            if (ua.probe_E) (ua.probe_E + zo)[col] = E;
                         }
                     }
                     nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
