@@ -24,16 +24,35 @@ sys.path.insert(0, ROOT)
 METRIC = "Gvoxel-iter/s at 512^3 sigma=3 (% HBM peak); p50/p99 tile latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
-# Algorithmic HBM bytes per voxel for one launch of each pass (FP32 fields):
-# reads + writes that the pass must make, each field once.
-PASS_BYTES = {
-    "z_heaviside": 16,    # phi, I -> Kz*(HI), Kz*H
-    "xy_fits": 20,        # Kz*(HI), Kz*H, K*I -> g1, g2
-    "xy_force": 16,       # g1, g2 -> Kxy*g1, Kxy*g2
-    "z_update": 20,       # Kxy*g1, Kxy*g2, I, phi -> phi'
-}
+def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4) -> dict:
+    """Algorithmic HBM bytes per voxel for one launch of each pass: the reads
+    and writes the pass must make, each field once (phi is always FP32)."""
+    i, s = image_bytes, storage_bytes
+    return {
+        "z_heaviside": 4 + i + 2 * s,   # phi, I -> Kz*(HI), Kz*H
+        "xy_fits": 5 * s,               # Kz*(HI), Kz*H, K*I -> g1, g2
+        "xy_force": 4 * s,              # g1, g2 -> Kxy*g1, Kxy*g2
+        "z_update": 8 + i + 2 * s,      # Kxy*g1, Kxy*g2, I, phi -> phi'
+    }
+
+
+PASS_BYTES = pass_bytes()               # FP32 image and fields
 ITER_BYTES = sum(PASS_BYTES.values())   # 72 B per voxel-iteration
 COPY_BYTES = 1 << 30
+
+# name -> (workload, image dtype, storage dtype)
+def workloads():
+    from paper_2404_02813_amd import inputs
+    big = inputs.Workload("mixed1024x1024x512_s4_it150", (512, 1024, 1024), 1500, 1.0, 4.0,
+                          seed=4, iters=150, sigma=4.0)
+    return {
+        inputs.LARGE_512.name: (inputs.LARGE_512, "f32", "f32"),
+        inputs.SMALL_64.name: (inputs.SMALL_64, "f32", "f32"),
+        inputs.LARGE_512.name + "_f16": (inputs.LARGE_512, "f32", "f16"),
+        big.name + "_u16_f16": (big, "u16", "f16"),
+        big.name + "_u16_bf16": (big, "u16", "bf16"),
+        big.name + "_u16_f32": (big, "u16", "f32"),
+    }
 
 KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
                   "paper_2404_02813_amd/csrc/rsf_kernels.hpp",
@@ -182,26 +201,30 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
-    workloads = {w.name: w for w in (inputs.SMALL_64, inputs.LARGE_512)}
-    w = workloads[args.workload]
+    w, image_t, storage_t = workloads()[args.workload]
     if args.iters > 0:
         import dataclasses
         w = dataclasses.replace(w, iters=args.iters)
     K, W = max(1, args.steps), max(0, args.warmup)
+    pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2)
 
     t_gen = time.perf_counter()
-    I_host, phi0_host = w.image(), w.phi0()
+    if image_t == "u16":
+        I_host = inputs.u16_phantom(w.shape, w.n_tubes, w.r_min, w.r_max, w.seed)
+    else:
+        I_host = w.image()
+    phi0_host = w.phi0()
     vol = torch.from_numpy(I_host).cuda()
     phi0 = torch.from_numpy(phi0_host).cuda()
     t_gen = time.perf_counter() - t_gen
+    params = rsf.make_params(**w.params(), storage=storage_t)
     phis = [torch.empty_like(phi0) for _ in range(K)]
     ctx = rsf.Context(0)
     scratch = torch.empty_like(phi0)
-    p = w.params()
 
     for _ in range(W):
         scratch.copy_(phi0)
-        ctx.evolve(vol, scratch, w.iters, **p)
+        ctx.evolve_ex(vol, scratch, params, w.iters)
     for ph in phis:
         ph.copy_(phi0)
     torch.cuda.synchronize()
@@ -225,7 +248,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ph in phis:
-        ctx.evolve(vol, ph, w.iters, **p)
+        ctx.evolve_ex(vol, ph, params, w.iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
@@ -236,12 +259,13 @@ def main() -> int:
     elapsed = t1 - t0
     vox = w.voxels
     value = vox * w.iters * K / elapsed / 1e9
-    hot = {k: v for k, v in prof.items() if k in PASS_BYTES}
+    hot = {k: v for k, v in prof.items() if k in pb}
     dom = max(hot, key=lambda k: hot[k][1])
     launches, total_ms = hot[dom]
     avg_s = total_ms / launches * 1e-3
-    achieved = PASS_BYTES[dom] * vox / avg_s / 1e9
-    traffic = traffic_for(dom, w.name)
+    achieved = pb[dom] * vox / avg_s / 1e9
+    traffic = traffic_for(dom, args.workload)
+    iter_bytes = sum(pb.values())
 
     out = {
         "metric": METRIC,
@@ -256,16 +280,17 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "shape_zyx": list(w.shape), "sigma": w.sigma,
+        "config": {"workload": args.workload, "shape_zyx": list(w.shape), "sigma": w.sigma,
+                   "image": image_t, "storage": storage_t,
                    "iters": w.iters, "n_tubes": w.n_tubes, "lambda1": w.lambda1,
                    "lambda2": w.lambda2, "nu": w.nu, "mu": w.mu, "dt": w.dt, "eps": w.eps,
                    "regulariser": "double_well", "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_voxel": PASS_BYTES[dom],
+                     "traffic": traffic, "bytes_per_voxel": pb[dom],
                      "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches},
-        "hbm_frac_path": round(value * ITER_BYTES / HBM_PEAK_GBS, 4),
-        "path_bytes_per_voxel_iter": ITER_BYTES,
+        "hbm_frac_path": round(value * iter_bytes / HBM_PEAK_GBS, 4),
+        "path_bytes_per_voxel_iter": iter_bytes,
         "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "copy_gbs": round(copy_gbs, 1),
         "iters_run": iters_run,
@@ -276,7 +301,8 @@ def main() -> int:
     del phis, vol, phi0, scratch
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, I_host, phi0_host, args.cpu_seconds)
+        img = I_host.astype("float64") / 65535.0 if image_t == "u16" else I_host
+        out["cpu_baseline"] = cpu_baseline(w, img, phi0_host, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 

@@ -53,9 +53,16 @@ typedef enum {
     RSF_ERR_INTERNAL = -6
 } rsf_status;
 
-/* Element type of the input image. */
+/* Element types.  The image may be RSF_F32 or RSF_U16 (normalised on the
+ * device to u / 65535); the intermediate fields (the convolved fields and
+ * K*I) may be stored as RSF_F32, RSF_F16 or RSF_BF16.  Arithmetic and phi
+ * are always FP32; the convergence sums FP64.  Combinations other than
+ * (F32 image, F32 storage) are built for ceil(3 sigma) in 4..12. */
 typedef enum {
-    RSF_F32 = 0
+    RSF_F32 = 0,
+    RSF_F16 = 1,
+    RSF_BF16 = 2,
+    RSF_U16 = 3
 } rsf_dtype;
 
 /* Distance-regulariser reading (Sec. 2.1).  The paper names "forward and
@@ -83,6 +90,7 @@ typedef struct {
     float eps;        /* Heaviside / Dirac width, > 0                         */
     float eta;        /* floor inside |grad phi| of the normal; <= 0 -> 1e-10 */
     int regulariser;  /* rsf_regulariser                                      */
+    int storage;      /* rsf_dtype of the intermediate fields (F32/F16/BF16)  */
 } rsf_params;
 
 /* Results of the last evolution on a context. */
@@ -104,12 +112,15 @@ void rsf_destroy(rsf_context *ctx);
 const char *rsf_last_error(const rsf_context *ctx);
 
 /* Bytes of device workspace an evolution of an nx*ny*nz volume over `iters`
- * iterations needs (six float fields plus small tables). */
-size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters);
+ * iterations needs with intermediate fields of type `storage`: five fields of
+ * that type, one float field, small tables (24 B/voxel at RSF_F32, 14 B/voxel
+ * at RSF_F16/RSF_BF16).  0 for invalid arguments. */
+size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters, int storage);
 
 /* Evolve phi in place for `iters` iterations of Eq. (1) with the default
- * (double-well) regulariser and eta = 1e-10.
- *   volume : device, const, nx*ny*nz elements of `volume_dtype` (the image I)
+ * (double-well) regulariser, eta = 1e-10 and FP32 storage.
+ *   volume : device, const, nx*ny*nz elements of `volume_dtype` (RSF_F32 or
+ *            RSF_U16; the image I)
  *   phi    : device, nx*ny*nz floats; phi_0 on entry, phi_iters on return
  *   nx,ny,nz >= 3; sigma > 0 with ceil(3 sigma) <= 16; eps > 0; dt > 0;
  *   nu, mu >= 0; lambda1, lambda2 finite; iters >= 0 (0 is a no-op).

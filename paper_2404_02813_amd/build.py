@@ -17,8 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsf.so")
-SOURCES = ["rsf_kernels.hip", "rsf_api.hip", "rsf_inst_a.hip", "rsf_inst_b.hip",
-           "rsf_inst_c.hip", "rsf_inst_d.hip"]
+SOURCES = ["rsf_kernels.hip", "rsf_api.hip"] + sorted(
+    f for f in os.listdir(CSRC) if f.startswith("rsf_inst_") and f.endswith(".hip"))
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -40,7 +40,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]

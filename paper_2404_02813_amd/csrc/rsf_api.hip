@@ -44,25 +44,31 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// P, Q: interleaved pairs of the storage type (the stage-1 z-convolved
+// fields, then alternately g1/g2 and their xy convolutions); KI: K*I.
 struct Layout {
-    size_t T1, T2, G1, G2, KI, phiB, cx, cy, cz, partials, hist, flags, total;
+    size_t P, Q, KI, phiB, cx, cy, cz, partials, hist, flags, total;
 };
 
-Layout layout(int64_t nx, int64_t ny, int64_t nz, int iters)
+size_t elem_size(int dtype) { return dtype == RSF_F32 ? 4 : 2; }
+
+// Two pair fields and K*I in the storage type, the phi ping-pong buffer in
+// float, plus edge tables, partial sums, history and flags.
+Layout layout(int64_t nx, int64_t ny, int64_t nz, int iters, int storage)
 {
     Layout L{};
-    const size_t field = align_up((size_t)nx * ny * nz * sizeof(float));
+    const size_t n = (size_t)nx * ny * nz;
+    const size_t field = align_up(n * elem_size(storage));
+    const size_t pair = align_up(2 * n * elem_size(storage));
     size_t off = 0;
-    L.T1 = off; off += field;
-    L.T2 = off; off += field;
-    L.G1 = off; off += field;
-    L.G2 = off; off += field;
+    L.P = off; off += pair;
+    L.Q = off; off += pair;
     L.KI = off; off += field;
-    L.phiB = off; off += field;
+    L.phiB = off; off += align_up(n * sizeof(float));
     L.cx = off; off += align_up((size_t)nx * sizeof(float));
     L.cy = off; off += align_up((size_t)ny * sizeof(float));
     L.cz = off; off += align_up((size_t)nz * sizeof(float));
-    Grid3 g{(int)nx, (int)ny, (int)nz, nx * ny};
+    rsf::Grid3 g{(int)nx, (int)ny, (int)nz, nx * ny};
     L.partials = off; off += align_up((size_t)rsf::u_blocks(g) * sizeof(double));
     L.hist = off; off += align_up((size_t)(iters > 0 ? iters : 1) * sizeof(double));
     L.flags = off; off += align_up(4 * sizeof(int));
@@ -154,6 +160,18 @@ rsf_status check_params(rsf_context *ctx, const rsf_params &p)
     if (p.nu < 0.f || p.mu < 0.f) return fail(ctx, RSF_ERR_INVALID_ARG, "nu and mu must be >= 0");
     if (p.regulariser != RSF_REG_DOUBLE_WELL && p.regulariser != RSF_REG_SINGLE_WELL)
         return fail(ctx, RSF_ERR_INVALID_ARG, "unknown regulariser");
+    if (p.storage != RSF_F32 && p.storage != RSF_F16 && p.storage != RSF_BF16)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "storage must be RSF_F32, RSF_F16 or RSF_BF16");
+    return RSF_OK;
+}
+
+rsf_status check_types(rsf_context *ctx, float sigma, int image, int storage)
+{
+    if (image != RSF_F32 && image != RSF_U16)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "volume dtype must be RSF_F32 or RSF_U16");
+    if (!rsf::types_supported(radius_of(sigma), image, storage))
+        return fail(ctx, RSF_ERR_INVALID_ARG,
+                    "this image/storage combination is built for ceil(3 sigma) in 4..12 only");
     return RSF_OK;
 }
 
@@ -184,25 +202,31 @@ rsf_status ensure_ws(rsf_context *ctx, size_t bytes)
 struct Plan {
     Grid3 g;
     int R;
+    int image, storage;
     Taps taps;
     Layout L;
     char *base;
-    float *T1, *T2, *G1, *G2, *KI, *phiB, *cx, *cy, *cz;
+    void *P, *Q, *KI;
+    float *phiB, *cx, *cy, *cz;
     double *partials, *hist;
     int *flags;
 };
 
-Plan make_plan(int64_t nx, int64_t ny, int64_t nz, float sigma, int iters, char *base)
+Plan make_plan(int64_t nx, int64_t ny, int64_t nz, float sigma, int iters, int image, int storage,
+               char *base)
 {
     Plan P{};
     P.g = Grid3{(int)nx, (int)ny, (int)nz, nx * ny};
     P.R = radius_of(sigma);
+    P.image = image;
+    P.storage = storage;
     P.taps = make_taps(sigma, P.R);
-    P.L = layout(nx, ny, nz, iters);
+    P.L = layout(nx, ny, nz, iters, storage);
     P.base = base;
     auto F = [&](size_t off) { return reinterpret_cast<float *>(base + off); };
-    P.T1 = F(P.L.T1); P.T2 = F(P.L.T2); P.G1 = F(P.L.G1); P.G2 = F(P.L.G2);
-    P.KI = F(P.L.KI); P.phiB = F(P.L.phiB);
+    auto V = [&](size_t off) { return static_cast<void *>(base + off); };
+    P.P = V(P.L.P); P.Q = V(P.L.Q);
+    P.KI = V(P.L.KI); P.phiB = F(P.L.phiB);
     P.cx = F(P.L.cx); P.cy = F(P.L.cy); P.cz = F(P.L.cz);
     P.partials = reinterpret_cast<double *>(base + P.L.partials);
     P.hist = reinterpret_cast<double *>(base + P.L.hist);
@@ -211,15 +235,16 @@ Plan make_plan(int64_t nx, int64_t ny, int64_t nz, float sigma, int iters, char 
 }
 
 // Per-volume set-up: edge tables of K*1, flags, and K*I.
-rsf_status prologue(rsf_context *ctx, const Plan &P, const float *I, hipStream_t s)
+rsf_status prologue(rsf_context *ctx, const Plan &P, const void *I, hipStream_t s)
 {
     HIP_TRY(timed(ctx, RSF_PASS_SETUP, s, [&] {
                 hipError_t e = rsf::launch_flags_init(P.flags, s);
                 if (e == hipSuccess) e = rsf::launch_edges(P.cx, P.cy, P.cz, P.g, P.taps, P.R, s);
                 if (e == hipSuccess)
-                    e = rsf::launch_xy(P.R, rsf::XY_ONE, I, nullptr, P.T1, nullptr, P.g, P.taps,
+                    e = rsf::launch_xy(P.R, rsf::XY_ONE, P.image, P.storage, I, P.P, P.g, P.taps,
                                        nullptr, nullptr, s);
-                if (e == hipSuccess) e = rsf::launch_z_plain(P.R, P.T1, P.KI, P.g, P.taps, s);
+                if (e == hipSuccess)
+                    e = rsf::launch_z_plain(P.R, P.storage, P.P, P.KI, P.g, P.taps, s);
                 return e;
             }),
             "setup (K*1 tables, K*I)");
@@ -232,25 +257,25 @@ struct Probe {
 };
 
 // One iteration phi_cur -> phi_nxt; its sum |dphi| goes to hist_slot.
-rsf_status iteration(rsf_context *ctx, const Plan &P, const float *I, const float *cur,
+rsf_status iteration(rsf_context *ctx, const Plan &P, const void *I, const float *cur,
                      float *nxt, const rsf_params &p, double *hist_slot, double tol_total,
                      const Probe &pr, hipStream_t s)
 {
     const int *done = P.flags;
     HIP_TRY(timed(ctx, RSF_PASS_Z_HEAVISIDE, s, [&] {
-                return rsf::launch_z_heaviside(P.R, cur, I, P.T1, P.T2, P.g, P.taps, p.eps, pr.H,
-                                               done, s);
+                return rsf::launch_z_heaviside(P.R, P.image, P.storage, cur, I, P.P, P.g, P.taps,
+                                               p.eps, pr.H, done, s);
             }),
             "z(H)");
     rsf::FitArgs fa{P.KI, P.cx, P.cy, P.cz, p.lambda1, p.lambda2, pr.f1, pr.f2};
     HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_FITS, P.T1, P.T2, P.G1, P.G2, P.g, P.taps, &fa,
-                                      done, s);
+                return rsf::launch_xy(P.R, rsf::XY_FITS, P.image, P.storage, P.P, P.Q, P.g,
+                                      P.taps, &fa, done, s);
             }),
             "xy(fits)");
     HIP_TRY(timed(ctx, RSF_PASS_XY_FORCE, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_TWO, P.G1, P.G2, P.T1, P.T2, P.g, P.taps,
-                                      nullptr, done, s);
+                return rsf::launch_xy(P.R, rsf::XY_TWO, P.image, P.storage, P.Q, P.P, P.g,
+                                      P.taps, nullptr, done, s);
             }),
             "xy(g)");
     rsf::UpdArgs ua{};
@@ -267,7 +292,10 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, const float *I, const floa
     ua.probe_Fd = pr.Fd; ua.probe_kappa = pr.kappa; ua.probe_lap = pr.lap;
     ua.probe_R = pr.R; ua.probe_E = pr.E;
     HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s,
-                  [&] { return rsf::launch_z_update(P.R, P.T1, P.T2, P.g, P.taps, ua, done, s); }),
+                  [&] {
+                      return rsf::launch_z_update(P.R, P.image, P.storage, P.P, P.g, P.taps, ua,
+                                                  done, s);
+                  }),
             "z(update)");
     HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] {
                 return rsf::launch_reduce(P.partials, rsf::u_blocks(P.g), hist_slot, P.flags,
@@ -284,14 +312,15 @@ rsf_status evolve_impl(rsf_context *ctx, const void *volume, int vdt, float *phi
     if (!ctx) return RSF_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!volume || !phi) return fail(ctx, RSF_ERR_INVALID_ARG, "null volume or phi");
-    if (vdt != RSF_F32) return fail(ctx, RSF_ERR_INVALID_ARG, "unsupported volume dtype");
     rsf_status st = check_dims(ctx, nx, ny, nz);
     if (st != RSF_OK) return st;
     st = check_params(ctx, p);
     if (st != RSF_OK) return st;
+    st = check_types(ctx, p.sigma, vdt, p.storage);
+    if (st != RSF_OK) return st;
     if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ctx, RSF_ERR_INVALID_ARG, "tol must be >= 0");
-    const Layout L = layout(nx, ny, nz, iters);
+    const Layout L = layout(nx, ny, nz, iters, p.storage);
     if (workspace && ws_bytes < L.total)
         return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
@@ -304,8 +333,8 @@ rsf_status evolve_impl(rsf_context *ctx, const void *volume, int vdt, float *phi
     }
     char *base = static_cast<char *>(workspace ? workspace : ctx->ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Plan P = make_plan(nx, ny, nz, p.sigma, iters, base);
-    const float *I = static_cast<const float *>(volume);
+    const Plan P = make_plan(nx, ny, nz, p.sigma, iters, vdt, p.storage, base);
+    const void *I = volume;
 
     st = prologue(ctx, P, I, s);
     if (st != RSF_OK) return st;
@@ -335,7 +364,7 @@ rsf_params default_params(float sigma, float l1, float l2, float nu, float mu, f
 {
     rsf_params p{};
     p.sigma = sigma; p.lambda1 = l1; p.lambda2 = l2; p.nu = nu; p.mu = mu; p.dt = dt;
-    p.eps = eps; p.eta = 1e-10f; p.regulariser = RSF_REG_DOUBLE_WELL;
+    p.eps = eps; p.eta = 1e-10f; p.regulariser = RSF_REG_DOUBLE_WELL; p.storage = RSF_F32;
     return p;
 }
 
@@ -411,10 +440,11 @@ const char *rsf_last_error(const rsf_context *ctx)
     return ctx->err.c_str();
 }
 
-size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters)
+size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters, int storage)
 {
     if (nx < 1 || ny < 1 || nz < 1) return 0;
-    return layout(nx, ny, nz, iters).total;
+    if (storage != RSF_F32 && storage != RSF_F16 && storage != RSF_BF16) return 0;
+    return layout(nx, ny, nz, iters, storage).total;
 }
 
 rsf_status rsf_evolve(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
@@ -503,10 +533,10 @@ rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx
         const Taps t = make_taps(sigma, R);
         float *tmp = static_cast<float *>(ctx->ws);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        HIP_TRY(rsf::launch_xy(R, rsf::XY_ONE, in, nullptr, tmp, nullptr, g, t, nullptr, nullptr,
+        HIP_TRY(rsf::launch_xy(R, rsf::XY_ONE, RSF_F32, RSF_F32, in, tmp, g, t, nullptr, nullptr,
                                s),
                 "xy");
-        HIP_TRY(rsf::launch_z_plain(R, tmp, out, g, t, s), "z");
+        HIP_TRY(rsf::launch_z_plain(R, RSF_F32, tmp, out, g, t, s), "z");
         return RSF_OK;
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
@@ -522,19 +552,21 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
         ctx->err.clear();
         if (!volume || !phi || !params || !fields)
             return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
-        if (volume_dtype != RSF_F32) return fail(ctx, RSF_ERR_INVALID_ARG, "unsupported volume dtype");
         rsf_status st = check_dims(ctx, nx, ny, nz);
         if (st != RSF_OK) return st;
         st = check_params(ctx, *params);
         if (st != RSF_OK) return st;
+        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        if (st != RSF_OK) return st;
         st = set_device(ctx);
         if (st != RSF_OK) return st;
-        const Layout L = layout(nx, ny, nz, 1);
+        const Layout L = layout(nx, ny, nz, 1, params->storage);
         st = ensure_ws(ctx, L.total);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const Plan P = make_plan(nx, ny, nz, params->sigma, 1, static_cast<char *>(ctx->ws));
-        const float *I = static_cast<const float *>(volume);
+        const Plan P = make_plan(nx, ny, nz, params->sigma, 1, volume_dtype, params->storage,
+                                 static_cast<char *>(ctx->ws));
+        const void *I = volume;
         st = prologue(ctx, P, I, s);
         if (st != RSF_OK) return st;
         Probe pr;

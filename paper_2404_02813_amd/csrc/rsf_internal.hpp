@@ -30,7 +30,7 @@ struct Grid3 {
 // Epilogue of the stage-1 xy pass: region fits and the two force-convolution
 // inputs g1 = l1 f1 - l2 f2, g2 = l1 f1^2 - l2 f2^2.
 struct FitArgs {
-    const float *KI;              // K * I
+    const void *KI;               // K * I, in the storage type
     const float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
     float l1, l2;
     float *probe_f1, *probe_f2;   // optional
@@ -38,7 +38,7 @@ struct FitArgs {
 
 // Epilogue of the stage-2 z pass: force, curvature, regulariser, update.
 struct UpdArgs {
-    const float *I;               // image
+    const void *I;                // image, in the image type
     const float *phi;             // phi_n
     float *phi_out;               // phi_{n+1}
     const float *cx, *cy, *cz;
@@ -63,34 +63,46 @@ hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t,
                         hipStream_t s);
 hipError_t launch_flags_init(int *flags, hipStream_t s);
 
+// Element types (values of rsf_dtype): image RSF_F32 or RSF_U16, storage of
+// the intermediate fields RSF_F32, RSF_F16 or RSF_BF16.  Combinations other
+// than (F32, F32) are built for radii kMinRMixed..kMaxRMixed.
+constexpr int kMinRMixed = 4;
+constexpr int kMaxRMixed = 12;
+bool types_supported(int R, int image_dtype, int storage_dtype);
+
 // xy pass modes: one field; two fields; two fields + region-fit epilogue.
 enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2 };
-hipError_t launch_xy(int R, int mode, const float *a, const float *b, float *oa, float *ob,
-                     Grid3 g, const Taps &t, const FitArgs *fa, const int *done, hipStream_t s);
-
-hipError_t launch_z_plain(int R, const float *in, float *out, Grid3 g, const Taps &t,
-                          hipStream_t s);
-// Stage-1 z pass: (phi, I) -> Kz*(H I), Kz*H.
-hipError_t launch_z_heaviside(int R, const float *phi, const float *I, float *t1, float *t2,
-                              Grid3 g, const Taps &t, float eps, float *probeH, const int *done,
-                              hipStream_t s);
-hipError_t launch_z_update(int R, const float *t1, const float *t2, Grid3 g, const Taps &t,
-                           const UpdArgs &ua, const int *done, hipStream_t s);
+// XY_ONE reads one field of the image type and writes one field of the
+// storage type; XY_TWO and XY_FITS read and write interleaved pairs of the
+// storage type.
+hipError_t launch_xy(int R, int mode, int image_dtype, int storage_dtype, const void *in,
+                     void *out, Grid3 g, const Taps &t, const FitArgs *fa, const int *done,
+                     hipStream_t s);
+hipError_t launch_z_plain(int R, int storage_dtype, const void *in, void *out, Grid3 g,
+                          const Taps &t, hipStream_t s);
+// Stage-1 z pass: (phi, I) -> the pair (Kz*(H I), Kz*H).
+hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const float *phi,
+                              const void *I, void *pair_out, Grid3 g, const Taps &t, float eps,
+                              float *probeH, const int *done, hipStream_t s);
+// Stage-2 z pass + update from the pair (Kxy*g1, Kxy*g2).
+hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const void *pair_in,
+                           Grid3 g, const Taps &t, const UpdArgs &ua, const int *done,
+                           hipStream_t s);
 hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,
                          double tol_total, hipStream_t s);
 
-// Per-radius launchers behind the dispatchers above (rsf_kernels.hpp).
-template <int R>
-hipError_t launch_xy_r(int mode, const float *a, const float *b, float *oa, float *ob, Grid3 g,
-                       const Taps &t, const FitArgs *fa, const int *done, hipStream_t s);
-template <int R>
-hipError_t launch_z_plain_r(const float *in, float *out, Grid3 g, const Taps &t, hipStream_t s);
-template <int R>
-hipError_t launch_z_heaviside_r(const float *phi, const float *I, float *t1, float *t2, Grid3 g,
+// Per-radius, per-type launchers behind the dispatchers (rsf_kernels.hpp).
+template <int R, class IT, class ST>
+hipError_t launch_xy_r(int mode, const void *in, void *out, Grid3 g, const Taps &t,
+                       const FitArgs *fa, const int *done, hipStream_t s);
+template <int R, class ST>
+hipError_t launch_z_plain_r(const void *in, void *out, Grid3 g, const Taps &t, hipStream_t s);
+template <int R, class IT, class ST>
+hipError_t launch_z_heaviside_r(const float *phi, const void *I, void *pair_out, Grid3 g,
                                 const Taps &t, float eps, float *probeH, const int *done,
                                 hipStream_t s);
-template <int R>
-hipError_t launch_z_update_r(const float *t1, const float *t2, Grid3 g, const Taps &t,
-                             const UpdArgs &ua, const int *done, hipStream_t s);
+template <int R, class IT, class ST>
+hipError_t launch_z_update_r(const void *pair_in, Grid3 g, const Taps &t, const UpdArgs &ua,
+                             const int *done, hipStream_t s);
 
 }  // namespace rsf

@@ -142,56 +142,79 @@ hipError_t launch_flags_init(int *flags, hipStream_t s)
     return hipGetLastError();
 }
 
-#define RSF_R_CASES(X) \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+// dtype codes as in rsf.h
+constexpr int F32 = 0, F16 = 1, BF16 = 2, U16 = 3;
 
-hipError_t launch_xy(int R, int mode, const float *a, const float *b, float *oa, float *ob,
-                     Grid3 g, const Taps &t, const FitArgs *fa, const int *done, hipStream_t s)
+bool types_supported(int R, int it, int st)
 {
-    switch (R) {
-#define C(RR) case RR: return launch_xy_r<RR>(mode, a, b, oa, ob, g, t, fa, done, s);
-        RSF_R_CASES(C)
-#undef C
-    default:
-        return hipErrorInvalidValue;
-    }
+    if (R < 1 || R > kMaxR) return false;
+    if (it == F32 && st == F32) return true;
+    if (R < kMinRMixed || R > kMaxRMixed) return false;
+    return (it == F32 || it == U16) && (st == F32 || st == F16 || st == BF16);
 }
 
-hipError_t launch_z_plain(int R, const float *in, float *out, Grid3 g, const Taps &t,
+// Expand F(RR, IT, ST) for every built (radius, image, storage) combination
+// matching the runtime (R, it, st).
+#define RSF_R_ALL(X, IT, ST) \
+    X(1, IT, ST) X(2, IT, ST) X(3, IT, ST) X(4, IT, ST) X(5, IT, ST) X(6, IT, ST) X(7, IT, ST) \
+    X(8, IT, ST) X(9, IT, ST) X(10, IT, ST) X(11, IT, ST) X(12, IT, ST) X(13, IT, ST)          \
+    X(14, IT, ST) X(15, IT, ST) X(16, IT, ST)
+#define RSF_R_MIXED(X, IT, ST) \
+    X(4, IT, ST) X(5, IT, ST) X(6, IT, ST) X(7, IT, ST) X(8, IT, ST) X(9, IT, ST) X(10, IT, ST) \
+    X(11, IT, ST) X(12, IT, ST)
+#define RSF_DISPATCH(CALL)                                                              \
+    if (!types_supported(R, it, st)) return hipErrorInvalidValue;                       \
+    if (it == F32 && st == F32) {                                                       \
+        switch (R) { RSF_R_ALL(CALL, float, float) default: break; }                     \
+    } else if (it == U16 && st == F16) {                                                \
+        switch (R) { RSF_R_MIXED(CALL, uint16_t, _Float16) default: break; }             \
+    } else if (it == U16 && st == BF16) {                                               \
+        switch (R) { RSF_R_MIXED(CALL, uint16_t, __bf16) default: break; }               \
+    } else if (it == U16 && st == F32) {                                                \
+        switch (R) { RSF_R_MIXED(CALL, uint16_t, float) default: break; }                \
+    } else if (it == F32 && st == F16) {                                                \
+        switch (R) { RSF_R_MIXED(CALL, float, _Float16) default: break; }                \
+    } else if (it == F32 && st == BF16) {                                               \
+        switch (R) { RSF_R_MIXED(CALL, float, __bf16) default: break; }                  \
+    }                                                                                   \
+    return hipErrorInvalidValue;
+
+hipError_t launch_xy(int R, int mode, int it, int st, const void *in, void *out, Grid3 g,
+                     const Taps &t, const FitArgs *fa, const int *done, hipStream_t s)
+{
+#define C(RR, IT, ST) \
+    case RR: return launch_xy_r<RR, IT, ST>(mode, in, out, g, t, fa, done, s);
+    RSF_DISPATCH(C)
+#undef C
+}
+
+hipError_t launch_z_plain(int R, int st, const void *in, void *out, Grid3 g, const Taps &t,
                           hipStream_t s)
 {
-    switch (R) {
-#define C(RR) case RR: return launch_z_plain_r<RR>(in, out, g, t, s);
-        RSF_R_CASES(C)
+    const int it = F32;   // the plain z pass only touches the storage type
+#define C(RR, IT, ST) \
+    case RR: return launch_z_plain_r<RR, ST>(in, out, g, t, s);
+    RSF_DISPATCH(C)
 #undef C
-    default:
-        return hipErrorInvalidValue;
-    }
 }
 
-hipError_t launch_z_heaviside(int R, const float *phi, const float *I, float *t1, float *t2,
-                              Grid3 g, const Taps &t, float eps, float *probeH, const int *done,
-                              hipStream_t s)
+hipError_t launch_z_heaviside(int R, int it, int st, const float *phi, const void *I,
+                              void *pair_out, Grid3 g, const Taps &t, float eps, float *probeH,
+                              const int *done, hipStream_t s)
 {
-    switch (R) {
-#define C(RR) case RR: return launch_z_heaviside_r<RR>(phi, I, t1, t2, g, t, eps, probeH, done, s);
-        RSF_R_CASES(C)
+#define C(RR, IT, ST) \
+    case RR: return launch_z_heaviside_r<RR, IT, ST>(phi, I, pair_out, g, t, eps, probeH, done, s);
+    RSF_DISPATCH(C)
 #undef C
-    default:
-        return hipErrorInvalidValue;
-    }
 }
 
-hipError_t launch_z_update(int R, const float *t1, const float *t2, Grid3 g, const Taps &t,
+hipError_t launch_z_update(int R, int it, int st, const void *pair_in, Grid3 g, const Taps &t,
                            const UpdArgs &ua, const int *done, hipStream_t s)
 {
-    switch (R) {
-#define C(RR) case RR: return launch_z_update_r<RR>(t1, t2, g, t, ua, done, s);
-        RSF_R_CASES(C)
+#define C(RR, IT, ST) \
+    case RR: return launch_z_update_r<RR, IT, ST>(pair_in, g, t, ua, done, s);
+    RSF_DISPATCH(C)
 #undef C
-    default:
-        return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,

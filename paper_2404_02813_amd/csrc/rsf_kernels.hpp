@@ -23,6 +23,24 @@ __device__ __forceinline__ float heaviside(float phi, float eps)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Storage and image element types: fields may be stored as float, FP16 or
+// BF16 (arithmetic is always FP32); the image may be float or uint16, the
+// latter normalised to [0, 1] as u / 65535 on load.
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(uint16_t v) { return (float)v * (1.f / 65535.f); }
+template <class T>
+__device__ __forceinline__ T from_f(float v) { return (T)v; }   // round to nearest even
+
+// The two fields every pass reads or writes together (Kz*(HI) and Kz*H; g1
+// and g2; their xy convolutions) are stored interleaved, so one 4-byte (FP16,
+// BF16) or 8-byte (FP32) access per lane moves both.
+template <class T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
 // Make `v` opaque to the optimiser: it must be computed here, so a sum that
 // feeds a register ring is not sunk to its distant use (which would keep all
 // of its inputs live instead of one value).
@@ -50,11 +68,12 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // work is paid only on the chunk's 2R extra rows, never per row.
 // ---------------------------------------------------------------------------
 
-template <int R, int MODE>
-__global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
-                                                const float *__restrict__ b,
-                                                float *__restrict__ oa, float *__restrict__ ob,
-                                                Grid3 g, Taps t, FitArgs fa, int nyc,
+// XY_ONE reads and writes one field of IN / ST; XY_TWO and XY_FITS read and
+// write interleaved pairs.
+template <int R, int MODE, class IN, class ST>
+__global__ __launch_bounds__(64) void xy_kernel(const void *__restrict__ in_,
+                                                void *__restrict__ out_, Grid3 g, Taps t,
+                                                FitArgs fa, int nyc,
                                                 const int *__restrict__ done)
 {
     if (done && *done) return;
@@ -82,8 +101,7 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
         Raw r;
         // uniform row bases, 32-bit lane offsets
         const int yy = min(max(y, 0), g.ny - 1);
-        const float *ra = a + zb + (int64_t)yy * g.nx;
-        const float *rb = NF == 2 ? b + zb + (int64_t)yy * g.nx : nullptr;
+        const int64_t rowo = zb + (int64_t)yy * g.nx;
         const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -92,8 +110,13 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
             const int j = lane + 64 * h;
             const int gx = x0 - R + j;
             if (yok && j < RW && gx >= 0 && gx < g.nx) {
-                r.a[h] = ra[gx];
-                if (NF == 2) r.b[h] = rb[gx];
+                if (NF == 2) {
+                    const Pair<IN> v = (static_cast<const Pair<IN> *>(in_) + rowo)[gx];
+                    r.a[h] = to_f(v.a);
+                    r.b[h] = to_f(v.b);
+                } else {
+                    r.a[h] = to_f((static_cast<const IN *>(in_) + rowo)[gx]);
+                }
             }
         }
         return r;
@@ -133,12 +156,12 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
     }
     float cxz = 0.f;
     const int xc = min(x, g.nx - 1);
-    const float *ki_slice = MODE == XY_FITS ? fa.KI + zb : nullptr;
+    const ST *ki_slice = MODE == XY_FITS ? static_cast<const ST *>(fa.KI) + zb : nullptr;
     if (MODE == XY_FITS) cxz = fa.cx[xc] * fa.cz[z];
-    float ki_next = MODE == XY_FITS ? ki_slice[y0 * g.nx + xc] : 0.f;
+    float ki_next = MODE == XY_FITS ? to_f(ki_slice[y0 * g.nx + xc]) : 0.f;
     float cy_next = MODE == XY_FITS ? fa.cy[y0] : 0.f;
-    float *oa_s = oa + zb;
-    float *ob_s = NF == 2 ? ob + zb : nullptr;
+    ST *o1_s = static_cast<ST *>(out_) + zb;
+    Pair<ST> *o2_s = static_cast<Pair<ST> *>(out_) + zb;
     for (int yb = y0; yb < y1; yb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -151,7 +174,7 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
                     ki = ki_next;
                     cyv = cy_next;
                     if (y + 1 < y1) {
-                        ki_next = ki_slice[(y + 1) * g.nx + xc];
+                        ki_next = to_f(ki_slice[(y + 1) * g.nx + xc]);
                         cy_next = fa.cy[y + 1];
                     }
                 }
@@ -174,13 +197,14 @@ __global__ __launch_bounds__(64) void xy_kernel(const float *__restrict__ a,
                         const float B2 = K1 - acc_b;
                         const float f1 = acc_a * rcp(acc_b);
                         const float f2 = A2 * rcp(B2);
-                        oa_s[v] = fa.l1 * f1 - fa.l2 * f2;
-                        ob_s[v] = fa.l1 * f1 * f1 - fa.l2 * f2 * f2;
+                        o2_s[v] = Pair<ST>{from_f<ST>(fa.l1 * f1 - fa.l2 * f2),
+                                           from_f<ST>(fa.l1 * f1 * f1 - fa.l2 * f2 * f2)};
                         if (fa.probe_f1) fa.probe_f1[zb + v] = f1;
                         if (fa.probe_f2) fa.probe_f2[zb + v] = f2;
+                    } else if (NF == 2) {
+                        o2_s[v] = Pair<ST>{from_f<ST>(acc_a), from_f<ST>(acc_b)};
                     } else {
-                        oa_s[v] = acc_a;
-                        if (NF == 2) ob_s[v] = acc_b;
+                        o1_s[v] = from_f<ST>(acc_a);
                     }
                 }
             }
@@ -273,9 +297,9 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void z_plain_kernel(const float *__restrict__ in,
-                                                           float *__restrict__ out, Grid3 g,
+template <int R, class ST>
+__global__ __launch_bounds__(kThreads) void z_plain_kernel(const ST *__restrict__ in,
+                                                           ST *__restrict__ out, Grid3 g,
                                                            Taps t, int nzc)
 {
     const ZTile zt = z_tile(g, nzc);
@@ -283,17 +307,16 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(const float *__restri
     const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
-        [&](int z) { return make_float2((in + (int64_t)z * g.sxy)[col], 0.f); },
+        [&](int z) { return make_float2(to_f((in + (int64_t)z * g.sxy)[col]), 0.f); },
         [&](float2 raw, int) { return raw; },
-        [&](int z, float va, float) { (out + (int64_t)z * g.sxy)[col] = va; });
+        [&](int z, float va, float) { (out + (int64_t)z * g.sxy)[col] = from_f<ST>(va); });
 }
 
 // Stage-1 z pass: H_eps(phi) and H I formed as slices enter the ring.
-template <int R, bool PROBE>
+template <int R, bool PROBE, class ST, class IT>
 __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
-    const float *__restrict__ phi, const float *__restrict__ I, float *__restrict__ t1,
-    float *__restrict__ t2, Grid3 g, Taps t, float eps, float *__restrict__ probeH, int nzc,
-    const int *__restrict__ done)
+    const float *__restrict__ phi, const IT *__restrict__ I, Pair<ST> *__restrict__ tp, Grid3 g,
+    Taps t, float eps, float *__restrict__ probeH, int nzc, const int *__restrict__ done)
 {
     if (done && *done) return;
     const ZTile zt = z_tile(g, nzc);
@@ -303,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
             const int64_t zo = (int64_t)z * g.sxy;
-            return make_float2((phi + zo)[col], (I + zo)[col]);
+            return make_float2((phi + zo)[col], to_f((I + zo)[col]));
         },
         [&](float2 raw, int z) {
             const float H = heaviside(raw.x, eps);
@@ -311,9 +334,7 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
             return make_float2(H * raw.y, H);
         },
         [&](int z, float va, float vb) {
-            const int64_t zo = (int64_t)z * g.sxy;
-            (t1 + zo)[col] = va;
-            (t2 + zo)[col] = vb;
+            (tp + (int64_t)z * g.sxy)[col] = Pair<ST>{from_f<ST>(va), from_f<ST>(vb)};
         });
 }
 
@@ -354,9 +375,8 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
 // Slot reuse is safe: phi(z+3) overwrites phi(z-3), last read in step z-2;
 // n, V of z+2 overwrite those of z-1, last read in step z-1; a barrier
 // separates each pair.
-template <int R, bool PROBE>
-__global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__restrict__ t1,
-                                                             const float *__restrict__ t2,
+template <int R, bool PROBE, class ST, class IT>
+__global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *__restrict__ tp,
                                                              Grid3 g, Taps t, UpdArgs ua,
                                                              int nzc, const int *__restrict__ done)
 {
@@ -457,7 +477,12 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
 
         const int col = min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
         const float cxy = ua.cx[min(zt.x, g.nx - 1)] * ua.cy[min(zt.y, g.ny - 1)];
-        auto at = [&](const float *base, int z) { return (base + (int64_t)z * g.sxy)[col]; };
+        const IT *img = static_cast<const IT *>(ua.I);
+        auto at = [&](const auto *base, int z) { return to_f((base + (int64_t)z * g.sxy)[col]); };
+        auto pair_at = [&](int z) {
+            const Pair<ST> v = (tp + (int64_t)z * g.sxy)[col];
+            return make_float2(to_f(v.a), to_f(v.b));
+        };
         const int z0 = zt.z0;
         // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
 #pragma unroll
@@ -473,30 +498,28 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
             const int z = z0 - R + j;
-            const bool ok = z >= 0 && z < g.nz;
-            ra[j] = ok ? at(t1, z) : 0.f;
-            rb[j] = ok ? at(t2, z) : 0.f;
+            const float2 v = (z >= 0 && z < g.nz) ? pair_at(z) : make_float2(0.f, 0.f);
+            ra[j] = v.x;
+            rb[j] = v.y;
         }
         __builtin_amdgcn_sched_barrier(0);
         // one-step-ahead prefetch of the next phi slice, conv inputs and image
         PhiRaw phi_nxt = fetch_phi(z0 + 3);
-        float t1_nxt = z0 + R < g.nz ? at(t1, z0 + R) : 0.f;
-        float t2_nxt = z0 + R < g.nz ? at(t2, z0 + R) : 0.f;
-        float I_nxt = z0 < zt.z1 ? at(ua.I, z0) : 0.f;
+        float2 t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : make_float2(0.f, 0.f);
+        float I_nxt = z0 < zt.z1 ? at(img, z0) : 0.f;
         for (int zb = z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
                     store_phi(phi_nxt, z + 3);
-                    ra[(s + 2 * R) % W] = t1_nxt;
-                    rb[(s + 2 * R) % W] = t2_nxt;
+                    ra[(s + 2 * R) % W] = t_nxt.x;
+                    rb[(s + 2 * R) % W] = t_nxt.y;
                     const float Iv = I_nxt;
                     phi_nxt = fetch_phi(z + 4);
                     const int zn = z + R + 1;
-                    t1_nxt = zn < g.nz ? at(t1, zn) : 0.f;
-                    t2_nxt = zn < g.nz ? at(t2, zn) : 0.f;
-                    if (z + 1 < zt.z1) I_nxt = at(ua.I, z + 1);
+                    t_nxt = zn < g.nz ? pair_at(zn) : make_float2(0.f, 0.f);
+                    if (z + 1 < zt.z1) I_nxt = at(img, z + 1);
                     __syncthreads();
                     float nzpp, vzpp;
                     q_phase(z + 2, nzpp, vzpp);
@@ -563,25 +586,25 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const float *__r
 // Per-radius launchers (explicitly instantiated in rsf_inst_*.hip)
 // ---------------------------------------------------------------------------
 
-template <int R>
-hipError_t launch_xy_r(int mode, const float *a, const float *b, float *oa, float *ob, Grid3 g,
-                       const Taps &t, const FitArgs *fa, const int *done, hipStream_t s)
+template <int R, class IT, class ST>
+hipError_t launch_xy_r(int mode, const void *in, void *out, Grid3 g, const Taps &t,
+                       const FitArgs *fa, const int *done, hipStream_t s)
 {
     const dim3 grid(xy_blocks(g));
     const FitArgs f = fa ? *fa : FitArgs{};
     const int nyc = xy_chunks(g);
     switch (mode) {
     case XY_ONE:
-        hipLaunchKernelGGL((xy_kernel<R, XY_ONE>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
+        hipLaunchKernelGGL((xy_kernel<R, XY_ONE, IT, ST>), grid, dim3(64), 0, s, in, out, g, t, f,
                            nyc, done);
         break;
     case XY_TWO:
-        hipLaunchKernelGGL((xy_kernel<R, XY_TWO>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
+        hipLaunchKernelGGL((xy_kernel<R, XY_TWO, ST, ST>), grid, dim3(64), 0, s, in, out, g, t, f,
                            nyc, done);
         break;
     case XY_FITS:
-        hipLaunchKernelGGL((xy_kernel<R, XY_FITS>), grid, dim3(64), 0, s, a, b, oa, ob, g, t, f,
-                           nyc, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_FITS, ST, ST>), grid, dim3(64), 0, s, in, out, g, t,
+                           f, nyc, done);
         break;
     default:
         return hipErrorInvalidValue;
@@ -589,54 +612,57 @@ hipError_t launch_xy_r(int mode, const float *a, const float *b, float *oa, floa
     return hipGetLastError();
 }
 
-template <int R>
-hipError_t launch_z_plain_r(const float *in, float *out, Grid3 g, const Taps &t, hipStream_t s)
+template <int R, class ST>
+hipError_t launch_z_plain_r(const void *in, void *out, Grid3 g, const Taps &t, hipStream_t s)
 {
-    hipLaunchKernelGGL((z_plain_kernel<R>), dim3((unsigned)z_blocks(g)), dim3(kThreads), 0, s, in,
-                       out, g, t, z_chunks(g));
+    hipLaunchKernelGGL((z_plain_kernel<R, ST>), dim3((unsigned)z_blocks(g)), dim3(kThreads), 0, s,
+                       static_cast<const ST *>(in), static_cast<ST *>(out), g, t, z_chunks(g));
     return hipGetLastError();
 }
 
-template <int R>
-hipError_t launch_z_heaviside_r(const float *phi, const float *I, float *t1, float *t2, Grid3 g,
+template <int R, class IT, class ST>
+hipError_t launch_z_heaviside_r(const float *phi, const void *I, void *pair_out, Grid3 g,
                                 const Taps &t, float eps, float *probeH, const int *done,
                                 hipStream_t s)
 {
     const dim3 grid((unsigned)z_blocks(g));
+    const IT *img = static_cast<const IT *>(I);
+    Pair<ST> *o = static_cast<Pair<ST> *>(pair_out);
     if (probeH)
-        hipLaunchKernelGGL((z_heaviside_kernel<R, true>), grid, dim3(kThreads), 0, s, phi, I, t1,
-                           t2, g, t, eps, probeH, z_chunks(g), done);
+        hipLaunchKernelGGL((z_heaviside_kernel<R, true, ST, IT>), grid, dim3(kThreads), 0, s, phi,
+                           img, o, g, t, eps, probeH, z_chunks(g), done);
     else
-        hipLaunchKernelGGL((z_heaviside_kernel<R, false>), grid, dim3(kThreads), 0, s, phi, I, t1,
-                           t2, g, t, eps, probeH, z_chunks(g), done);
+        hipLaunchKernelGGL((z_heaviside_kernel<R, false, ST, IT>), grid, dim3(kThreads), 0, s, phi,
+                           img, o, g, t, eps, probeH, z_chunks(g), done);
     return hipGetLastError();
 }
 
-template <int R>
-hipError_t launch_z_update_r(const float *t1, const float *t2, Grid3 g, const Taps &t,
-                             const UpdArgs &ua, const int *done, hipStream_t s)
+template <int R, class IT, class ST>
+hipError_t launch_z_update_r(const void *pair_in, Grid3 g, const Taps &t, const UpdArgs &ua,
+                             const int *done, hipStream_t s)
 {
     const dim3 grid((unsigned)u_blocks(g));
+    const Pair<ST> *p = static_cast<const Pair<ST> *>(pair_in);
     const bool probe = ua.probe_Fd || ua.probe_kappa || ua.probe_lap || ua.probe_R || ua.probe_E;
     if (probe)
-        hipLaunchKernelGGL((z_update_kernel<R, true>), grid, dim3(kUThreads), 0, s, t1, t2, g, t,
+        hipLaunchKernelGGL((z_update_kernel<R, true, ST, IT>), grid, dim3(kUThreads), 0, s, p, g, t,
                            ua, u_chunks(g), done);
     else
-        hipLaunchKernelGGL((z_update_kernel<R, false>), grid, dim3(kUThreads), 0, s, t1, t2, g, t,
-                           ua, u_chunks(g), done);
+        hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT>), grid, dim3(kUThreads), 0, s, p, g,
+                           t, ua, u_chunks(g), done);
     return hipGetLastError();
 }
 
-#define RSF_INSTANTIATE(RR)                                                                     \
-    template hipError_t launch_xy_r<RR>(int, const float *, const float *, float *, float *,    \
-                                        Grid3, const Taps &, const FitArgs *, const int *,      \
-                                        hipStream_t);                                           \
-    template hipError_t launch_z_plain_r<RR>(const float *, float *, Grid3, const Taps &,       \
-                                             hipStream_t);                                      \
-    template hipError_t launch_z_heaviside_r<RR>(const float *, const float *, float *, float *, \
-                                                 Grid3, const Taps &, float, float *,           \
-                                                 const int *, hipStream_t);                     \
-    template hipError_t launch_z_update_r<RR>(const float *, const float *, Grid3, const Taps &, \
-                                              const UpdArgs &, const int *, hipStream_t);
+// Instantiate every pass launcher for radius RR, image type IT, storage ST.
+#define RSF_INSTANTIATE(RR, IT, ST)                                                          \
+    template hipError_t launch_xy_r<RR, IT, ST>(int, const void *, void *, Grid3, const Taps &, \
+                                                const FitArgs *, const int *, hipStream_t);  \
+    template hipError_t launch_z_plain_r<RR, ST>(const void *, void *, Grid3, const Taps &,  \
+                                                 hipStream_t);                               \
+    template hipError_t launch_z_heaviside_r<RR, IT, ST>(const float *, const void *, void *, \
+                                                         Grid3, const Taps &, float, float *, \
+                                                         const int *, hipStream_t);          \
+    template hipError_t launch_z_update_r<RR, IT, ST>(const void *, Grid3, const Taps &,     \
+                                                      const UpdArgs &, const int *, hipStream_t);
 
 }  // namespace rsf

@@ -78,6 +78,28 @@ def vessel_phantom(shape, n_tubes: int, r_min: float, r_max: float, seed: int,
     return np.ascontiguousarray(img, dtype=np.float32)
 
 
+def u16_phantom(shape, n_tubes: int, r_min: float, r_max: float, seed: int,
+                background: float = 6000.0, vessel: float = 50000.0, gain: float = 8.0,
+                read_sd: float = 100.0, blur_sd: float = 1.0) -> np.ndarray:
+    """uint16 phantom [nz][ny][nx] in detector numbers: the tube mask blurred by
+    a Gaussian of sd `blur_sd`, mapped to background..vessel, then
+    Poisson-Gaussian noise u = gain * Poisson(clean / gain) + N(0, read_sd^2),
+    clipped to [0, 65535] and rounded."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = rng_for(seed)
+    m = tube_mask(shape, n_tubes, r_min, r_max, rng).astype(np.float32)
+    mb = gaussian_filter(m, sigma=blur_sd, truncate=3.0, mode="reflect")
+    del m
+    clean = np.float32(background) + np.float32(vessel - background) * mb
+    del mb
+    u = np.float32(gain) * rng.poisson(clean / np.float32(gain)).astype(np.float32)
+    del clean
+    u += np.float32(read_sd) * rng.standard_normal(size=shape, dtype=np.float32)
+    np.clip(u, 0.0, 65535.0, out=u)
+    return np.rint(u).astype(np.uint16)
+
+
 def box_phi0(shape, inside: float = 2.0, outside: float = -2.0) -> np.ndarray:
     """+inside on [n/4, 3n/4) along every axis, `outside` elsewhere."""
     phi = np.full(shape, outside, dtype=np.float32)

@@ -24,6 +24,9 @@ RSF_ERR_BUDGET = -5
 RSF_ERR_INTERNAL = -6
 
 RSF_F32 = 0
+RSF_F16 = 1
+RSF_BF16 = 2
+RSF_U16 = 3
 
 RSF_REG_DOUBLE_WELL = 0
 RSF_REG_SINGLE_WELL = 1
@@ -45,7 +48,7 @@ class rsf_params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_float), ("lambda1", ctypes.c_float),
                 ("lambda2", ctypes.c_float), ("nu", ctypes.c_float), ("mu", ctypes.c_float),
                 ("dt", ctypes.c_float), ("eps", ctypes.c_float), ("eta", ctypes.c_float),
-                ("regulariser", ctypes.c_int)]
+                ("regulariser", ctypes.c_int), ("storage", ctypes.c_int)]
 
 
 class rsf_stats(ctypes.Structure):
@@ -82,7 +85,7 @@ def lib() -> ctypes.CDLL:
     L.rsf_destroy.restype = None
     L.rsf_last_error.argtypes = [vp]
     L.rsf_last_error.restype = ctypes.c_char_p
-    L.rsf_workspace_bytes.argtypes = [i64, i64, i64, i]
+    L.rsf_workspace_bytes.argtypes = [i64, i64, i64, i, i]
     L.rsf_workspace_bytes.restype = ctypes.c_size_t
     L.rsf_evolve.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, f, f, f, f, i, vp]
     L.rsf_evolve.restype = i
@@ -118,10 +121,17 @@ def _stream(stream) -> int:
     return int(stream)
 
 
+_IMAGE_DTYPES = {torch.float32: RSF_F32, torch.uint16: RSF_U16}
+_STORAGE = {"f32": RSF_F32, "f16": RSF_F16, "bf16": RSF_BF16}
+
+
 def _field(t: torch.Tensor, name: str, dtype=torch.float32) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
-    if t.dtype != dtype:
+    if dtype == "image":
+        if t.dtype not in _IMAGE_DTYPES:
+            raise ValueError(f"{name} must be float32 or uint16")
+    elif t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}")
     if t.dim() != 3 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous 3D tensor [nz][ny][nx]")
@@ -129,8 +139,9 @@ def _field(t: torch.Tensor, name: str, dtype=torch.float32) -> torch.Tensor:
 
 
 def make_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10,
-                regulariser=RSF_REG_DOUBLE_WELL) -> rsf_params:
-    return rsf_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta, regulariser)
+                regulariser=RSF_REG_DOUBLE_WELL, storage="f32") -> rsf_params:
+    st = _STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return rsf_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta, regulariser, st)
 
 
 def rsf_create(device: int = 0) -> ctypes.c_void_p:
@@ -150,27 +161,29 @@ def rsf_last_error(ctx) -> str:
     return lib().rsf_last_error(ctx).decode(errors="replace")
 
 
-def rsf_workspace_bytes(nx: int, ny: int, nz: int, iters: int) -> int:
-    return int(lib().rsf_workspace_bytes(nx, ny, nz, iters))
+def rsf_workspace_bytes(nx: int, ny: int, nz: int, iters: int, storage=RSF_F32) -> int:
+    st = _STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return int(lib().rsf_workspace_bytes(nx, ny, nz, iters, st))
 
 
 def rsf_evolve(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma: float, lambda1: float,
                lambda2: float, nu: float, mu: float, dt: float, eps: float, iters: int,
                stream=None) -> None:
     """Evolve `phi` in place (default double-well regulariser)."""
-    _field(volume, "volume")
+    _field(volume, "volume", "image")
     _field(phi, "phi")
     if volume.shape != phi.shape or volume.device != phi.device:
         raise ValueError("volume and phi must have the same shape and device")
     nz, ny, nx = phi.shape
-    _check(ctx, lib().rsf_evolve(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+    _check(ctx, lib().rsf_evolve(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                 phi.data_ptr(), nx, ny, nz,
                                  sigma, lambda1, lambda2, nu, mu, dt, eps, int(iters),
                                  _stream(stream)))
 
 
 def rsf_evolve_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params, iters: int,
                   tol: float = 0.0, workspace: torch.Tensor | None = None, stream=None) -> None:
-    _field(volume, "volume")
+    _field(volume, "volume", "image")
     _field(phi, "phi")
     if volume.shape != phi.shape or volume.device != phi.device:
         raise ValueError("volume and phi must have the same shape and device")
@@ -180,7 +193,8 @@ def rsf_evolve_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_para
         if not workspace.is_cuda or not workspace.is_contiguous():
             raise ValueError("workspace must be a contiguous CUDA tensor")
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-    _check(ctx, lib().rsf_evolve_ex(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+    _check(ctx, lib().rsf_evolve_ex(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                    phi.data_ptr(), nx, ny, nz,
                                     ctypes.byref(params), int(iters), float(tol), ws_ptr,
                                     ws_bytes, _stream(stream)))
 
@@ -208,12 +222,13 @@ def rsf_gauss3d(ctx, inp: torch.Tensor, out: torch.Tensor, sigma: float, stream=
 def rsf_probe(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
               stream=None) -> dict:
     """One iteration's intermediate fields as new tensors (see rsf.h)."""
-    _field(volume, "volume")
+    _field(volume, "volume", "image")
     _field(phi, "phi")
     nz, ny, nx = phi.shape
     out = {n: torch.empty_like(phi) for n in PROBE_NAMES}
     pf = rsf_probe_fields(*[out[n].data_ptr() for n in PROBE_NAMES])
-    _check(ctx, lib().rsf_probe(ctx, volume.data_ptr(), RSF_F32, phi.data_ptr(), nx, ny, nz,
+    _check(ctx, lib().rsf_probe(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                phi.data_ptr(), nx, ny, nz,
                                 ctypes.byref(params), ctypes.byref(pf), _stream(stream)))
     return out
 

@@ -44,8 +44,11 @@ def test_host_only_entry_points():
     L = rsf.lib()
     # six float fields dominate the workspace
     nb = rsf.rsf_workspace_bytes(64, 64, 64, 20)
-    assert 6 * 64 ** 3 * 4 <= nb < 6 * 64 ** 3 * 4 + 1 << 20
+    assert 6 * 64 ** 3 * 4 <= nb < 6 * 64 ** 3 * 4 + (1 << 20)
+    nh = rsf.rsf_workspace_bytes(64, 64, 64, 20, "f16")
+    assert 14 * 64 ** 3 <= nh < 14 * 64 ** 3 + (1 << 20)
     assert rsf.rsf_workspace_bytes(0, 4, 4, 1) == 0
+    assert rsf.rsf_workspace_bytes(8, 8, 8, 1, 7) == 0
     assert L.rsf_last_error(None) == b"null context"
     # a NULL context is rejected before anything touches a device
     st = L.rsf_evolve(None, None, 0, None, 8, 8, 8, 3.0, 1, 1, 0.001, 1, 0.1, 1, 1, None)

@@ -341,3 +341,39 @@ def test_full_size_200_iterations_properties(rsf, large):
     frac = float((a > 0).float().mean())
     assert 0.5 * frac0 < frac < 1.5 * frac0
     assert hist[-1] < hist[0]
+
+
+# --- FP16 / BF16 storage, uint16 images -----------------------------------------------
+
+@pytest.mark.parametrize("storage,image", [("f16", "u16"), ("bf16", "u16"), ("f32", "u16"),
+                                           ("f16", "f32"), ("bf16", "f32")])
+def test_mixed_precision_evolution(rsf, storage, image):
+    """Intermediate fields stored in FP16/BF16 (FP32 arithmetic and phi) on
+    the mixed-precision recipe (uint16 detector numbers, sigma 4, 150
+    iterations) against the FP64 oracle on the exact image u / 65535."""
+    mod, ctx = rsf
+    n, iters = 96, 150
+    say(f"mixed precision storage={storage} image={image} n={n}")
+    u = inputs.u16_phantom((n, n, n), 30, 1.0, 4.0, seed=41)
+    I = u.astype(np.float64) / 65535.0
+    phi0 = inputs.box_phi0((n, n, n))
+    p = dict(sigma=4.0, lambda1=1.0, lambda2=1.0, nu=0.001, mu=1.0, dt=0.1, eps=1.0)
+    vol = torch.from_numpy(u).cuda() if image == "u16" else dev(I)
+    phi = dev(phi0)
+    ctx.evolve_ex(vol, phi, mod.make_params(**p, storage=storage), iters)
+    got = host(phi)
+    want, _ = oracle.evolve(I, phi0, oracle.params_array(**p, eta=1e-10), iters)
+    dmax, agree = parity(got, want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.7f}")
+    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+
+
+def test_mixed_precision_radius_limits(rsf):
+    mod, ctx = rsf
+    say("mixed precision radius limits")
+    u = torch.zeros((8, 8, 8), dtype=torch.uint16, device="cuda")
+    phi = dev(inputs.box_phi0((8, 8, 8)))
+    for sigma in (1.0, 5.0):    # R = 3 and 15: outside the built 4..12
+        with pytest.raises(mod.RsfError) as e:
+            ctx.evolve_ex(u, phi, mod.make_params(sigma, 1, 1, 0.001, 1, 0.1, 1, storage="f16"), 1)
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
