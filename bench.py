@@ -144,14 +144,15 @@ def ingest_counters(fetch_dir: str, write_dir: str, workload: str, copy_bytes: i
     return data
 
 
-def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0):
-    """The FP64 oracle on a centred crop of the same phantom (bounded sample)."""
+def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = ""):
+    """The FP64 oracle on a centred crop (at most 192 per axis) of the same
+    image and phi0 (bounded sample)."""
     import numpy as np
 
     import oracle
 
-    n = 192 if w.shape[0] >= 192 else w.shape[0]
-    sl = tuple(slice((s - n) // 2, (s - n) // 2 + n) for s in w.shape)
+    ext = [min(192, s) for s in I.shape]
+    sl = tuple(slice((s - n) // 2, (s - n) // 2 + n) for s, n in zip(I.shape, ext))
     Ic = np.ascontiguousarray(I[sl], dtype=np.float64)
     pc = np.ascontiguousarray(phi0[sl], dtype=np.float64)
     p = oracle.params_array(**w.params(), eta=1e-10)
@@ -162,11 +163,149 @@ def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0):
     t0 = time.perf_counter()
     oracle.evolve(Ic, pc, p, iters)
     dt = time.perf_counter() - t0
-    vox_iters = float(n ** 3) * iters
+    vox_iters = float(Ic.size) * iters
+    shape = "x".join(str(n) for n in ext)
     return {"value": vox_iters / dt / 1e9, "unit": "Gvoxel-iter/s", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"{n}^3 centre crop of the {w.name} phantom and phi0, {iters} iterations, "
-                      f"{dt:.1f} s"}
+            "sample": f"{shape} (z,y,x) centre crop of {what or 'the ' + w.name + ' phantom'} "
+                      f"and its phi0, {iters} iterations, {dt:.1f} s"}
+
+
+def copy_bandwidth(torch) -> float:
+    """HBM copy bandwidth of a plain device copy (GB/s), for context, and the
+    known-size copy the rocprofv3 counter runs are calibrated against."""
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def roofline(prof: dict, pb: dict, voxels: int, workload: str) -> dict:
+    """Dominant pass (largest total time) priced at its algorithmic bytes per
+    voxel times the voxels one launch covers, over its mean launch time."""
+    hot = {k: v for k, v in prof.items() if k in pb}
+    dom = max(hot, key=lambda k: hot[k][1])
+    launches, total_ms = hot[dom]
+    avg_s = total_ms / launches * 1e-3
+    achieved = pb[dom] * voxels / avg_s / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, workload), "bytes_per_voxel": pb[dom],
+            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches}
+
+
+def run_tiles(args, w) -> int:
+    """A step is one rsf_evolve_batch of all tiles (set-up plus `iters`
+    iterations, every tile in the same launches), after the autotuner has
+    picked the tiles' workgroup splits.  Also timed once each, outside the
+    timed region: the batch under the default splits, and a loop of one
+    rsf_evolve_ex per tile."""
+    import numpy as np
+    import torch
+
+    from paper_2404_02813_amd import rsf
+
+    if args.iters > 0:
+        import dataclasses
+        w = dataclasses.replace(w, iters=args.iters)
+    K, W = max(1, args.steps), max(0, args.warmup)
+    pb = pass_bytes()
+    t_gen = time.perf_counter()
+    vol_host = w.volume()
+    tiles = w.tiles(vol_host)
+    del vol_host
+    vols = [torch.from_numpy(t[1]).cuda() for t in tiles]
+    phi0 = [torch.from_numpy(t[2]).cuda() for t in tiles]
+    t_gen = time.perf_counter() - t_gen
+    voxels = sum(int(v.numel()) for v in vols)
+    interior = sum(int(np.prod([n - 2 * w.halo for n in v.shape])) for v in vols)
+    params = rsf.make_params(**w.params())
+    ctx = rsf.Context(0)
+
+    def fresh():
+        return [p.clone() for p in phi0]
+
+    def timed_once(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # default splits, then the per-tile loop (each once, after one warm-up)
+    ph = fresh()
+    ctx.evolve_batch(vols, ph, params, w.iters)
+    ph = fresh()
+    t_default = timed_once(lambda: ctx.evolve_batch(vols, ph, params, w.iters))
+    ph = fresh()
+    t_loop = timed_once(lambda: [ctx.evolve_ex(v, p, params, w.iters) for v, p in zip(vols, ph)])
+    loop_result = ph
+    t_tune = time.perf_counter()
+    ctx.autotune(vols, phi0, params, trial_iters=3)
+    t_tune = time.perf_counter() - t_tune
+
+    for _ in range(W):
+        ph = fresh()
+        ctx.evolve_batch(vols, ph, params, w.iters)
+    steps = [fresh() for _ in range(K)]
+    copy_gbs = copy_bandwidth(torch)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ph in steps:
+        ctx.evolve_batch(vols, ph, params, w.iters)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    prof = ctx.profile_read()
+    same = all(torch.equal(a, b) for a, b in zip(steps[-1], loop_result))
+    ok = all(bool(torch.isfinite(p).all().item()) for p in steps[-1])
+
+    value = voxels * w.iters * K / elapsed / 1e9
+    rate = lambda t: round(voxels * w.iters / t / 1e9, 3)  # noqa: E731
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gvoxel-iter/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "phantom_zyx": list(w.shape), "n_tiles": w.n_tiles,
+                   "edges": list(w.edges), "halo": w.halo, "sigma": w.sigma, "iters": w.iters,
+                   "image": "f32", "storage": "f32", "voxels_with_halo": voxels,
+                   "voxels_interior": interior, "parallelism": "single_gpu"},
+        "roofline": roofline(prof, pb, voxels, w.name),
+        "interior_value": round(interior * w.iters * K / elapsed / 1e9, 3),
+        "batch_default_split_value": rate(t_default),
+        "per_tile_loop_value": rate(t_loop),
+        "gain_over_loop": round(t_loop / (elapsed / K), 3),
+        "autotune_s": round(t_tune, 2),
+        "batch_equals_loop_bitwise": bool(same),
+        "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
+        "copy_gbs": round(copy_gbs, 1),
+        "finite": ok,
+        "input_gen_s": round(t_gen, 1),
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        first = tiles[0]
+        out["cpu_baseline"] = cpu_baseline(w, first[1], first[2], args.cpu_seconds,
+                                           what=f"tile 0 of {w.name}")
+    print(json.dumps(out), flush=True)
+    return 0 if ok and same else 1
 
 
 def main() -> int:
@@ -201,6 +340,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
+    if args.workload == inputs.TILES_64.name:
+        return run_tiles(args, inputs.TILES_64)
     w, image_t, storage_t = workloads()[args.workload]
     if args.iters > 0:
         import dataclasses
@@ -229,20 +370,7 @@ def main() -> int:
         ph.copy_(phi0)
     torch.cuda.synchronize()
 
-    # HBM copy bandwidth of a plain device copy, for context (and the known-size
-    # copy the rocprofv3 counter runs are calibrated against).
-    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
+    copy_gbs = copy_bandwidth(torch)
 
     ctx.profile(True)
     torch.cuda.synchronize()
@@ -259,12 +387,6 @@ def main() -> int:
     elapsed = t1 - t0
     vox = w.voxels
     value = vox * w.iters * K / elapsed / 1e9
-    hot = {k: v for k, v in prof.items() if k in pb}
-    dom = max(hot, key=lambda k: hot[k][1])
-    launches, total_ms = hot[dom]
-    avg_s = total_ms / launches * 1e-3
-    achieved = pb[dom] * vox / avg_s / 1e9
-    traffic = traffic_for(dom, args.workload)
     iter_bytes = sum(pb.values())
 
     out = {
@@ -285,10 +407,7 @@ def main() -> int:
                    "iters": w.iters, "n_tubes": w.n_tubes, "lambda1": w.lambda1,
                    "lambda2": w.lambda2, "nu": w.nu, "mu": w.mu, "dt": w.dt, "eps": w.eps,
                    "regulariser": "double_well", "parallelism": "single_gpu"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_voxel": pb[dom],
-                     "avg_launch_ms": round(avg_s * 1e3, 4), "launches": launches},
+        "roofline": roofline(prof, pb, vox, args.workload),
         "hbm_frac_path": round(value * iter_bytes / HBM_PEAK_GBS, 4),
         "path_bytes_per_voxel_iter": iter_bytes,
         "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},

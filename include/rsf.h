@@ -142,13 +142,55 @@ rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype,
                          int iters, double tol, void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* One volume of a batch (device pointers, as in rsf_evolve). */
+typedef struct {
+    const void *volume;   /* image I, nx*ny*nz elements of the batch's volume dtype */
+    float *phi;           /* phi_0 on entry, phi_iters on return                    */
+    int64_t nx, ny, nz;   /* each >= 3                                              */
+} rsf_tile;
+
+/* Bytes of device workspace rsf_evolve_batch needs for these tiles. */
+size_t rsf_batch_workspace_bytes(const rsf_tile *tiles, int n_tiles, int iters, int storage);
+
+/* Evolve every tile of a batch by `iters` iterations with shared parameters
+ * (the sub-volume parallelism of Sec. 4.1: tiles are independent problems,
+ * each with its own boundary; a tile's result does not depend on the rest of
+ * the batch).  Every pass is one launch over all tiles, however uneven their
+ * shapes; tiles may differ in size but share sigma, the volume dtype and the
+ * storage type.  tiles: host array, read during the call; other arguments as
+ * in rsf_evolve_ex (tol applies per tile).  rsf_get_tile_stats() reads the
+ * per-tile statistics afterwards. */
+rsf_status rsf_evolve_batch(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                            int volume_dtype, const rsf_params *params, int iters, double tol,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+/* Autotuner.  Times `trial_iters` iterations of these tiles (on copies of
+ * their phi; the caller's buffers are not modified) for candidate workgroup
+ * splits of each pass (row chunks of the xy passes, z chunks of the z and
+ * update passes), one pass at a time, and keeps the fastest split per tile
+ * shape and radius in the context.  Later evolutions of the same shapes use
+ * it.  phi after an evolution is bitwise independent of the split; the FP64
+ * sums of |dphi| are grouped per update workgroup, so they may differ in the
+ * last bits.  Synchronises `stream`; allocates a scratch copy of phi for the
+ * duration of the call; invalidates the statistics of the last evolution. */
+rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
+                        const rsf_params *params, int trial_iters, void *stream);
+
+/* Forget all autotuned splits of the context. */
+void rsf_autotune_reset(rsf_context *ctx);
+
+/* Statistics of tile `tile` of the last evolution (tile 0 for rsf_evolve). */
+rsf_status rsf_get_tile_stats(rsf_context *ctx, int tile, rsf_stats *out, double *s_hist,
+                              int cap);
+
 /* Synchronise the stream of the last evolution and report its statistics.
  * s_hist (host, may be NULL) receives up to `cap` per-iteration sums
  * sum|phi_{n+1} - phi_n| in double (the convergence reduction). */
 rsf_status rsf_get_stats(rsf_context *ctx, rsf_stats *out, double *s_hist, int cap);
 
 /* One zero-padded Gaussian convolution out = K * in (Sec. 3 kernel), the
- * separable passes the evolution uses.  in, out: device floats, distinct. */
+ * separable passes the evolution uses.  in, out: device floats, distinct;
+ * every dimension >= 3. */
 rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out,
                        int64_t nx, int64_t ny, int64_t nz, float sigma, void *stream);
 

@@ -1,11 +1,14 @@
 // C ABI of the RSF evolution library (declared in include/rsf.h): argument
-// validation, workspace layout, and the per-iteration launch sequence.
+// validation, batch planning and workspace layout, and the per-iteration
+// launch sequence.  A single volume is evolved as a batch of one tile.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,15 +16,36 @@
 #include "rsf.h"
 #include "rsf_internal.hpp"
 
+namespace {
+
+using rsf::Batch;
+using rsf::Coeffs;
+using rsf::Grid3;
+using rsf::Split;
+using rsf::Taps;
+using rsf::TileDesc;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+size_t elem_size(int dtype) { return dtype == RSF_F32 ? 4 : 2; }
+
+}  // namespace
+
 struct rsf_context {
     int device = 0;
     std::string err;
     void *ws = nullptr;          // owned workspace
     size_t ws_bytes = 0;
-    // last evolution, for rsf_get_stats
+    // pinned staging of the tile table, and the event of its last upload
+    void *stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
+    // last evolution, for rsf_get_stats / rsf_get_tile_stats
     hipStream_t last_stream = nullptr;
-    const double *last_hist = nullptr;
-    const int *last_flags = nullptr;
+    std::vector<const double *> last_hist;
+    std::vector<const int *> last_flags;
     int last_iters = 0;
     bool has_last = false;
     // per-pass event timing
@@ -33,45 +57,64 @@ struct rsf_context {
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<Rec> recs;
+    // autotuned splits by tile shape and radius
+    std::map<std::vector<int64_t>, Split> tuned;
 };
 
 namespace {
 
-using rsf::Grid3;
-using rsf::Taps;
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// P, Q: interleaved pairs of the storage type (the stage-1 z-convolved
-// fields, then alternately g1/g2 and their xy convolutions); KI: K*I.
-struct Layout {
-    size_t P, Q, KI, phiB, cx, cy, cz, partials, hist, flags, total;
+// Per-tile regions: the pair fields P and Q and K*I in the storage type, the
+// phi ping-pong buffer in float, K*1 edge tables, update partials, the
+// per-iteration history and two flags.
+struct TileLayout {
+    Grid3 g;
+    Split sp;
+    size_t P, Q, KI, phiB, cx, cy, cz, partials, hist, flags;
 };
 
-size_t elem_size(int dtype) { return dtype == RSF_F32 ? 4 : 2; }
+// Batch header (tile table and the three workgroup prefix tables) followed by
+// the tiles' regions.
+struct BatchLayout {
+    size_t descs, start_xy, start_z, start_u, table_bytes;
+    std::vector<TileLayout> tiles;
+    std::vector<int> pre_xy, pre_z, pre_u;
+    size_t total;
+};
 
-// Two pair fields and K*I in the storage type, the phi ping-pong buffer in
-// float, plus edge tables, partial sums, history and flags.
-Layout layout(int64_t nx, int64_t ny, int64_t nz, int iters, int storage)
+BatchLayout plan_layout(const rsf_tile *tiles, int n, int iters, int storage,
+                        const std::vector<Split> &splits)
 {
-    Layout L{};
-    const size_t n = (size_t)nx * ny * nz;
-    const size_t field = align_up(n * elem_size(storage));
-    const size_t pair = align_up(2 * n * elem_size(storage));
+    BatchLayout L;
     size_t off = 0;
-    L.P = off; off += pair;
-    L.Q = off; off += pair;
-    L.KI = off; off += field;
-    L.phiB = off; off += align_up(n * sizeof(float));
-    L.cx = off; off += align_up((size_t)nx * sizeof(float));
-    L.cy = off; off += align_up((size_t)ny * sizeof(float));
-    L.cz = off; off += align_up((size_t)nz * sizeof(float));
-    rsf::Grid3 g{(int)nx, (int)ny, (int)nz, nx * ny};
-    L.partials = off; off += align_up((size_t)rsf::u_blocks(g) * sizeof(double));
-    L.hist = off; off += align_up((size_t)(iters > 0 ? iters : 1) * sizeof(double));
-    L.flags = off; off += align_up(4 * sizeof(int));
+    L.descs = off; off += align_up(sizeof(TileDesc) * (size_t)n);
+    L.start_xy = off; off += align_up(sizeof(int) * (size_t)(n + 1));
+    L.start_z = off; off += align_up(sizeof(int) * (size_t)(n + 1));
+    L.start_u = off; off += align_up(sizeof(int) * (size_t)(n + 1));
+    L.table_bytes = off;
+    L.pre_xy.assign(1, 0);
+    L.pre_z.assign(1, 0);
+    L.pre_u.assign(1, 0);
+    for (int t = 0; t < n; ++t) {
+        TileLayout T{};
+        T.g = Grid3{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
+                    tiles[t].nx * tiles[t].ny};
+        T.sp = splits[t];
+        const size_t v = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz;
+        T.P = off; off += align_up(2 * v * elem_size(storage));
+        T.Q = off; off += align_up(2 * v * elem_size(storage));
+        T.KI = off; off += align_up(v * elem_size(storage));
+        T.phiB = off; off += align_up(v * sizeof(float));
+        T.cx = off; off += align_up((size_t)tiles[t].nx * sizeof(float));
+        T.cy = off; off += align_up((size_t)tiles[t].ny * sizeof(float));
+        T.cz = off; off += align_up((size_t)tiles[t].nz * sizeof(float));
+        T.partials = off; off += align_up((size_t)rsf::u_blocks(T.g, T.sp) * sizeof(double));
+        T.hist = off; off += align_up((size_t)(iters > 0 ? iters : 1) * sizeof(double));
+        T.flags = off; off += align_up(4 * sizeof(int));
+        L.pre_xy.push_back(L.pre_xy.back() + (int)rsf::xy_blocks(T.g, T.sp));
+        L.pre_z.push_back(L.pre_z.back() + (int)rsf::z_blocks(T.g, T.sp));
+        L.pre_u.push_back(L.pre_u.back() + (int)rsf::u_blocks(T.g, T.sp));
+        L.tiles.push_back(T);
+    }
     L.total = off;
     return L;
 }
@@ -104,9 +147,9 @@ rsf_status hip_fail(rsf_context *ctx, hipError_t e, const char *what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                              \
-    do {                                                 \
-        hipError_t e_ = (expr);                          \
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
 
@@ -175,6 +218,18 @@ rsf_status check_types(rsf_context *ctx, float sigma, int image, int storage)
     return RSF_OK;
 }
 
+rsf_status check_tiles(rsf_context *ctx, const rsf_tile *tiles, int n, bool need_pointers)
+{
+    if (!tiles || n < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "need at least one tile");
+    for (int t = 0; t < n; ++t) {
+        if (need_pointers && (!tiles[t].volume || !tiles[t].phi))
+            return fail(ctx, RSF_ERR_INVALID_ARG, "null volume or phi in tile " + std::to_string(t));
+        rsf_status st = check_dims(ctx, tiles[t].nx, tiles[t].ny, tiles[t].nz);
+        if (st != RSF_OK) return st;
+    }
+    return RSF_OK;
+}
+
 rsf_status set_device(rsf_context *ctx)
 {
     HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -191,6 +246,7 @@ rsf_status ensure_ws(rsf_context *ctx, size_t bytes)
         HIP_TRY(hipFree(ctx->ws), "hipFree");
         ctx->ws = nullptr;
         ctx->ws_bytes = 0;
+        ctx->has_last = false;   // its statistics lived in the freed buffer
     }
     void *p = nullptr;
     HIP_TRY(hipMalloc(&p, bytes), "hipMalloc(workspace)");
@@ -199,163 +255,262 @@ rsf_status ensure_ws(rsf_context *ctx, size_t bytes)
     return RSF_OK;
 }
 
+// Pinned staging for the tile table; waits for its previous upload first.
+rsf_status ensure_stage(rsf_context *ctx, size_t bytes)
+{
+    if (ctx->stage_pending) {
+        HIP_TRY(hipEventSynchronize(ctx->stage_ev), "hipEventSynchronize(stage)");
+        ctx->stage_pending = false;
+    }
+    if (!ctx->stage_ev)
+        HIP_TRY(hipEventCreateWithFlags(&ctx->stage_ev, hipEventDisableTiming),
+                "hipEventCreate(stage)");
+    if (ctx->stage_bytes >= bytes) return RSF_OK;
+    if (ctx->stage) HIP_TRY(hipHostFree(ctx->stage), "hipHostFree");
+    ctx->stage = nullptr;
+    ctx->stage_bytes = 0;
+    HIP_TRY(hipHostMalloc(&ctx->stage, bytes, hipHostMallocDefault), "hipHostMalloc(stage)");
+    ctx->stage_bytes = bytes;
+    return RSF_OK;
+}
+
+// A planned batch: device tile table plus the pass views.
 struct Plan {
-    Grid3 g;
+    int n;
     int R;
     int image, storage;
     Taps taps;
-    Layout L;
+    Coeffs c;
+    BatchLayout L;
     char *base;
-    void *P, *Q, *KI;
-    float *phiB, *cx, *cy, *cz;
-    double *partials, *hist;
-    int *flags;
+    TileDesc *descs;             // device
+    Batch xy, z, u, tile;
+    int64_t blocks_xy, blocks_z, blocks_u;
 };
 
-Plan make_plan(int64_t nx, int64_t ny, int64_t nz, float sigma, int iters, int image, int storage,
-               char *base)
+Coeffs make_coeffs(const rsf_params &p, double tol)
 {
-    Plan P{};
-    P.g = Grid3{(int)nx, (int)ny, (int)nz, nx * ny};
-    P.R = radius_of(sigma);
-    P.image = image;
-    P.storage = storage;
-    P.taps = make_taps(sigma, P.R);
-    P.L = layout(nx, ny, nz, iters, storage);
-    P.base = base;
-    auto F = [&](size_t off) { return reinterpret_cast<float *>(base + off); };
-    auto V = [&](size_t off) { return static_cast<void *>(base + off); };
-    P.P = V(P.L.P); P.Q = V(P.L.Q);
-    P.KI = V(P.L.KI); P.phiB = F(P.L.phiB);
-    P.cx = F(P.L.cx); P.cy = F(P.L.cy); P.cz = F(P.L.cz);
-    P.partials = reinterpret_cast<double *>(base + P.L.partials);
-    P.hist = reinterpret_cast<double *>(base + P.L.hist);
-    P.flags = reinterpret_cast<int *>(base + P.L.flags);
-    return P;
+    Coeffs c{};
+    c.l1 = p.lambda1; c.l2 = p.lambda2; c.nu = p.nu; c.mu = p.mu; c.dt = p.dt;
+    c.eps = p.eps;
+    c.eps_over_pi = (float)((double)p.eps / M_PI);
+    c.eps2 = p.eps * p.eps;
+    c.eta = p.eta > 0.f ? p.eta : 1e-10f;
+    c.reg = p.regulariser == RSF_REG_SINGLE_WELL ? 1 : 0;
+    c.tol = tol;
+    return c;
 }
 
-// Per-volume set-up: edge tables of K*1, flags, and K*I.
-rsf_status prologue(rsf_context *ctx, const Plan &P, const void *I, hipStream_t s)
+Split split_for(rsf_context *ctx, const Grid3 &g, int R)
+{
+    auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
+    if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) return it->second;
+    return rsf::default_split(g);
+}
+
+std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R)
+{
+    std::vector<Split> splits;
+    for (int t = 0; t < n; ++t) {
+        const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
+                      tiles[t].nx * tiles[t].ny};
+        splits.push_back(split_for(ctx, g, R));
+    }
+    return splits;
+}
+
+// Lay out the batch in `base`, upload its tile table, fill the pass views.
+// `probe` is for rsf_probe (one tile); `ki_out` for rsf_gauss3d.
+rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, int image,
+                     const rsf_params &p, double tol, int iters, char *base, hipStream_t s,
+                     const rsf_probe_fields *probe = nullptr, void *ki_out = nullptr)
+{
+    P.n = n;
+    P.R = radius_of(p.sigma);
+    P.image = image;
+    P.storage = p.storage;
+    P.taps = make_taps(p.sigma, P.R);
+    P.c = make_coeffs(p, tol);
+    P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R));
+    P.base = base;
+    rsf_status st = ensure_stage(ctx, P.L.table_bytes);
+    if (st != RSF_OK) return st;
+    char *h = static_cast<char *>(ctx->stage);
+    std::memset(h, 0, P.L.table_bytes);
+    TileDesc *hd = reinterpret_cast<TileDesc *>(h + P.L.descs);
+    for (int t = 0; t < n; ++t) {
+        const TileLayout &T = P.L.tiles[t];
+        TileDesc d{};
+        d.g = T.g;
+        d.sp = T.sp;
+        d.I = tiles[t].volume;
+        d.phi[0] = tiles[t].phi;
+        d.phi[1] = reinterpret_cast<float *>(base + T.phiB);
+        d.P = base + T.P;
+        d.Q = base + T.Q;
+        d.KI = ki_out ? ki_out : static_cast<void *>(base + T.KI);
+        d.cx = reinterpret_cast<float *>(base + T.cx);
+        d.cy = reinterpret_cast<float *>(base + T.cy);
+        d.cz = reinterpret_cast<float *>(base + T.cz);
+        d.partials = reinterpret_cast<double *>(base + T.partials);
+        d.hist = reinterpret_cast<double *>(base + T.hist);
+        d.hist_cap = iters > 0 ? iters : 1;
+        d.flags = reinterpret_cast<int *>(base + T.flags);
+        if (probe) {
+            d.probe_H = probe->H; d.probe_f1 = probe->f1; d.probe_f2 = probe->f2;
+            d.probe_Fd = probe->Fd; d.probe_kappa = probe->kappa; d.probe_lap = probe->lap;
+            d.probe_R = probe->R; d.probe_E = probe->E;
+            if (probe->phi_next) d.phi[1] = probe->phi_next;
+        }
+        hd[t] = d;
+    }
+    std::memcpy(h + P.L.start_xy, P.L.pre_xy.data(), sizeof(int) * (n + 1));
+    std::memcpy(h + P.L.start_z, P.L.pre_z.data(), sizeof(int) * (n + 1));
+    std::memcpy(h + P.L.start_u, P.L.pre_u.data(), sizeof(int) * (n + 1));
+    HIP_TRY(hipMemcpyAsync(base, h, P.L.table_bytes, hipMemcpyHostToDevice, s), "upload tile table");
+    HIP_TRY(hipEventRecord(ctx->stage_ev, s), "hipEventRecord(stage)");
+    ctx->stage_pending = true;
+    P.descs = reinterpret_cast<TileDesc *>(base + P.L.descs);
+    auto view = [&](size_t start) {
+        return Batch{P.descs, reinterpret_cast<const int *>(base + start), n, 0};
+    };
+    P.xy = view(P.L.start_xy);
+    P.z = view(P.L.start_z);
+    P.u = view(P.L.start_u);
+    P.tile = Batch{P.descs, nullptr, n, 0};
+    P.blocks_xy = P.L.pre_xy.back();
+    P.blocks_z = P.L.pre_z.back();
+    P.blocks_u = P.L.pre_u.back();
+    return RSF_OK;
+}
+
+// Per-batch set-up: K*1 edge tables, flags, and K*I.
+rsf_status prologue(rsf_context *ctx, const Plan &P, hipStream_t s)
 {
     HIP_TRY(timed(ctx, RSF_PASS_SETUP, s, [&] {
-                hipError_t e = rsf::launch_flags_init(P.flags, s);
-                if (e == hipSuccess) e = rsf::launch_edges(P.cx, P.cy, P.cz, P.g, P.taps, P.R, s);
+                hipError_t e = rsf::launch_setup(P.tile, P.taps, P.R, s);
                 if (e == hipSuccess)
-                    e = rsf::launch_xy(P.R, rsf::XY_ONE, P.image, P.storage, I, P.P, P.g, P.taps,
-                                       nullptr, nullptr, s);
+                    e = rsf::launch_xy(P.R, rsf::XY_ONE, P.image, P.storage, P.xy, P.blocks_xy,
+                                       P.taps, P.c, false, s);
                 if (e == hipSuccess)
-                    e = rsf::launch_z_plain(P.R, P.storage, P.P, P.KI, P.g, P.taps, s);
+                    e = rsf::launch_z_plain(P.R, P.storage, P.z, P.blocks_z, P.taps, s);
                 return e;
             }),
             "setup (K*1 tables, K*I)");
     return RSF_OK;
 }
 
-struct Probe {
-    float *H = nullptr, *f1 = nullptr, *f2 = nullptr, *Fd = nullptr, *kappa = nullptr,
-          *lap = nullptr, *R = nullptr, *E = nullptr;
-};
-
-// One iteration phi_cur -> phi_nxt; its sum |dphi| goes to hist_slot.
-rsf_status iteration(rsf_context *ctx, const Plan &P, const void *I, const float *cur,
-                     float *nxt, const rsf_params &p, double *hist_slot, double tol_total,
-                     const Probe &pr, hipStream_t s)
+// One iteration of every tile; par = which phi buffer holds the current iterate.
+rsf_status iteration(rsf_context *ctx, const Plan &P, int par, bool probe, hipStream_t s)
 {
-    const int *done = P.flags;
+    Batch z = P.z, u = P.u;
+    z.par = par;
+    u.par = par;
     HIP_TRY(timed(ctx, RSF_PASS_Z_HEAVISIDE, s, [&] {
-                return rsf::launch_z_heaviside(P.R, P.image, P.storage, cur, I, P.P, P.g, P.taps,
-                                               p.eps, pr.H, done, s);
+                return rsf::launch_z_heaviside(P.R, P.image, P.storage, z, P.blocks_z, P.taps,
+                                               P.c, probe, s);
             }),
             "z(H)");
-    rsf::FitArgs fa{P.KI, P.cx, P.cy, P.cz, p.lambda1, p.lambda2, pr.f1, pr.f2};
     HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_FITS, P.image, P.storage, P.P, P.Q, P.g,
-                                      P.taps, &fa, done, s);
+                return rsf::launch_xy(P.R, rsf::XY_FITS, P.image, P.storage, P.xy, P.blocks_xy,
+                                      P.taps, P.c, probe, s);
             }),
             "xy(fits)");
     HIP_TRY(timed(ctx, RSF_PASS_XY_FORCE, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_TWO, P.image, P.storage, P.Q, P.P, P.g,
-                                      P.taps, nullptr, done, s);
+                return rsf::launch_xy(P.R, rsf::XY_TWO, P.image, P.storage, P.xy, P.blocks_xy,
+                                      P.taps, P.c, probe, s);
             }),
             "xy(g)");
-    rsf::UpdArgs ua{};
-    ua.I = I;
-    ua.phi = cur;
-    ua.phi_out = nxt;
-    ua.cx = P.cx; ua.cy = P.cy; ua.cz = P.cz;
-    ua.l1 = p.lambda1; ua.l2 = p.lambda2; ua.nu = p.nu; ua.mu = p.mu; ua.dt = p.dt;
-    ua.eps_over_pi = (float)((double)p.eps / M_PI);
-    ua.eps2 = p.eps * p.eps;
-    ua.eta = p.eta > 0.f ? p.eta : 1e-10f;
-    ua.reg = p.regulariser == RSF_REG_SINGLE_WELL ? 1 : 0;
-    ua.partials = P.partials;
-    ua.probe_Fd = pr.Fd; ua.probe_kappa = pr.kappa; ua.probe_lap = pr.lap;
-    ua.probe_R = pr.R; ua.probe_E = pr.E;
-    HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s,
-                  [&] {
-                      return rsf::launch_z_update(P.R, P.image, P.storage, P.P, P.g, P.taps, ua,
-                                                  done, s);
-                  }),
-            "z(update)");
-    HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] {
-                return rsf::launch_reduce(P.partials, rsf::u_blocks(P.g), hist_slot, P.flags,
-                                          tol_total, s);
+    HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s, [&] {
+                return rsf::launch_z_update(P.R, P.image, P.storage, u, P.blocks_u, P.taps, P.c,
+                                            probe, s);
             }),
+            "z(update)");
+    HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] { return rsf::launch_reduce(P.tile, P.c, s); }),
             "reduce");
     return RSF_OK;
 }
 
-rsf_status evolve_impl(rsf_context *ctx, const void *volume, int vdt, float *phi, int64_t nx,
-                       int64_t ny, int64_t nz, const rsf_params &p, int iters, double tol,
-                       void *workspace, size_t ws_bytes, void *stream)
+rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
+                       const rsf_params &p, int iters, double tol, void *workspace,
+                       size_t ws_bytes, void *stream)
 {
     if (!ctx) return RSF_ERR_INVALID_ARG;
     ctx->err.clear();
-    if (!volume || !phi) return fail(ctx, RSF_ERR_INVALID_ARG, "null volume or phi");
-    rsf_status st = check_dims(ctx, nx, ny, nz);
+    rsf_status st = check_tiles(ctx, tiles, n, true);
     if (st != RSF_OK) return st;
     st = check_params(ctx, p);
     if (st != RSF_OK) return st;
     st = check_types(ctx, p.sigma, vdt, p.storage);
     if (st != RSF_OK) return st;
     if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
-    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(ctx, RSF_ERR_INVALID_ARG, "tol must be >= 0");
-    const Layout L = layout(nx, ny, nz, iters, p.storage);
-    if (workspace && ws_bytes < L.total)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
-    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (!(tol >= 0.0) || !std::isfinite(tol))
+        return fail(ctx, RSF_ERR_INVALID_ARG, "tol must be >= 0");
     st = set_device(ctx);
     if (st != RSF_OK) return st;
+    const size_t need =
+        plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, radius_of(p.sigma)))
+            .total;
+    if (workspace && ws_bytes < need) return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (!workspace) {
-        st = ensure_ws(ctx, L.total);
+        st = ensure_ws(ctx, need);
         if (st != RSF_OK) return st;
     }
     char *base = static_cast<char *>(workspace ? workspace : ctx->ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Plan P = make_plan(nx, ny, nz, p.sigma, iters, vdt, p.storage, base);
-    const void *I = volume;
-
-    st = prologue(ctx, P, I, s);
+    Plan P;
+    st = make_plan(ctx, P, tiles, n, vdt, p, tol, iters, base, s);
     if (st != RSF_OK) return st;
-    const double tol_total = tol * (double)nx * ny * nz;
-    float *cur = phi, *nxt = P.phiB;
+    st = prologue(ctx, P, s);
+    if (st != RSF_OK) return st;
     for (int it = 0; it < iters; ++it) {
-        st = iteration(ctx, P, I, cur, nxt, p, P.hist + it, tol_total, Probe{}, s);
+        st = iteration(ctx, P, it & 1, false, s);
         if (st != RSF_OK) return st;
-        float *t = cur;
-        cur = nxt;
-        nxt = t;
     }
-    if (cur != phi)
-        HIP_TRY(hipMemcpyAsync(phi, cur, (size_t)nx * ny * nz * sizeof(float),
-                               hipMemcpyDeviceToDevice, s),
-                "copy phi");
+    if (iters & 1) {
+        // the last iterate is in the workspace buffer
+        for (int t = 0; t < n; ++t) {
+            const size_t bytes = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float);
+            HIP_TRY(hipMemcpyAsync(tiles[t].phi, base + P.L.tiles[t].phiB, bytes,
+                                   hipMemcpyDeviceToDevice, s),
+                    "copy phi");
+        }
+    }
     ctx->last_stream = s;
-    ctx->last_hist = P.hist;
-    ctx->last_flags = P.flags;
+    ctx->last_hist.clear();
+    ctx->last_flags.clear();
+    for (int t = 0; t < n; ++t) {
+        ctx->last_hist.push_back(reinterpret_cast<const double *>(base + P.L.tiles[t].hist));
+        ctx->last_flags.push_back(reinterpret_cast<const int *>(base + P.L.tiles[t].flags));
+    }
     ctx->last_iters = iters;
     ctx->has_last = true;
+    return RSF_OK;
+}
+
+// Time `iters` iterations of a planned batch (after its prologue) in ms.
+rsf_status time_iterations(rsf_context *ctx, const Plan &P, int iters, hipStream_t s, float *ms)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(ctx, e, "hipEventCreate");
+    }
+    rsf_status st = RSF_OK;
+    e = hipEventRecord(a, s);
+    for (int it = 0; st == RSF_OK && e == hipSuccess && it < iters; ++it)
+        st = iteration(ctx, P, it & 1, false, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != RSF_OK) return st;
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune timing");
     return RSF_OK;
 }
 
@@ -366,6 +521,38 @@ rsf_params default_params(float sigma, float l1, float l2, float nu, float mu, f
     p.sigma = sigma; p.lambda1 = l1; p.lambda2 = l2; p.nu = nu; p.mu = mu; p.dt = dt;
     p.eps = eps; p.eta = 1e-10f; p.regulariser = RSF_REG_DOUBLE_WELL; p.storage = RSF_F32;
     return p;
+}
+
+rsf_status tile_stats(rsf_context *ctx, int tile, rsf_stats *out, double *s_hist, int cap)
+{
+    if (!ctx || !out) return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
+    if (!ctx->has_last) return fail(ctx, RSF_ERR_INVALID_ARG, "no evolution has run");
+    if (tile < 0 || tile >= (int)ctx->last_hist.size())
+        return fail(ctx, RSF_ERR_INVALID_ARG, "tile index out of range");
+    rsf_status st = set_device(ctx);
+    if (st != RSF_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->last_stream), "hipStreamSynchronize");
+    int flags[2] = {0, 0};
+    HIP_TRY(hipMemcpy(flags, ctx->last_flags[tile], sizeof(flags), hipMemcpyDeviceToHost),
+            "copy flags");
+    out->iters_requested = ctx->last_iters;
+    out->iters_run = flags[1];
+    out->last_sum_abs = 0.0;
+    const int n = flags[1];
+    if (n > 0) {
+        HIP_TRY(hipMemcpy(&out->last_sum_abs, ctx->last_hist[tile] + (n - 1), sizeof(double),
+                          hipMemcpyDeviceToHost),
+                "copy last sum");
+    }
+    if (s_hist && cap > 0 && n > 0) {
+        const int m = cap < n ? cap : n;
+        HIP_TRY(hipMemcpy(s_hist, ctx->last_hist[tile], (size_t)m * sizeof(double),
+                          hipMemcpyDeviceToHost),
+                "copy history");
+    }
+    if (!std::isfinite(out->last_sum_abs))
+        return fail(ctx, RSF_ERR_NONFINITE, "non-finite sum |dphi|");
+    return RSF_OK;
 }
 
 }  // namespace
@@ -395,8 +582,10 @@ void rsf_destroy(rsf_context *ctx)
     if (!ctx) return;
     try {
         (void)hipSetDevice(ctx->device);
-        if (ctx->ws || !ctx->ev_pool.empty()) (void)hipDeviceSynchronize();
+        if (ctx->ws || !ctx->ev_pool.empty() || ctx->stage) (void)hipDeviceSynchronize();
         if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->stage) (void)hipHostFree(ctx->stage);
+        if (ctx->stage_ev) (void)hipEventDestroy(ctx->stage_ev);
         for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     } catch (...) {
     }
@@ -440,11 +629,29 @@ const char *rsf_last_error(const rsf_context *ctx)
     return ctx->err.c_str();
 }
 
+size_t rsf_batch_workspace_bytes(const rsf_tile *tiles, int n, int iters, int storage)
+{
+    try {
+        if (!tiles || n < 1 || iters < 0) return 0;
+        if (storage != RSF_F32 && storage != RSF_F16 && storage != RSF_BF16) return 0;
+        std::vector<Split> splits;
+        for (int t = 0; t < n; ++t) {
+            if (tiles[t].nx < 3 || tiles[t].ny < 3 || tiles[t].nz < 3) return 0;
+            const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
+                          tiles[t].nx * tiles[t].ny};
+            splits.push_back(rsf::default_split(g));
+        }
+        return plan_layout(tiles, n, iters, storage, splits).total;
+    } catch (...) {
+        return 0;
+    }
+}
+
 size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters, int storage)
 {
-    if (nx < 1 || ny < 1 || nz < 1) return 0;
-    if (storage != RSF_F32 && storage != RSF_F16 && storage != RSF_BF16) return 0;
-    return layout(nx, ny, nz, iters, storage).total;
+    rsf_tile t{};
+    t.nx = nx; t.ny = ny; t.nz = nz;
+    return rsf_batch_workspace_bytes(&t, 1, iters, storage);
 }
 
 rsf_status rsf_evolve(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
@@ -454,8 +661,8 @@ rsf_status rsf_evolve(rsf_context *ctx, const void *volume, int volume_dtype, fl
 {
     try {
         const rsf_params p = default_params(sigma, lambda1, lambda2, nu, mu, dt, eps);
-        return evolve_impl(ctx, volume, volume_dtype, phi, nx, ny, nz, p, iters, 0.0, nullptr, 0,
-                           stream);
+        rsf_tile t{volume, phi, nx, ny, nz};
+        return evolve_impl(ctx, &t, 1, volume_dtype, p, iters, 0.0, nullptr, 0, stream);
     } catch (const std::bad_alloc &) {
         return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
@@ -469,8 +676,24 @@ rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype,
 {
     try {
         if (!params) return fail(ctx, RSF_ERR_INVALID_ARG, "null params");
-        return evolve_impl(ctx, volume, volume_dtype, phi, nx, ny, nz, *params, iters, tol,
-                           workspace, workspace_bytes, stream);
+        rsf_tile t{volume, phi, nx, ny, nz};
+        return evolve_impl(ctx, &t, 1, volume_dtype, *params, iters, tol, workspace,
+                           workspace_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+rsf_status rsf_evolve_batch(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                            int volume_dtype, const rsf_params *params, int iters, double tol,
+                            void *workspace, size_t workspace_bytes, void *stream)
+{
+    try {
+        if (!params) return fail(ctx, RSF_ERR_INVALID_ARG, "null params");
+        return evolve_impl(ctx, tiles, n_tiles, volume_dtype, *params, iters, tol, workspace,
+                           workspace_bytes, stream);
     } catch (const std::bad_alloc &) {
         return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
@@ -481,35 +704,121 @@ rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype,
 rsf_status rsf_get_stats(rsf_context *ctx, rsf_stats *out, double *s_hist, int cap)
 {
     try {
-        if (!ctx || !out) return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
-        if (!ctx->has_last) return fail(ctx, RSF_ERR_INVALID_ARG, "no evolution has run");
-        rsf_status st = set_device(ctx);
-        if (st != RSF_OK) return st;
-        HIP_TRY(hipStreamSynchronize(ctx->last_stream), "hipStreamSynchronize");
-        int flags[2] = {0, 0};
-        HIP_TRY(hipMemcpy(flags, ctx->last_flags, sizeof(flags), hipMemcpyDeviceToHost),
-                "copy flags");
-        out->iters_requested = ctx->last_iters;
-        out->iters_run = flags[1];
-        out->last_sum_abs = 0.0;
-        const int n = flags[1];
-        if (n > 0) {
-            HIP_TRY(hipMemcpy(&out->last_sum_abs, ctx->last_hist + (n - 1), sizeof(double),
-                              hipMemcpyDeviceToHost),
-                    "copy last sum");
-            if (!std::isfinite(out->last_sum_abs))
-                (void)fail(ctx, RSF_ERR_NONFINITE, "non-finite sum |dphi|");
-        }
-        if (s_hist && cap > 0 && n > 0) {
-            const int m = cap < n ? cap : n;
-            HIP_TRY(hipMemcpy(s_hist, ctx->last_hist, (size_t)m * sizeof(double),
-                              hipMemcpyDeviceToHost),
-                    "copy history");
-        }
-        return std::isfinite(out->last_sum_abs) ? RSF_OK : RSF_ERR_NONFINITE;
+        return tile_stats(ctx, 0, out, s_hist, cap);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
+}
+
+rsf_status rsf_get_tile_stats(rsf_context *ctx, int tile, rsf_stats *out, double *s_hist,
+                              int cap)
+{
+    try {
+        return tile_stats(ctx, tile, out, s_hist, cap);
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
+                        const rsf_params *params, int trial_iters, void *stream)
+{
+    float *scratch = nullptr;
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (!params) return fail(ctx, RSF_ERR_INVALID_ARG, "null params");
+        rsf_status st = check_tiles(ctx, tiles, n_tiles, true);
+        if (st != RSF_OK) return st;
+        st = check_params(ctx, *params);
+        if (st != RSF_OK) return st;
+        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        if (st != RSF_OK) return st;
+        if (trial_iters < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "trial_iters must be >= 1");
+        st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int R = radius_of(params->sigma);
+        // trials evolve copies of phi, never the caller's
+        size_t total = 0;
+        std::vector<size_t> off;
+        for (int t = 0; t < n_tiles; ++t) {
+            off.push_back(total);
+            total += align_up((size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float));
+        }
+        HIP_TRY(hipMalloc(&scratch, total), "hipMalloc(autotune scratch)");
+        std::vector<rsf_tile> tt(tiles, tiles + n_tiles);
+        for (int t = 0; t < n_tiles; ++t) {
+            tt[t].phi = reinterpret_cast<float *>(reinterpret_cast<char *>(scratch) + off[t]);
+            const size_t bytes = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float);
+            hipError_t e = hipMemcpyAsync(tt[t].phi, tiles[t].phi, bytes, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) {
+                (void)hipFree(scratch);
+                return hip_fail(ctx, e, "autotune copy");
+            }
+        }
+        // coordinate search over the three per-pass workgroup targets
+        const int64_t cand_xy[] = {4096, 8192, 16384, 32768};
+        const int64_t cand_z[] = {1024, 2048, 4096};
+        const int64_t cand_u[] = {512, 1024, 2048};
+        int64_t best[3] = {16384, 2048, 1024};
+        auto apply = [&](const int64_t tg[3]) {
+            for (int t = 0; t < n_tiles; ++t) {
+                const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
+                              tiles[t].nx * tiles[t].ny};
+                ctx->tuned[{g.nx, g.ny, g.nz, R}] = rsf::make_split(g, tg[0], tg[1], tg[2]);
+            }
+        };
+        float best_ms = -1.f;
+        for (int axis = 0; axis < 3; ++axis) {
+            const int64_t *cands = axis == 0 ? cand_xy : (axis == 1 ? cand_z : cand_u);
+            const int nc = axis == 0 ? 4 : 3;
+            int64_t keep = best[axis];
+            for (int c = 0; c < nc; ++c) {
+                int64_t tg[3] = {best[0], best[1], best[2]};
+                tg[axis] = cands[c];
+                apply(tg);
+                // one warm-up iteration, then the timed ones
+                const int runs = trial_iters + 1;
+                const size_t need =
+                    plan_layout(tt.data(), n_tiles, runs, params->storage,
+                                splits_for(ctx, tt.data(), n_tiles, R)).total;
+                st = ensure_ws(ctx, need);
+                if (st != RSF_OK) break;
+                ctx->has_last = false;   // the trials overwrite the workspace
+                Plan P;
+                st = make_plan(ctx, P, tt.data(), n_tiles, volume_dtype, *params, 0.0, runs,
+                               static_cast<char *>(ctx->ws), s);
+                if (st == RSF_OK) st = prologue(ctx, P, s);
+                float ms = 0.f;
+                if (st == RSF_OK) st = iteration(ctx, P, 0, false, s);   // warm-up
+                if (st == RSF_OK) st = time_iterations(ctx, P, trial_iters, s, &ms);
+                if (st != RSF_OK) break;
+                if (best_ms < 0.f || ms < best_ms) {
+                    best_ms = ms;
+                    keep = cands[c];
+                }
+            }
+            if (st != RSF_OK) break;
+            best[axis] = keep;
+        }
+        if (st == RSF_OK) apply(best);
+        else {
+            for (int t = 0; t < n_tiles; ++t)
+                ctx->tuned.erase({tiles[t].nx, tiles[t].ny, tiles[t].nz, R});
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(scratch);
+        return st;
+    } catch (...) {
+        if (scratch) (void)hipFree(scratch);
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+void rsf_autotune_reset(rsf_context *ctx)
+{
+    if (ctx) ctx->tuned.clear();
 }
 
 rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx, int64_t ny,
@@ -519,25 +828,25 @@ rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx
         if (!ctx) return RSF_ERR_INVALID_ARG;
         ctx->err.clear();
         if (!in || !out || in == out) return fail(ctx, RSF_ERR_INVALID_ARG, "bad in/out pointers");
-        if (nx < 1 || ny < 1 || nz < 1 || nx * ny > ((int64_t)1 << 31))
-            return fail(ctx, RSF_ERR_INVALID_ARG, "bad dimensions");
+        rsf_status st = check_dims(ctx, nx, ny, nz);
+        if (st != RSF_OK) return st;
         if (!std::isfinite(sigma) || !(sigma > 0.f) || radius_of(sigma) > rsf::kMaxR)
             return fail(ctx, RSF_ERR_INVALID_ARG, "sigma must be > 0 with ceil(3 sigma) <= 16");
-        rsf_status st = set_device(ctx);
+        st = set_device(ctx);
         if (st != RSF_OK) return st;
-        const size_t need = align_up((size_t)nx * ny * nz * sizeof(float));
-        st = ensure_ws(ctx, need);
+        // the K*I prologue of a one-tile batch with I = in and K*I -> out
+        rsf_tile t{in, nullptr, nx, ny, nz};
+        const rsf_params p = default_params(sigma, 1, 1, 0, 0, 1, 1);
+        st = ensure_ws(ctx, plan_layout(&t, 1, 0, RSF_F32,
+                                        splits_for(ctx, &t, 1, radius_of(sigma)))
+                                .total);
         if (st != RSF_OK) return st;
-        const Grid3 g{(int)nx, (int)ny, (int)nz, nx * ny};
-        const int R = radius_of(sigma);
-        const Taps t = make_taps(sigma, R);
-        float *tmp = static_cast<float *>(ctx->ws);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        HIP_TRY(rsf::launch_xy(R, rsf::XY_ONE, RSF_F32, RSF_F32, in, tmp, g, t, nullptr, nullptr,
-                               s),
-                "xy");
-        HIP_TRY(rsf::launch_z_plain(R, RSF_F32, tmp, out, g, t, s), "z");
-        return RSF_OK;
+        Plan P;
+        st = make_plan(ctx, P, &t, 1, RSF_F32, p, 0.0, 0, static_cast<char *>(ctx->ws), s,
+                       nullptr, out);
+        if (st != RSF_OK) return st;
+        return prologue(ctx, P, s);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
@@ -560,20 +869,20 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
         if (st != RSF_OK) return st;
         st = set_device(ctx);
         if (st != RSF_OK) return st;
-        const Layout L = layout(nx, ny, nz, 1, params->storage);
-        st = ensure_ws(ctx, L.total);
+        // phi is only read: the update writes into phi_next (or the workspace)
+        rsf_tile t{volume, const_cast<float *>(phi), nx, ny, nz};
+        st = ensure_ws(ctx, plan_layout(&t, 1, 1, params->storage,
+                                        splits_for(ctx, &t, 1, radius_of(params->sigma)))
+                                .total);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const Plan P = make_plan(nx, ny, nz, params->sigma, 1, volume_dtype, params->storage,
-                                 static_cast<char *>(ctx->ws));
-        const void *I = volume;
-        st = prologue(ctx, P, I, s);
+        Plan P;
+        st = make_plan(ctx, P, &t, 1, volume_dtype, *params, 0.0, 1,
+                       static_cast<char *>(ctx->ws), s, fields);
         if (st != RSF_OK) return st;
-        Probe pr;
-        pr.H = fields->H; pr.f1 = fields->f1; pr.f2 = fields->f2; pr.Fd = fields->Fd;
-        pr.kappa = fields->kappa; pr.lap = fields->lap; pr.R = fields->R; pr.E = fields->E;
-        float *nxt = fields->phi_next ? fields->phi_next : P.phiB;
-        return iteration(ctx, P, I, phi, nxt, *params, P.hist, 0.0, pr, s);
+        st = prologue(ctx, P, s);
+        if (st != RSF_OK) return st;
+        return iteration(ctx, P, 0, true, s);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }

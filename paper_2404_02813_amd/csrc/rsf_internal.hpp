@@ -1,5 +1,10 @@
-// Internal declarations shared by the kernels (rsf_kernels.hip) and the
-// C-ABI host code (rsf_api.hip).  gfx950 only.
+// Internal declarations shared by the kernels (rsf_kernels.hpp / .hip) and
+// the C-ABI host code (rsf_api.hip).  gfx950 only.
+//
+// Every pass runs over a batch of tiles (independent volumes); a single
+// volume is a batch of one.  A pass launches one grid for the whole batch:
+// each tile owns a contiguous range of the pass's workgroups, found from a
+// prefix table, so uneven tiles share one launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +22,11 @@ constexpr int kUx = 64;            // update pass: columns per block along x
 constexpr int kUy = 8;             // update pass: columns per block along y
 constexpr int kUThreads = kUx * kUy;
 
+// Image/storage combinations other than (F32, F32) are built for radii
+// kMinRMixed..kMaxRMixed.
+constexpr int kMinRMixed = 4;
+constexpr int kMaxRMixed = 12;
+
 // Sampled, truncated, unit-sum Gaussian taps w[k + R], k = -R..R.
 struct Taps {
     float w[2 * kMaxR + 1];
@@ -27,82 +37,107 @@ struct Grid3 {
     int64_t sxy;  // nx * ny
 };
 
-// Epilogue of the stage-1 xy pass: region fits and the two force-convolution
-// inputs g1 = l1 f1 - l2 f2, g2 = l1 f1^2 - l2 f2^2.
-struct FitArgs {
-    const void *KI;               // K * I, in the storage type
-    const float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
-    float l1, l2;
-    float *probe_f1, *probe_f2;   // optional
+// How each pass cuts a tile into workgroups: row chunks of the xy passes,
+// z chunks of the stage-1 z pass and of the update pass.
+struct Split {
+    int xy, z, u;
 };
 
-// Epilogue of the stage-2 z pass: force, curvature, regulariser, update.
-struct UpdArgs {
-    const void *I;                // image, in the image type
-    const float *phi;             // phi_n
-    float *phi_out;               // phi_{n+1}
-    const float *cx, *cy, *cz;
+// One tile of a batch as the kernels see it (device pointers).
+struct TileDesc {
+    Grid3 g;
+    Split sp;
+    const void *I;          // image, in the image type
+    float *phi[2];          // phi ping-pong: [0] the caller's buffer, [1] workspace
+    void *P, *Q;            // interleaved pair fields, storage type
+    void *KI;               // K * I, storage type
+    float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
+    double *partials;       // one sum |dphi| per update-pass block
+    double *hist;           // sum |dphi| per iteration run
+    int hist_cap;           // entries of hist
+    int *flags;             // [0] stopped early, [1] iterations run
+    // one-step probe outputs (float fields), null when unused
+    float *probe_H, *probe_f1, *probe_f2, *probe_Fd, *probe_kappa, *probe_lap, *probe_R,
+        *probe_E;
+};
+
+// Scalars shared by every tile of a batch.
+struct Coeffs {
     float l1, l2, nu, mu, dt;
-    float eps_over_pi, eps2;      // delta = eps_over_pi / (eps2 + phi^2)
+    float eps, eps_over_pi, eps2;   // delta = eps_over_pi / (eps2 + phi^2)
     float eta;
-    int reg;                      // 0 double well, 1 single well
-    double *partials;             // one sum|dphi| per block
-    float *probe_Fd, *probe_kappa, *probe_lap, *probe_R, *probe_E;
+    int reg;                        // 0 double well, 1 single well
+    double tol;                     // stop a tile once sum|dphi| / voxels < tol (0: never)
 };
 
-// Number of z chunks a z pass splits the volume into (also sizes the
-// per-block partial sums of the update pass).
-int z_chunks(const Grid3 &g);
-int64_t z_blocks(const Grid3 &g);
-int u_chunks(const Grid3 &g);
-int64_t u_blocks(const Grid3 &g);   // blocks (and partial sums) of the update pass
-int xy_chunks(const Grid3 &g);
-int xy_blocks(const Grid3 &g);
+// A pass over a batch: the tiles, the pass's workgroup prefix table (n + 1
+// entries: tile t owns workgroups [start[t], start[t+1])), and which phi
+// buffer holds the current iterate.
+struct Batch {
+    const TileDesc *tiles;
+    const int *start;
+    int n;
+    int par;
+};
 
-hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,
-                        hipStream_t s);
-hipError_t launch_flags_init(int *flags, hipStream_t s);
+// Workgroup counts of one tile under a split.
+__host__ __device__ inline int nbx64(int nx) { return (nx + 63) / 64; }
+__host__ __device__ inline int64_t xy_blocks(const Grid3 &g, const Split &s)
+{
+    return (int64_t)nbx64(g.nx) * s.xy * g.nz;
+}
+__host__ __device__ inline int64_t z_blocks(const Grid3 &g, const Split &s)
+{
+    return (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy) * s.z;
+}
+__host__ __device__ inline int64_t u_blocks(const Grid3 &g, const Split &s)
+{
+    return (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy) * s.u;
+}
 
-// Element types (values of rsf_dtype): image RSF_F32 or RSF_U16, storage of
-// the intermediate fields RSF_F32, RSF_F16 or RSF_BF16.  Combinations other
-// than (F32, F32) are built for radii kMinRMixed..kMaxRMixed.
-constexpr int kMinRMixed = 4;
-constexpr int kMaxRMixed = 12;
+// Split of one volume aiming at the given workgroup counts per pass (the
+// autotuner varies them); every chunk is non-empty and at least 8 long.
+Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_target);
+Split default_split(const Grid3 &g);
+bool split_valid(const Grid3 &g, const Split &s);
+
 bool types_supported(int R, int image_dtype, int storage_dtype);
 
-// xy pass modes: one field; two fields; two fields + region-fit epilogue.
+// xy pass modes: XY_ONE reads the image and writes one field (P), for K*I;
+// XY_FITS reads the pair P and K*I and writes the pair Q; XY_TWO reads the
+// pair Q and writes the pair P.
 enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2 };
-// XY_ONE reads one field of the image type and writes one field of the
-// storage type; XY_TWO and XY_FITS read and write interleaved pairs of the
-// storage type.
-hipError_t launch_xy(int R, int mode, int image_dtype, int storage_dtype, const void *in,
-                     void *out, Grid3 g, const Taps &t, const FitArgs *fa, const int *done,
-                     hipStream_t s);
-hipError_t launch_z_plain(int R, int storage_dtype, const void *in, void *out, Grid3 g,
+
+// One workgroup per tile: K*1 edge tables, flags cleared.
+hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s);
+hipError_t launch_xy(int R, int mode, int image_dtype, int storage_dtype, const Batch &b,
+                     int64_t blocks, const Taps &t, const Coeffs &c, bool probe, hipStream_t s);
+// K*I: the z pass of P into KI.
+hipError_t launch_z_plain(int R, int storage_dtype, const Batch &b, int64_t blocks,
                           const Taps &t, hipStream_t s);
-// Stage-1 z pass: (phi, I) -> the pair (Kz*(H I), Kz*H).
-hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const float *phi,
-                              const void *I, void *pair_out, Grid3 g, const Taps &t, float eps,
-                              float *probeH, const int *done, hipStream_t s);
-// Stage-2 z pass + update from the pair (Kxy*g1, Kxy*g2).
-hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const void *pair_in,
-                           Grid3 g, const Taps &t, const UpdArgs &ua, const int *done,
+// Stage-1 z pass: (phi, I) -> the pair P = (Kz*(H I), Kz*H).
+hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const Batch &b,
+                              int64_t blocks, const Taps &t, const Coeffs &c, bool probe,
+                              hipStream_t s);
+// Stage-2 z pass of the pair P = (Kxy*g1, Kxy*g2) and the update into the
+// other phi buffer, with per-block |dphi| partial sums.
+hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const Batch &b,
+                           int64_t blocks, const Taps &t, const Coeffs &c, bool probe,
                            hipStream_t s);
-hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,
-                         double tol_total, hipStream_t s);
+// One workgroup per tile: fixed-order FP64 sum of the partials.
+hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s);
 
 // Per-radius, per-type launchers behind the dispatchers (rsf_kernels.hpp).
 template <int R, class IT, class ST>
-hipError_t launch_xy_r(int mode, const void *in, void *out, Grid3 g, const Taps &t,
-                       const FitArgs *fa, const int *done, hipStream_t s);
+hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                       bool probe, hipStream_t s);
 template <int R, class ST>
-hipError_t launch_z_plain_r(const void *in, void *out, Grid3 g, const Taps &t, hipStream_t s);
+hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, hipStream_t s);
 template <int R, class IT, class ST>
-hipError_t launch_z_heaviside_r(const float *phi, const void *I, void *pair_out, Grid3 g,
-                                const Taps &t, float eps, float *probeH, const int *done,
-                                hipStream_t s);
+hipError_t launch_z_heaviside_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                                bool probe, hipStream_t s);
 template <int R, class IT, class ST>
-hipError_t launch_z_update_r(const void *pair_in, Grid3 g, const Taps &t, const UpdArgs &ua,
-                             const int *done, hipStream_t s);
+hipError_t launch_z_update_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                             bool probe, hipStream_t s);
 
 }  // namespace rsf

@@ -12,11 +12,13 @@
 //   reduce   : fixed-order FP64 sum of the partials.
 // The separable Gaussian is applied as z passes (each thread marches one
 // (x, y) column through a z chunk with a register ring of 2R+1 slices) and xy
-// passes (LDS tile with an R halo, x then y), so every global access is
-// coalesced along x.  Stage 1 runs z first, so H_eps is evaluated once per
-// voxel; stage 2 runs z last, so the update sees the z window it needs.
-// Workgroups are handed to tiles so that each of the 8 XCDs works on one
-// contiguous range of tiles, keeping halo re-reads within one L2.
+// passes (a wave marches a 64-wide strip down a row chunk: rows staged in LDS
+// and x-convolved, a register ring of 2R+1 rows for y), so every global
+// access is coalesced along x.  Stage 1 runs z first, so H_eps is evaluated
+// once per voxel; stage 2 runs z last, so the update sees the z window it
+// needs.  Every pass is one launch over a batch of tiles; workgroups are
+// numbered so that each of the 8 XCDs works on one contiguous range, keeping
+// halo re-reads within one L2.
 #include "rsf_internal.hpp"
 
 namespace rsf {
@@ -24,41 +26,38 @@ namespace rsf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Tables and flags
+// Per-tile set-up and reduction (one workgroup per tile)
 // ---------------------------------------------------------------------------
 
-// K * 1 = cx[x] cy[y] cz[z]: partial sums of the taps that land inside.
-__global__ __launch_bounds__(kThreads) void edges_kernel(float *cx, float *cy, float *cz,
-                                                         Grid3 g, Taps t, int R)
+// K * 1 = cx[x] cy[y] cz[z]: partial sums of the taps that land inside; the
+// tile's flags cleared.
+__global__ __launch_bounds__(kThreads) void setup_kernel(Batch bt, Taps t, int R)
 {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    int n, p;
-    float *dst;
-    if (i < g.nx) { n = g.nx; p = i; dst = cx; }
-    else if (i < g.nx + g.ny) { n = g.ny; p = i - g.nx; dst = cy; }
-    else if (i < g.nx + g.ny + g.nz) { n = g.nz; p = i - g.nx - g.ny; dst = cz; }
-    else return;
-    float acc = 0.f;
-    for (int k = -R; k <= R; ++k)
-        if (p + k >= 0 && p + k < n) acc += t.w[k + R];
-    dst[p] = acc;
+    const TileDesc &d = bt.tiles[blockIdx.x];
+    const Grid3 g = d.g;
+    if (threadIdx.x < 2) d.flags[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < g.nx + g.ny + g.nz; i += kThreads) {
+        int n, p;
+        float *dst;
+        if (i < g.nx) { n = g.nx; p = i; dst = d.cx; }
+        else if (i < g.nx + g.ny) { n = g.ny; p = i - g.nx; dst = d.cy; }
+        else { n = g.nz; p = i - g.nx - g.ny; dst = d.cz; }
+        float acc = 0.f;
+        for (int k = -R; k <= R; ++k)
+            if (p + k >= 0 && p + k < n) acc += t.w[k + R];
+        dst[p] = acc;
+    }
 }
 
-// flags[0] = early-stop flag, flags[1] = iterations run.
-__global__ void flags_init_kernel(int *flags)
+// Fixed-order FP64 sum of one tile's update-pass partials into hist[iters
+// run]; sets the tile's stop flag when the tolerance is met.
+__global__ __launch_bounds__(kThreads) void reduce_kernel(Batch bt, Coeffs c)
 {
-    if (threadIdx.x < 2) flags[threadIdx.x] = 0;
-}
-
-// Fixed-order FP64 sum of the per-block partials; sets the early-stop flag.
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const double *__restrict__ partials,
-                                                          int64_t n, double *__restrict__ out,
-                                                          int *__restrict__ flags,
-                                                          double tol_total)
-{
-    if (flags[0]) return;
+    const TileDesc &d = bt.tiles[blockIdx.x];
+    if (d.flags[0]) return;
+    const int64_t n = u_blocks(d.g, d.sp);
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kThreads) acc += partials[i];
+    for (int64_t i = threadIdx.x; i < n; i += kThreads) acc += d.partials[i];
     __shared__ double sh[kThreads];
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -67,20 +66,22 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const double *__restri
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        *out = sh[0];
-        flags[1] += 1;
-        if (tol_total > 0.0 && sh[0] < tol_total) flags[0] = 1;
+        const int k = d.flags[1];
+        if (k < d.hist_cap) d.hist[k] = sh[0];
+        d.flags[1] = k + 1;
+        const double voxels = (double)d.g.nx * d.g.ny * d.g.nz;
+        if (c.tol > 0.0 && sh[0] < c.tol * voxels) d.flags[0] = 1;
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Splits
 // ---------------------------------------------------------------------------
 
-// Split n into the fewest chunks giving at least `want` blocks over `cols`
-// columns, each chunk at least `least` long; every chunk is non-empty.
+// The fewest chunks giving at least `want_blocks` over `cols` columns, each
+// chunk at least `least` long; re-derived so every chunk is non-empty.
 static int chunks(int64_t n, int64_t cols, int64_t want_blocks, int64_t least)
 {
     int64_t want = (want_blocks + cols - 1) / cols;
@@ -91,54 +92,54 @@ static int chunks(int64_t n, int64_t cols, int64_t want_blocks, int64_t least)
     return (int)((n + len - 1) / len);
 }
 
-int z_chunks(const Grid3 &g)
+Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_target)
 {
-    const int64_t cols = (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy);
-    return chunks(g.nz, cols, 2048, 8);
+    Split s;
+    const int64_t strips = nbx64(g.nx);
+    s.xy = chunks(g.ny, strips * g.nz, xy_waves, 8);
+    s.z = chunks(g.nz, (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy), z_target, 8);
+    s.u = chunks(g.nz, (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy), u_target, 8);
+    return s;
 }
 
-int64_t z_blocks(const Grid3 &g)
+// xy: enough row chunks for ~16K waves but chunks no shorter than needed for
+// 128-row chunks; z: ~2K workgroups; update: ~1K workgroups.
+Split default_split(const Grid3 &g)
 {
-    return (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy) * z_chunks(g);
+    Split s = make_split(g, 16384, 2048, 1024);
+    const int base = (g.ny + 127) / 128;
+    if (s.xy < base) {
+        const int64_t len = (g.ny + base - 1) / base;
+        s.xy = (int)((g.ny + len - 1) / len);
+    }
+    return s;
 }
 
-int u_chunks(const Grid3 &g)
+static bool chunks_ok(int n, int c)
 {
-    const int64_t cols = (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy);
-    return chunks(g.nz, cols, 1024, 8);
+    if (c < 1 || c > n) return false;
+    const int len = (n + c - 1) / c;
+    return (c - 1) * len < n;
 }
 
-int64_t u_blocks(const Grid3 &g)
+bool split_valid(const Grid3 &g, const Split &s)
 {
-    return (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy) * u_chunks(g);
+    return chunks_ok(g.ny, s.xy) && chunks_ok(g.nz, s.z) && chunks_ok(g.nz, s.u);
 }
 
-// xy pass: one wave per (64-wide strip, row chunk, slice); rows per chunk
-// >= 8, enough chunks for ~16K waves, no more than needed for 128-row chunks.
-int xy_chunks(const Grid3 &g)
-{
-    const int64_t strips = (g.nx + 63) / 64;
-    const int64_t base = (g.ny + 127) / 128;
-    int64_t c = chunks(g.ny, strips * g.nz, 16384, 8);
-    if (c < base) c = base;
-    const int64_t len = (g.ny + c - 1) / c;
-    return (int)((g.ny + len - 1) / len);
-}
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
 
-int xy_blocks(const Grid3 &g) { return (int)(((g.nx + 63) / 64) * xy_chunks(g) * g.nz); }
-
-hipError_t launch_edges(float *cx, float *cy, float *cz, Grid3 g, const Taps &t, int R,
-                        hipStream_t s)
+hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s)
 {
-    const int n = g.nx + g.ny + g.nz;
-    hipLaunchKernelGGL(edges_kernel, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
-                       cx, cy, cz, g, t, R);
+    hipLaunchKernelGGL(setup_kernel, dim3(b.n), dim3(kThreads), 0, s, b, t, R);
     return hipGetLastError();
 }
 
-hipError_t launch_flags_init(int *flags, hipStream_t s)
+hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s)
 {
-    hipLaunchKernelGGL(flags_init_kernel, dim3(1), dim3(64), 0, s, flags);
+    hipLaunchKernelGGL(reduce_kernel, dim3(b.n), dim3(kThreads), 0, s, b, c);
     return hipGetLastError();
 }
 
@@ -153,7 +154,7 @@ bool types_supported(int R, int it, int st)
     return (it == F32 || it == U16) && (st == F32 || st == F16 || st == BF16);
 }
 
-// Expand F(RR, IT, ST) for every built (radius, image, storage) combination
+// Expand CALL(RR, IT, ST) for the built (radius, image, storage) combination
 // matching the runtime (R, it, st).
 #define RSF_R_ALL(X, IT, ST) \
     X(1, IT, ST) X(2, IT, ST) X(3, IT, ST) X(4, IT, ST) X(5, IT, ST) X(6, IT, ST) X(7, IT, ST) \
@@ -179,50 +180,41 @@ bool types_supported(int R, int it, int st)
     }                                                                                   \
     return hipErrorInvalidValue;
 
-hipError_t launch_xy(int R, int mode, int it, int st, const void *in, void *out, Grid3 g,
-                     const Taps &t, const FitArgs *fa, const int *done, hipStream_t s)
+hipError_t launch_xy(int R, int mode, int it, int st, const Batch &b, int64_t blocks,
+                     const Taps &t, const Coeffs &c, bool probe, hipStream_t s)
 {
 #define C(RR, IT, ST) \
-    case RR: return launch_xy_r<RR, IT, ST>(mode, in, out, g, t, fa, done, s);
+    case RR: return launch_xy_r<RR, IT, ST>(mode, b, blocks, t, c, probe, s);
     RSF_DISPATCH(C)
 #undef C
 }
 
-hipError_t launch_z_plain(int R, int st, const void *in, void *out, Grid3 g, const Taps &t,
+hipError_t launch_z_plain(int R, int st, const Batch &b, int64_t blocks, const Taps &t,
                           hipStream_t s)
 {
     const int it = F32;   // the plain z pass only touches the storage type
 #define C(RR, IT, ST) \
-    case RR: return launch_z_plain_r<RR, ST>(in, out, g, t, s);
+    case RR: return launch_z_plain_r<RR, ST>(b, blocks, t, s);
     RSF_DISPATCH(C)
 #undef C
 }
 
-hipError_t launch_z_heaviside(int R, int it, int st, const float *phi, const void *I,
-                              void *pair_out, Grid3 g, const Taps &t, float eps, float *probeH,
-                              const int *done, hipStream_t s)
+hipError_t launch_z_heaviside(int R, int it, int st, const Batch &b, int64_t blocks,
+                              const Taps &t, const Coeffs &c, bool probe, hipStream_t s)
 {
 #define C(RR, IT, ST) \
-    case RR: return launch_z_heaviside_r<RR, IT, ST>(phi, I, pair_out, g, t, eps, probeH, done, s);
+    case RR: return launch_z_heaviside_r<RR, IT, ST>(b, blocks, t, c, probe, s);
     RSF_DISPATCH(C)
 #undef C
 }
 
-hipError_t launch_z_update(int R, int it, int st, const void *pair_in, Grid3 g, const Taps &t,
-                           const UpdArgs &ua, const int *done, hipStream_t s)
+hipError_t launch_z_update(int R, int it, int st, const Batch &b, int64_t blocks, const Taps &t,
+                           const Coeffs &c, bool probe, hipStream_t s)
 {
 #define C(RR, IT, ST) \
-    case RR: return launch_z_update_r<RR, IT, ST>(pair_in, g, t, ua, done, s);
+    case RR: return launch_z_update_r<RR, IT, ST>(b, blocks, t, c, probe, s);
     RSF_DISPATCH(C)
 #undef C
-}
-
-hipError_t launch_reduce(const double *partials, int64_t n, double *out, int *flags,
-                         double tol_total, hipStream_t s)
-{
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kThreads), 0, s, partials, n, out, flags,
-                       tol_total);
-    return hipGetLastError();
 }
 
 }  // namespace rsf

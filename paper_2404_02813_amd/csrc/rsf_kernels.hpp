@@ -51,13 +51,37 @@ __device__ __forceinline__ int reflect(int i, int n)
     return i < 0 ? -i : (i > n - 1 ? 2 * (n - 1) - i : i);
 }
 
-// Workgroup b runs on XCD b % 8.  Give XCD k the contiguous tile range
-// [k*per + min(k, rem), ...) so spatial neighbours share an L2.
+// Workgroup b runs on XCD b % 8.  Give XCD k the contiguous range
+// [k*per + min(k, rem), ...) of the batch's workgroup numbers, so spatial
+// neighbours (and each tile) share an L2.
 __device__ __forceinline__ int xcd_tile(int b, int n)
 {
     const int per = n / kXcds, rem = n % kXcds;
     const int x = b % kXcds, local = b / kXcds;
     return x * per + min(x, rem) + local;
+}
+
+// The tile owning workgroup number gb: the last t with start[t] <= gb.
+__device__ __forceinline__ int find_tile(const int *start, int n, int gb)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= gb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// This workgroup's tile and its workgroup number within the tile.
+struct Where {
+    int t, lb;
+};
+__device__ __forceinline__ Where locate(const Batch &bt)
+{
+    const int gb = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = find_tile(bt.start, bt.n, gb);
+    return Where{t, gb - bt.start[t]};
 }
 
 // ---------------------------------------------------------------------------
@@ -68,22 +92,26 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 // work is paid only on the chunk's 2R extra rows, never per row.
 // ---------------------------------------------------------------------------
 
-// XY_ONE reads and writes one field of IN / ST; XY_TWO and XY_FITS read and
-// write interleaved pairs.
+// XY_ONE reads the image (IN) and writes one field P (ST), for K*I; XY_FITS
+// reads the pair P and K*I and writes the pair Q; XY_TWO reads the pair Q and
+// writes the pair P.
 template <int R, int MODE, class IN, class ST>
-__global__ __launch_bounds__(64) void xy_kernel(const void *__restrict__ in_,
-                                                void *__restrict__ out_, Grid3 g, Taps t,
-                                                FitArgs fa, int nyc,
-                                                const int *__restrict__ done)
+__global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 {
-    if (done && *done) return;
     constexpr int NF = MODE == XY_ONE ? 1 : 2;
     constexpr int W = 2 * R + 1;
     constexpr int RW = 64 + 2 * R;
     __shared__ float row[2][NF][RW];
 
+    const Where wh = locate(bt);
+    const TileDesc &d = bt.tiles[wh.t];
+    if (d.flags[0]) return;
+    const Grid3 g = d.g;
+    const int nyc = d.sp.xy;
+    const void *__restrict__ in_ = MODE == XY_ONE ? d.I : (MODE == XY_FITS ? d.P : d.Q);
+    void *__restrict__ out_ = MODE == XY_FITS ? d.Q : d.P;
     const int nbx = (g.nx + 63) / 64;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = wh.lb;
     const int xs = tile % nbx, rest = tile / nbx;
     const int yc = rest % nyc, z = rest / nyc;
     const int ly = (g.ny + nyc - 1) / nyc;
@@ -156,10 +184,12 @@ __global__ __launch_bounds__(64) void xy_kernel(const void *__restrict__ in_,
     }
     float cxz = 0.f;
     const int xc = min(x, g.nx - 1);
-    const ST *ki_slice = MODE == XY_FITS ? static_cast<const ST *>(fa.KI) + zb : nullptr;
-    if (MODE == XY_FITS) cxz = fa.cx[xc] * fa.cz[z];
+    const ST *ki_slice = MODE == XY_FITS ? static_cast<const ST *>(d.KI) + zb : nullptr;
+    const float *cyp = d.cy;
+    if (MODE == XY_FITS) cxz = d.cx[xc] * d.cz[z];
     float ki_next = MODE == XY_FITS ? to_f(ki_slice[y0 * g.nx + xc]) : 0.f;
-    float cy_next = MODE == XY_FITS ? fa.cy[y0] : 0.f;
+    float cy_next = MODE == XY_FITS ? cyp[y0] : 0.f;
+    float *probe_f1 = d.probe_f1, *probe_f2 = d.probe_f2;
     ST *o1_s = static_cast<ST *>(out_) + zb;
     Pair<ST> *o2_s = static_cast<Pair<ST> *>(out_) + zb;
     for (int yb = y0; yb < y1; yb += W) {
@@ -175,7 +205,7 @@ __global__ __launch_bounds__(64) void xy_kernel(const void *__restrict__ in_,
                     cyv = cy_next;
                     if (y + 1 < y1) {
                         ki_next = to_f(ki_slice[(y + 1) * g.nx + xc]);
-                        cy_next = fa.cy[y + 1];
+                        cy_next = cyp[y + 1];
                     }
                 }
                 // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
@@ -197,10 +227,10 @@ __global__ __launch_bounds__(64) void xy_kernel(const void *__restrict__ in_,
                         const float B2 = K1 - acc_b;
                         const float f1 = acc_a * rcp(acc_b);
                         const float f2 = A2 * rcp(B2);
-                        o2_s[v] = Pair<ST>{from_f<ST>(fa.l1 * f1 - fa.l2 * f2),
-                                           from_f<ST>(fa.l1 * f1 * f1 - fa.l2 * f2 * f2)};
-                        if (fa.probe_f1) fa.probe_f1[zb + v] = f1;
-                        if (fa.probe_f2) fa.probe_f2[zb + v] = f2;
+                        o2_s[v] = Pair<ST>{from_f<ST>(c.l1 * f1 - c.l2 * f2),
+                                           from_f<ST>(c.l1 * f1 * f1 - c.l2 * f2 * f2)};
+                        if (probe_f1) probe_f1[zb + v] = f1;
+                        if (probe_f2) probe_f2[zb + v] = f2;
                     } else if (NF == 2) {
                         o2_s[v] = Pair<ST>{from_f<ST>(acc_a), from_f<ST>(acc_b)};
                     } else {
@@ -224,12 +254,13 @@ struct ZTile {
     bool active;
 };
 
-// Tiles are (TX x TY columns) x (one z chunk), z chunk fastest.
+// Workgroup lb of a tile covers (TX x TY columns) x (one z chunk), z chunk
+// fastest.
 template <int TX, int TY>
-__device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc)
+__device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc, int lb)
 {
     ZTile zt;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = lb;
     const int nbx = (g.nx + TX - 1) / TX;
     const int zc = tile % nzc, col = tile / nzc;
     const int lz = (g.nz + nzc - 1) / nzc;
@@ -242,7 +273,10 @@ __device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc)
     return zt;
 }
 
-__device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc) { return z_tile_t<kZx, kZy>(g, nzc); }
+__device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc, int lb)
+{
+    return z_tile_t<kZx, kZy>(g, nzc, lb);
+}
 
 // Conv ring.  fetch(z) loads the raw inputs of slice z (0 <= z < nz) and
 // cook(raw, z) turns them into the two convolved quantities; each slice is
@@ -297,12 +331,16 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
     }
 }
 
+// K*I: z pass of the field P into KI.
 template <int R, class ST>
-__global__ __launch_bounds__(kThreads) void z_plain_kernel(const ST *__restrict__ in,
-                                                           ST *__restrict__ out, Grid3 g,
-                                                           Taps t, int nzc)
+__global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t)
 {
-    const ZTile zt = z_tile(g, nzc);
+    const Where wh = locate(bt);
+    const TileDesc &d = bt.tiles[wh.t];
+    const Grid3 g = d.g;
+    const ST *__restrict__ in = static_cast<const ST *>(d.P);
+    ST *__restrict__ out = static_cast<ST *>(d.KI);
+    const ZTile zt = z_tile(g, d.sp.z, wh.lb);
     if (!zt.active) return;
     const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
     z_march<R, 1>(
@@ -314,12 +352,18 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(const ST *__restrict_
 
 // Stage-1 z pass: H_eps(phi) and H I formed as slices enter the ring.
 template <int R, bool PROBE, class ST, class IT>
-__global__ __launch_bounds__(kThreads) void z_heaviside_kernel(
-    const float *__restrict__ phi, const IT *__restrict__ I, Pair<ST> *__restrict__ tp, Grid3 g,
-    Taps t, float eps, float *__restrict__ probeH, int nzc, const int *__restrict__ done)
+__global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t, Coeffs c)
 {
-    if (done && *done) return;
-    const ZTile zt = z_tile(g, nzc);
+    const Where wh = locate(bt);
+    const TileDesc &d = bt.tiles[wh.t];
+    if (d.flags[0]) return;
+    const Grid3 g = d.g;
+    const float *__restrict__ phi = d.phi[bt.par];
+    const IT *__restrict__ I = static_cast<const IT *>(d.I);
+    Pair<ST> *__restrict__ tp = static_cast<Pair<ST> *>(d.P);
+    float *__restrict__ probeH = d.probe_H;
+    const float eps = c.eps;
+    const ZTile zt = z_tile(g, d.sp.z, wh.lb);
     if (!zt.active) return;
     const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
     z_march<R, 2>(
@@ -376,9 +420,7 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
 // n, V of z+2 overwrite those of z-1, last read in step z-1; a barrier
 // separates each pair.
 template <int R, bool PROBE, class ST, class IT>
-__global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *__restrict__ tp,
-                                                             Grid3 g, Taps t, UpdArgs ua,
-                                                             int nzc, const int *__restrict__ done)
+__global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t, Coeffs ua)
 {
     constexpr int TX = kUx, TY = kUy, NT = kUThreads;
     constexpr int PX = TX + 4, PY = TY + 4;
@@ -390,19 +432,25 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *
     __shared__ float sq[NQ][4][QS];   // n_x, V_x, n_y, V_y
     __shared__ double wsum[NT / 64];
 
-    const ZTile zt = z_tile_t<TX, TY>(g, nzc);
+    const Where wh = locate(bt);
+    const TileDesc &d = bt.tiles[wh.t];
+    const Grid3 g = d.g;
+    const Pair<ST> *__restrict__ tp = static_cast<const Pair<ST> *>(d.P);
+    const float *__restrict__ phi = d.phi[bt.par];
+    float *__restrict__ phi_out = d.phi[bt.par ^ 1];
+    const ZTile zt = z_tile_t<TX, TY>(g, d.sp.u, wh.lb);
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1), ty = tid / TX;
     const int x0 = zt.x - tx, y0 = zt.y - ty;
-    const bool stopped = done && *done;
-    const float *__restrict__ phi = ua.phi;
+    const bool stopped = d.flags[0] != 0;
     double acc = 0.0;
 
     if (stopped) {
+        // a stopped tile keeps phi: copy it so the ping-pong stays consistent
         if (zt.active) {
             const int col = zt.y * g.nx + zt.x;
             for (int z = zt.z0; z < zt.z1; ++z)
-                (ua.phi_out + (int64_t)z * g.sxy)[col] = (phi + (int64_t)z * g.sxy)[col];
+                (phi_out + (int64_t)z * g.sxy)[col] = (phi + (int64_t)z * g.sxy)[col];
         }
     } else {
         // phi tile loads: reflected in-slice offsets of this thread's points
@@ -476,8 +524,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *
         };
 
         const int col = min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
-        const float cxy = ua.cx[min(zt.x, g.nx - 1)] * ua.cy[min(zt.y, g.ny - 1)];
-        const IT *img = static_cast<const IT *>(ua.I);
+        const float cxy = d.cx[min(zt.x, g.nx - 1)] * d.cy[min(zt.y, g.ny - 1)];
+        const float *czp = d.cz;
+        const IT *img = static_cast<const IT *>(d.I);
         auto at = [&](const auto *base, int z) { return to_f((base + (int64_t)z * g.sxy)[col]); };
         auto pair_at = [&](int z) {
             const Pair<ST> v = (tp + (int64_t)z * g.sxy)[col];
@@ -544,20 +593,20 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *
                         const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
                                            0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
                                            0.5f * (vzp - vzm);
-                        const float K1 = cxy * ua.cz[z];
+                        const float K1 = cxy * czp[z];
                         const float Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
                         const float Rt = lap + divV;
                         const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                         const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
                         const float nxt = cphi + ua.dt * E;
-                        (ua.phi_out + zo)[col] = nxt;
+                        (phi_out + zo)[col] = nxt;
                         acc += fabs((double)nxt - (double)cphi);
                         if (PROBE) {
-                            if (ua.probe_Fd) (ua.probe_Fd + zo)[col] = Fd;
-                            if (ua.probe_kappa) (ua.probe_kappa + zo)[col] = kappa;
-                            if (ua.probe_lap) (ua.probe_lap + zo)[col] = lap;
-                            if (ua.probe_R) (ua.probe_R + zo)[col] = Rt;
-                            if (ua.probe_E) (ua.probe_E + zo)[col] = E;
+                            if (d.probe_Fd) (d.probe_Fd + zo)[col] = Fd;
+                            if (d.probe_kappa) (d.probe_kappa + zo)[col] = kappa;
+                            if (d.probe_lap) (d.probe_lap + zo)[col] = lap;
+                            if (d.probe_R) (d.probe_R + zo)[col] = Rt;
+                            if (d.probe_E) (d.probe_E + zo)[col] = E;
                         }
                     }
                     nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
@@ -576,7 +625,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *
         double sum = 0.0;
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) sum += wsum[w];
-        ua.partials[zt.tile] = sum;
+        d.partials[wh.lb] = sum;
     }
 }
 
@@ -587,24 +636,19 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(const Pair<ST> *
 // ---------------------------------------------------------------------------
 
 template <int R, class IT, class ST>
-hipError_t launch_xy_r(int mode, const void *in, void *out, Grid3 g, const Taps &t,
-                       const FitArgs *fa, const int *done, hipStream_t s)
+hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                       bool, hipStream_t s)
 {
-    const dim3 grid(xy_blocks(g));
-    const FitArgs f = fa ? *fa : FitArgs{};
-    const int nyc = xy_chunks(g);
+    const dim3 grid((unsigned)blocks);
     switch (mode) {
     case XY_ONE:
-        hipLaunchKernelGGL((xy_kernel<R, XY_ONE, IT, ST>), grid, dim3(64), 0, s, in, out, g, t, f,
-                           nyc, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_ONE, IT, ST>), grid, dim3(64), 0, s, b, t, c);
         break;
     case XY_TWO:
-        hipLaunchKernelGGL((xy_kernel<R, XY_TWO, ST, ST>), grid, dim3(64), 0, s, in, out, g, t, f,
-                           nyc, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_TWO, ST, ST>), grid, dim3(64), 0, s, b, t, c);
         break;
     case XY_FITS:
-        hipLaunchKernelGGL((xy_kernel<R, XY_FITS, ST, ST>), grid, dim3(64), 0, s, in, out, g, t,
-                           f, nyc, done);
+        hipLaunchKernelGGL((xy_kernel<R, XY_FITS, ST, ST>), grid, dim3(64), 0, s, b, t, c);
         break;
     default:
         return hipErrorInvalidValue;
@@ -613,56 +657,49 @@ hipError_t launch_xy_r(int mode, const void *in, void *out, Grid3 g, const Taps 
 }
 
 template <int R, class ST>
-hipError_t launch_z_plain_r(const void *in, void *out, Grid3 g, const Taps &t, hipStream_t s)
+hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, hipStream_t s)
 {
-    hipLaunchKernelGGL((z_plain_kernel<R, ST>), dim3((unsigned)z_blocks(g)), dim3(kThreads), 0, s,
-                       static_cast<const ST *>(in), static_cast<ST *>(out), g, t, z_chunks(g));
+    hipLaunchKernelGGL((z_plain_kernel<R, ST>), dim3((unsigned)blocks), dim3(kThreads), 0, s, b, t);
     return hipGetLastError();
 }
 
 template <int R, class IT, class ST>
-hipError_t launch_z_heaviside_r(const float *phi, const void *I, void *pair_out, Grid3 g,
-                                const Taps &t, float eps, float *probeH, const int *done,
-                                hipStream_t s)
+hipError_t launch_z_heaviside_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                                bool probe, hipStream_t s)
 {
-    const dim3 grid((unsigned)z_blocks(g));
-    const IT *img = static_cast<const IT *>(I);
-    Pair<ST> *o = static_cast<Pair<ST> *>(pair_out);
-    if (probeH)
-        hipLaunchKernelGGL((z_heaviside_kernel<R, true, ST, IT>), grid, dim3(kThreads), 0, s, phi,
-                           img, o, g, t, eps, probeH, z_chunks(g), done);
-    else
-        hipLaunchKernelGGL((z_heaviside_kernel<R, false, ST, IT>), grid, dim3(kThreads), 0, s, phi,
-                           img, o, g, t, eps, probeH, z_chunks(g), done);
-    return hipGetLastError();
-}
-
-template <int R, class IT, class ST>
-hipError_t launch_z_update_r(const void *pair_in, Grid3 g, const Taps &t, const UpdArgs &ua,
-                             const int *done, hipStream_t s)
-{
-    const dim3 grid((unsigned)u_blocks(g));
-    const Pair<ST> *p = static_cast<const Pair<ST> *>(pair_in);
-    const bool probe = ua.probe_Fd || ua.probe_kappa || ua.probe_lap || ua.probe_R || ua.probe_E;
+    const dim3 grid((unsigned)blocks);
     if (probe)
-        hipLaunchKernelGGL((z_update_kernel<R, true, ST, IT>), grid, dim3(kUThreads), 0, s, p, g, t,
-                           ua, u_chunks(g), done);
+        hipLaunchKernelGGL((z_heaviside_kernel<R, true, ST, IT>), grid, dim3(kThreads), 0, s, b, t,
+                           c);
     else
-        hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT>), grid, dim3(kUThreads), 0, s, p, g,
-                           t, ua, u_chunks(g), done);
+        hipLaunchKernelGGL((z_heaviside_kernel<R, false, ST, IT>), grid, dim3(kThreads), 0, s, b, t,
+                           c);
+    return hipGetLastError();
+}
+
+template <int R, class IT, class ST>
+hipError_t launch_z_update_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                             bool probe, hipStream_t s)
+{
+    const dim3 grid((unsigned)blocks);
+    if (probe)
+        hipLaunchKernelGGL((z_update_kernel<R, true, ST, IT>), grid, dim3(kUThreads), 0, s, b, t,
+                           c);
+    else
+        hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT>), grid, dim3(kUThreads), 0, s, b, t,
+                           c);
     return hipGetLastError();
 }
 
 // Instantiate every pass launcher for radius RR, image type IT, storage ST.
-#define RSF_INSTANTIATE(RR, IT, ST)                                                          \
-    template hipError_t launch_xy_r<RR, IT, ST>(int, const void *, void *, Grid3, const Taps &, \
-                                                const FitArgs *, const int *, hipStream_t);  \
-    template hipError_t launch_z_plain_r<RR, ST>(const void *, void *, Grid3, const Taps &,  \
-                                                 hipStream_t);                               \
-    template hipError_t launch_z_heaviside_r<RR, IT, ST>(const float *, const void *, void *, \
-                                                         Grid3, const Taps &, float, float *, \
-                                                         const int *, hipStream_t);          \
-    template hipError_t launch_z_update_r<RR, IT, ST>(const void *, Grid3, const Taps &,     \
-                                                      const UpdArgs &, const int *, hipStream_t);
+#define RSF_INSTANTIATE(RR, IT, ST)                                                           \
+    template hipError_t launch_xy_r<RR, IT, ST>(int, const Batch &, int64_t, const Taps &,    \
+                                                const Coeffs &, bool, hipStream_t);           \
+    template hipError_t launch_z_plain_r<RR, ST>(const Batch &, int64_t, const Taps &,        \
+                                                 hipStream_t);                                \
+    template hipError_t launch_z_heaviside_r<RR, IT, ST>(const Batch &, int64_t, const Taps &, \
+                                                         const Coeffs &, bool, hipStream_t);  \
+    template hipError_t launch_z_update_r<RR, IT, ST>(const Batch &, int64_t, const Taps &,   \
+                                                      const Coeffs &, bool, hipStream_t);
 
 }  // namespace rsf

@@ -154,3 +154,70 @@ def scaled(w: Workload, n: int, iters: int | None = None, name: str | None = Non
     return Workload(name or f"{w.name}_n{n}", (n, n, n), tubes, w.r_min, w.r_max,
                     w.seed + 1000 + n, iters if iters is not None else w.iters,
                     w.sigma, w.lambda1, w.lambda2, w.nu, w.mu, w.dt, w.eps)
+
+
+def tile_phi0(shape, halo: int, inside: float = 2.0, outside: float = -2.0) -> np.ndarray:
+    """phi0 of one tile: +inside on the centred box whose sides are half the
+    tile's interior (extent minus the halo on both sides), `outside` elsewhere."""
+    phi = np.full(shape, outside, dtype=np.float32)
+    sl = []
+    for n in shape:
+        e = n - 2 * halo
+        lo = halo + e // 4
+        sl.append(slice(lo, lo + max(e // 2, 1)))
+    phi[tuple(sl)] = inside
+    return phi
+
+
+def cut_tiles(volume: np.ndarray, n_tiles: int, edges, halo: int, seed: int):
+    """`n_tiles` sub-volumes of `volume`: interior edge lengths drawn from
+    `edges` independently per axis, `halo` voxels added on every side, origins
+    uniform so the tile fits.  Returns [(origin_zyx, image tile, phi0 tile)]."""
+    rng = rng_for(seed)
+    out = []
+    for _ in range(int(n_tiles)):
+        ext = [int(rng.choice(edges)) + 2 * halo for _ in range(3)]
+        org = [int(rng.integers(0, n - e + 1)) for n, e in zip(volume.shape, ext)]
+        sl = tuple(slice(o, o + e) for o, e in zip(org, ext))
+        img = np.ascontiguousarray(volume[sl])
+        out.append((tuple(org), img, tile_phi0(img.shape, halo)))
+    return out
+
+
+@dataclass(frozen=True)
+class TileWorkload:
+    """A batch of sub-volume tiles with halos cut from one phantom volume,
+    each evolved as an independent problem from its own box phi0."""
+    name: str
+    shape: tuple            # phantom (nz, ny, nx)
+    n_tubes: int
+    r_min: float
+    r_max: float
+    seed: int
+    n_tiles: int
+    edges: tuple            # interior edge lengths, drawn per axis
+    halo: int
+    iters: int
+    sigma: float = 3.0
+    lambda1: float = 1.0
+    lambda2: float = 1.0
+    nu: float = 0.001
+    mu: float = 1.0
+    dt: float = 0.1
+    eps: float = 1.0
+
+    def volume(self) -> np.ndarray:
+        return vessel_phantom(self.shape, self.n_tubes, self.r_min, self.r_max, self.seed)
+
+    def tiles(self, volume: np.ndarray):
+        return cut_tiles(volume, self.n_tiles, self.edges, self.halo, self.seed + 100)
+
+    def params(self) -> dict:
+        return dict(sigma=self.sigma, lambda1=self.lambda1, lambda2=self.lambda2,
+                    nu=self.nu, mu=self.mu, dt=self.dt, eps=self.eps)
+
+
+# 64 tiles, interior edges from {96..256} per axis plus a 9-voxel (3 sigma)
+# halo, cut from a 1024x1024x512 phantom of 1500 tubes r 1-4; 100 iterations.
+TILES_64 = TileWorkload("tiles64_s3_it100", (512, 1024, 1024), 1500, 1.0, 4.0, seed=3,
+                        n_tiles=64, edges=(96, 128, 160, 192, 256), halo=9, iters=100)

@@ -33,7 +33,8 @@ RSF_REG_SINGLE_WELL = 1
 
 EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
-           "rsf_profile_enable", "rsf_profile_read")
+           "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
+           "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset")
 
 PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce")
 
@@ -54,6 +55,11 @@ class rsf_params(ctypes.Structure):
 class rsf_stats(ctypes.Structure):
     _fields_ = [("iters_requested", ctypes.c_int), ("iters_run", ctypes.c_int),
                 ("last_sum_abs", ctypes.c_double)]
+
+
+class rsf_tile(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
 
 
 class rsf_profile(ctypes.Structure):
@@ -99,6 +105,19 @@ def lib() -> ctypes.CDLL:
     L.rsf_probe.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params),
                             ctypes.POINTER(rsf_probe_fields), vp]
     L.rsf_probe.restype = i
+    L.rsf_batch_workspace_bytes.argtypes = [ctypes.POINTER(rsf_tile), i, i, i]
+    L.rsf_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.rsf_evolve_batch.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params),
+                                   i, ctypes.c_double, vp, ctypes.c_size_t, vp]
+    L.rsf_evolve_batch.restype = i
+    L.rsf_get_tile_stats.argtypes = [vp, i, ctypes.POINTER(rsf_stats),
+                                     ctypes.POINTER(ctypes.c_double), i]
+    L.rsf_get_tile_stats.restype = i
+    L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
+                               vp]
+    L.rsf_autotune.restype = i
+    L.rsf_autotune_reset.argtypes = [vp]
+    L.rsf_autotune_reset.restype = None
     L.rsf_profile_enable.argtypes = [vp, i]
     L.rsf_profile_enable.restype = i
     L.rsf_profile_read.argtypes = [vp, ctypes.POINTER(rsf_profile)]
@@ -201,12 +220,70 @@ def rsf_evolve_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_para
 
 def rsf_get_stats(ctx, cap: int = 0):
     """Returns (iters_requested, iters_run, last_sum_abs, history list)."""
+    return rsf_get_tile_stats(ctx, 0, cap)
+
+
+def rsf_get_tile_stats(ctx, tile: int, cap: int = 0):
+    """Statistics of one tile of the last evolution (see rsf_get_stats)."""
     st = rsf_stats()
     hist = (ctypes.c_double * max(cap, 1))()
-    status = lib().rsf_get_stats(ctx, ctypes.byref(st), hist if cap > 0 else None, int(cap))
+    status = lib().rsf_get_tile_stats(ctx, int(tile), ctypes.byref(st),
+                                      hist if cap > 0 else None, int(cap))
     _check(ctx, status)
     n = min(cap, st.iters_run)
     return st.iters_requested, st.iters_run, st.last_sum_abs, [hist[i] for i in range(n)]
+
+
+def _tiles(volumes, phis):
+    if len(volumes) != len(phis) or not volumes:
+        raise ValueError("need matching, non-empty lists of volumes and phis")
+    dt = None
+    arr = (rsf_tile * len(volumes))()
+    for k, (v, p) in enumerate(zip(volumes, phis)):
+        _field(v, "volume", "image")
+        _field(p, "phi")
+        if v.shape != p.shape:
+            raise ValueError("each volume and phi must have the same shape")
+        if dt is None:
+            dt = v.dtype
+        elif v.dtype != dt:
+            raise ValueError("all volumes of a batch must share a dtype")
+        nz, ny, nx = p.shape
+        arr[k] = rsf_tile(v.data_ptr(), p.data_ptr(), nx, ny, nz)
+    return arr, _IMAGE_DTYPES[dt]
+
+
+def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
+                 stream=None) -> None:
+    """Pick and keep per-shape workgroup splits by timing (phis untouched)."""
+    arr, vdt = _tiles(volumes, phis)
+    _check(ctx, lib().rsf_autotune(ctx, arr, len(volumes), vdt, ctypes.byref(params),
+                                   int(trial_iters), _stream(stream)))
+
+
+def rsf_autotune_reset(ctx) -> None:
+    lib().rsf_autotune_reset(ctx)
+
+
+def rsf_batch_workspace_bytes(shapes, iters: int, storage=RSF_F32) -> int:
+    """shapes: list of (nz, ny, nx)."""
+    arr = (rsf_tile * len(shapes))()
+    for k, (nz, ny, nx) in enumerate(shapes):
+        arr[k] = rsf_tile(None, None, nx, ny, nz)
+    st = _STORAGE[storage] if isinstance(storage, str) else int(storage)
+    return int(lib().rsf_batch_workspace_bytes(arr, len(shapes), int(iters), st))
+
+
+def rsf_evolve_batch(ctx, volumes, phis, params: rsf_params, iters: int, tol: float = 0.0,
+                     workspace: torch.Tensor | None = None, stream=None) -> None:
+    """Evolve each phi in place against its volume; one launch per pass for all."""
+    arr, vdt = _tiles(volumes, phis)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    _check(ctx, lib().rsf_evolve_batch(ctx, arr, len(volumes), vdt, ctypes.byref(params),
+                                       int(iters), float(tol), ws_ptr, ws_bytes,
+                                       _stream(stream)))
 
 
 def rsf_gauss3d(ctx, inp: torch.Tensor, out: torch.Tensor, sigma: float, stream=None) -> None:
@@ -278,6 +355,18 @@ class Context:
 
     def stats(self, cap=0):
         return rsf_get_stats(self.handle, cap)
+
+    def tile_stats(self, tile, cap=0):
+        return rsf_get_tile_stats(self.handle, tile, cap)
+
+    def evolve_batch(self, volumes, phis, params, iters, tol=0.0, workspace=None, stream=None):
+        rsf_evolve_batch(self.handle, volumes, phis, params, iters, tol, workspace, stream)
+
+    def autotune(self, volumes, phis, params, trial_iters=3, stream=None):
+        rsf_autotune(self.handle, volumes, phis, params, trial_iters, stream)
+
+    def autotune_reset(self):
+        rsf_autotune_reset(self.handle)
 
     def gauss3d(self, inp, sigma, out=None, stream=None):
         out = torch.empty_like(inp) if out is None else out

@@ -377,3 +377,93 @@ def test_mixed_precision_radius_limits(rsf):
         with pytest.raises(mod.RsfError) as e:
             ctx.evolve_ex(u, phi, mod.make_params(sigma, 1, 1, 0.001, 1, 0.1, 1, storage="f16"), 1)
         assert e.value.status == mod.RSF_ERR_INVALID_ARG
+
+
+# --- batches of uneven tiles ------------------------------------------------------------
+
+BATCH_SHAPES = [(40, 50, 60), (33, 47, 61), (64, 64, 64), (20, 130, 70), (27, 27, 150)]
+
+
+def batch_inputs(seed=51):
+    r = np.random.default_rng(seed)
+    vols, phis = [], []
+    for k, shape in enumerate(BATCH_SHAPES):
+        vols.append(inputs.vessel_phantom(shape, 6, 1.0, 3.0, seed=seed + k))
+        phis.append(inputs.tile_phi0(shape, 3))
+    return vols, phis
+
+
+def test_batch_equals_each_tile_alone(rsf):
+    """A tile's result (and its sum|dphi| history) is bitwise the same alone
+    and in a batch of uneven tiles."""
+    mod, ctx = rsf
+    say("batch vs alone (bitwise)")
+    vols, phis = batch_inputs()
+    p = params(mod, sigma=3.0)
+    dv = [dev(v) for v in vols]
+    batch = [dev(q) for q in phis]
+    ctx.evolve_batch(dv, batch, p, 12)
+    hb = [ctx.tile_stats(k, cap=12)[3] for k in range(len(vols))]
+    for k in range(len(vols)):
+        alone = dev(phis[k])
+        ctx.evolve_ex(dv[k], alone, p, 12)
+        _, run, _, ha = ctx.stats(cap=12)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, batch[k]), k
+        assert run == 12 and ha == hb[k]
+
+
+def test_batch_matches_oracle(rsf):
+    mod, ctx = rsf
+    say("batch vs oracle")
+    vols, phis = batch_inputs(61)
+    iters = 15
+    dv = [dev(v) for v in vols]
+    out = [dev(q) for q in phis]
+    ctx.evolve_batch(dv, out, params(mod, sigma=3.0, lambda1=2.0, lambda2=2.0), iters)
+    for k in range(len(vols)):
+        want, _ = oracle.evolve(vols[k], phis[k], oparams(sigma=3.0, lambda1=2.0, lambda2=2.0),
+                                iters)
+        dmax, agree = parity(host(out[k]), want)
+        assert dmax <= PHI_TOL and agree >= SIGN_AGREE, (k, dmax, agree)
+
+
+def test_batch_tolerance_is_per_tile(rsf):
+    """With a tolerance each tile stops on its own; the others keep going."""
+    mod, ctx = rsf
+    say("batch tol per tile")
+    vols, phis = batch_inputs(71)
+    dv = [dev(v) for v in vols]
+    out = [dev(q) for q in phis]
+    ctx.evolve_batch(dv, out, params(mod), 40, tol=3e-3)
+    runs = [ctx.tile_stats(k, cap=40)[1] for k in range(len(vols))]
+    for k, run in enumerate(runs):
+        alone = dev(phis[k])
+        ctx.evolve(dv[k], alone, run)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, out[k]), (k, run)
+    assert min(runs) < 40
+
+
+def test_autotune_keeps_results(rsf):
+    """Autotuning leaves the caller's phi alone and changes only the
+    workgroup split: results after tuning are bitwise those before."""
+    mod, ctx = rsf
+    say("autotune")
+    vols, phis = batch_inputs(81)
+    p = params(mod, sigma=3.0)
+    dv = [dev(v) for v in vols]
+    ref = [dev(q) for q in phis]
+    ctx.evolve_batch(dv, ref, p, 10)
+    probe = [dev(q) for q in phis]
+    try:
+        ctx.autotune(dv, probe, p, trial_iters=2)
+        torch.cuda.synchronize()
+        for k in range(len(vols)):
+            assert torch.equal(probe[k], dev(phis[k])), k
+        ctx.evolve_batch(dv, probe, p, 10)
+        torch.cuda.synchronize()
+        for k in range(len(vols)):
+            assert torch.equal(probe[k], ref[k]), k
+    finally:
+        ctx.autotune_reset()
