@@ -308,6 +308,173 @@ def run_tiles(args, w) -> int:
     return 0 if ok and same else 1
 
 
+def run_serve(args, w) -> int:
+    """Served tiles.  (1) The saturated service rate: the first `sample`
+    requests submitted at once.  (2) The stream: requests submitted at Poisson
+    arrival times of rate 0.7 x that rate; latency = completion - scheduled
+    arrival.  (3) FIFO one at a time: the same sample through rsf_evolve_ex in
+    arrival order.  (4) Alone vs in the mix: sampled stream requests re-run
+    alone and compared bitwise.  Request inputs are cut from the device-resident
+    volume when each request is submitted, as a client would."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2404_02813_amd import inputs, rsf
+
+    n_req = args.requests or w.n_requests
+    reqs = w.requests(n_req)
+    sample = min(len(reqs), args.serve_sample)
+    t_gen = time.perf_counter()
+    vol_host = w.volume()
+    vol = torch.from_numpy(vol_host).cuda()
+    del vol_host
+    t_gen = time.perf_counter() - t_gen
+    params = {s: rsf.make_params(**w.params(s), storage=w.storage) for s in w.sigmas}
+    budget = int(args.budget_gb * (1 << 30))
+
+    def inputs_of(r):
+        (z, y, x), (ez, ey, ex), sigma, halo, iters = r
+        v = vol[z:z + ez, y:y + ey, x:x + ex].contiguous()
+        phi = torch.full((ez, ey, ex), -2.0, dtype=torch.float32, device="cuda")
+        sl = []
+        for n in (ez, ey, ex):
+            e = n - 2 * halo
+            lo = halo + e // 4
+            sl.append(slice(lo, lo + max(e // 2, 1)))
+        phi[tuple(sl)] = 2.0
+        return v, phi
+
+    def vi(r):
+        return float(np.prod(r[1])) * r[4]
+
+    def serve(stream, arrivals, keep=()):
+        """Submit stream[i] at arrivals[i] (monotonic seconds); returns
+        per-request results and the outputs of the requests in `keep`."""
+        srv = rsf.Server(budget_bytes=budget, chunk_iters=args.chunk_iters)
+        tickets = [None] * len(stream)
+        results = [None] * len(stream)
+        kept = {}
+        done = threading.Event()
+
+        def collect():
+            for i in range(len(stream)):
+                while tickets[i] is None:
+                    time.sleep(0.0005)
+                results[i] = srv.wait(tickets[i])
+            done.set()
+
+        th = threading.Thread(target=collect, daemon=True)
+        th.start()
+        for i, (r, t_arr) in enumerate(zip(stream, arrivals)):
+            if i % 200 == 0:
+                print(f"[serve] submitting {i}/{len(stream)}", file=sys.stderr, flush=True)
+            now = time.monotonic()
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            v, phi = inputs_of(r)
+            torch.cuda.current_stream().synchronize()
+            if i in keep:
+                kept[i] = phi
+            tickets[i] = srv.submit(v, phi, params[r[2]], r[4])
+        done.wait()
+        st = srv.stats()
+        srv.close()
+        return results, kept, st
+
+    # (1) saturated service rate
+    print("[serve] (1) saturated service rate", file=sys.stderr, flush=True)
+    t0 = time.monotonic()
+    res_sat, _, st_sat = serve(reqs[:sample], [t0] * sample)
+    t_sat = max(r["t_done"] for r in res_sat) - t0
+    rate_sat = sample / t_sat
+    gvi_sat = sum(vi(r) for r in reqs[:sample]) / t_sat / 1e9
+
+    # (2) the stream at 0.7 x the saturated rate
+    print("[serve] (2) the stream at 0.7 x the saturated rate", file=sys.stderr, flush=True)
+    lam = 0.7 * rate_sat
+    rng = np.random.default_rng(w.seed + 300)
+    gaps = rng.exponential(1.0 / lam, size=len(reqs))
+    keep = set(int(k) for k in rng.choice(len(reqs), size=min(args.check, len(reqs)),
+                                             replace=False))
+    t0 = time.monotonic() + 0.05
+    arrivals = list(t0 + np.cumsum(gaps) - gaps[0])
+    res, kept, st = serve(reqs, arrivals, keep)
+    ok = all(r["status"] == 0 for r in res)
+    lat = np.array([r["t_done"] - a for r, a in zip(res, arrivals)])
+    span = max(r["t_done"] for r in res) - arrivals[0]
+    gvi_stream = sum(vi(r) for r in reqs) / span / 1e9
+
+    # (3) FIFO one at a time over the saturation sample
+    print("[serve] (3) FIFO one at a time over the saturation sample", file=sys.stderr, flush=True)
+    ctx = rsf.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.monotonic()
+    for r in reqs[:sample]:
+        v, phi = inputs_of(r)
+        ctx.evolve_ex(v, phi, params[r[2]], r[4])
+    torch.cuda.synchronize()
+    t_fifo = time.monotonic() - t0
+    rate_fifo = sample / t_fifo
+
+    # (4) alone vs in the mix
+    print("[serve] (4) alone vs in the mix", file=sys.stderr, flush=True)
+    same = 0
+    for i, phi_mix in kept.items():
+        v, phi = inputs_of(reqs[i])
+        ctx.evolve_ex(v, phi, params[reqs[i][2]], reqs[i][4])
+        torch.cuda.synchronize()
+        same += int(torch.equal(phi, phi_mix))
+    ctx.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(float(np.percentile(lat, 50)) * 1e3, 2),
+        "unit": "ms p50 latency",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(span * 1e3, 1),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f16 storage, u16 image)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "volume_zyx": list(w.shape), "requests": len(reqs),
+                   "edges": [w.edges[0], w.edges[-1], w.edges[1] - w.edges[0]],
+                   "sigmas": list(w.sigmas), "iters": [w.it_lo, w.it_hi], "storage": w.storage,
+                   "image": "u16", "budget_gb": args.budget_gb, "chunk_iters": args.chunk_iters,
+                   "arrival_rate_per_s": round(lam, 3), "parallelism": "single_gpu"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p90": round(float(np.percentile(lat, 90)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                       "max": round(float(lat.max()) * 1e3, 2)},
+        "stream_gvoxel_iter_s": round(gvi_stream, 3),
+        "saturated": {"requests": sample, "per_s": round(rate_sat, 3),
+                      "gvoxel_iter_s": round(gvi_sat, 3), "peak_resident": st_sat["peak_resident"],
+                      "peak_gb": round(st_sat["peak_bytes"] / 2**30, 2)},
+        "fifo_one_at_a_time": {"requests": sample, "per_s": round(rate_fifo, 3),
+                               "gvoxel_iter_s": round(sum(vi(r) for r in reqs[:sample]) / t_fifo
+                                                      / 1e9, 3)},
+        "gain_over_fifo": round(rate_sat / rate_fifo, 3),
+        "stream_peak_resident": st["peak_resident"],
+        "stream_peak_gb": round(st["peak_bytes"] / 2**30, 2),
+        "alone_vs_mix_bitwise": f"{same}/{len(kept)}",
+        "hbm_frac_path": round(gvi_sat * sum(pass_bytes(2, 2).values()) / HBM_PEAK_GBS, 4),
+        "input_gen_s": round(t_gen, 1),
+    }
+    if not args.no_cpu_baseline:
+        r = reqs[0]
+        v, phi = inputs_of(r)
+        img = v.cpu().numpy().astype("float64") / 65535.0
+        wl = inputs.Workload(w.name, r[1], 0, 0.0, 0.0, w.seed, r[4], sigma=r[2])
+        out["cpu_baseline"] = cpu_baseline(wl, img, phi.cpu().numpy(), args.cpu_seconds,
+                                           what=f"request 0 of {w.name}")
+    print(json.dumps(out), flush=True)
+    return 0 if ok and same == len(kept) else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +485,13 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--iters", type=int, default=0,
                     help="override the workload's iteration count (profiling runs)")
+    ap.add_argument("--requests", type=int, default=0, help="served workload: stream length")
+    ap.add_argument("--serve-sample", type=int, default=150,
+                    help="served workload: requests timed for the saturated and FIFO rates")
+    ap.add_argument("--chunk-iters", type=int, default=4, help="served workload: server chunk")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM budget")
+    ap.add_argument("--check", type=int, default=20,
+                    help="served workload: requests re-run alone and compared")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="record rocprofv3 FETCH_SIZE / WRITE_SIZE runs in profiles/traffic.json")
     args = ap.parse_args()
@@ -342,6 +516,8 @@ def main() -> int:
         return 1
     if args.workload == inputs.TILES_64.name:
         return run_tiles(args, inputs.TILES_64)
+    if args.workload == inputs.SERVE_2000.name:
+        return run_serve(args, inputs.SERVE_2000)
     w, image_t, storage_t = workloads()[args.workload]
     if args.iters > 0:
         import dataclasses

@@ -44,6 +44,7 @@ extern "C" {
 typedef struct rsf_context rsf_context;
 
 typedef enum {
+    RSF_NOT_READY = 1,          /* rsf_server_poll / _wait: request not done yet */
     RSF_OK = 0,
     RSF_ERR_INVALID_ARG = -1,
     RSF_ERR_OUT_OF_MEMORY = -2,
@@ -230,6 +231,96 @@ rsf_status rsf_profile_enable(rsf_context *ctx, int on);
 
 /* Wait for the recorded launches, return their totals and clear them. */
 rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of independent tiles.
+ *
+ * The paper evolves a large volume as independent sub-volumes, each with a
+ * curtain (halo) sized by the Gaussian scale (Sec. 4.1, volume level
+ * parallelism).  A server evolves such tiles as requests arrive: a worker
+ * thread admits requests in arrival order while the sum of the admitted
+ * requests' workspaces (rsf_workspace_bytes) stays within the HBM budget and
+ * a resident slot is free, then advances every resident tile by up to
+ * `chunk_iters` iterations per scheduling chunk.  Tiles with equal
+ * parameters, image type and storage type (in particular equal sigma) share
+ * each launch; tiles join and leave the batch at chunk boundaries, each with
+ * its own iteration count, so requests that arrive while others run overlap
+ * with them on the device.  A tile's result is bitwise the one rsf_evolve_ex
+ * gives for it alone.
+ *
+ * Workspaces come from a device arena that grows in segments up to the
+ * budget and is kept until the server is destroyed.  One server per device;
+ * its functions may be called from any host thread.
+ * ---------------------------------------------------------------------- */
+typedef struct rsf_server rsf_server;
+
+typedef struct {
+    int device;            /* HIP device ordinal                               */
+    size_t budget_bytes;   /* HBM for request workspaces (admission limit)     */
+    size_t segment_bytes;  /* arena growth step; 0 = 8 GiB                     */
+    int chunk_iters;       /* iterations per scheduling chunk; 0 = 4           */
+    int max_resident;      /* most tiles resident at once; 0 = 256 (<= 4096)  */
+} rsf_server_config;
+
+typedef struct {
+    const void *volume;    /* device image [nz][ny][nx], volume_dtype         */
+    float *phi;            /* device phi0 on entry, phi_iters when done        */
+    int64_t nx, ny, nz;
+    int volume_dtype;      /* RSF_F32 or RSF_U16                               */
+    rsf_params params;     /* sigma ... storage, as for rsf_evolve_ex          */
+    int iters;             /* >= 0                                             */
+    double tol;            /* early stop as for rsf_evolve_ex (0 = never)      */
+} rsf_request;
+
+typedef struct {
+    int status;            /* RSF_OK, or the error that ended the request     */
+    int iters_run;
+    double last_sum_abs;   /* sum |dphi| of the last iteration run            */
+    double t_submit;       /* host monotonic clock (CLOCK_MONOTONIC), seconds */
+    double t_admit;
+    double t_done;         /* when the worker saw the result complete         */
+    size_t workspace_bytes;
+} rsf_result;
+
+typedef struct {
+    uint64_t submitted, completed;
+    int pending, resident, peak_resident;
+    size_t bytes_in_use, peak_bytes, bytes_reserved;
+    uint64_t chunks;       /* scheduling chunks launched                      */
+    double voxel_iters;    /* voxel-iterations of completed requests          */
+} rsf_server_stats;
+
+/* Create a server.  Validates the configuration; allocates streams, events
+ * and pinned staging, not the arena (that grows as requests are admitted). */
+rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg);
+
+/* Queue a request; *ticket identifies it.  Validation as for rsf_evolve_ex
+ * (RSF_ERR_INVALID_ARG); a request whose workspace alone exceeds the budget
+ * is refused with RSF_ERR_BUDGET.  The volume and phi must be ready on the
+ * device (the server's stream does not wait for the caller's streams) and
+ * must stay allocated and untouched until the request is done. */
+rsf_status rsf_server_submit(rsf_server *srv, const rsf_request *req, uint64_t *ticket);
+
+/* Result of a request: RSF_OK and *out filled when done (the server no
+ * longer references its buffers), RSF_NOT_READY while queued or running,
+ * RSF_ERR_INVALID_ARG for an unknown ticket.  A result is kept until read
+ * by poll or wait, then forgotten. */
+rsf_status rsf_server_poll(rsf_server *srv, uint64_t ticket, rsf_result *out);
+
+/* As poll, but blocks up to timeout_s seconds (< 0: no limit). */
+rsf_status rsf_server_wait(rsf_server *srv, uint64_t ticket, double timeout_s, rsf_result *out);
+
+/* Block until every request submitted so far is done. */
+rsf_status rsf_server_drain(rsf_server *srv);
+
+rsf_status rsf_server_get_stats(rsf_server *srv, rsf_server_stats *out);
+
+/* Last error of the server (validation, or the device error that failed its
+ * requests). */
+const char *rsf_server_last_error(const rsf_server *srv);
+
+/* Drain, stop the worker and free the server.  NULL is a no-op. */
+void rsf_server_destroy(rsf_server *srv);
 
 #ifdef __cplusplus
 }

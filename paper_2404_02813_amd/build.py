@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsf.so")
-SOURCES = ["rsf_kernels.hip", "rsf_api.hip"] + sorted(
+SOURCES = ["rsf_kernels.hip", "rsf_split.hip", "rsf_api.hip", "rsf_server.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith("rsf_inst_") and f.endswith(".hip"))
 ARCH = "gfx950"
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rsf.h"
+#include "rsf_host.hpp"
 #include "rsf_internal.hpp"
 
 namespace {
@@ -24,11 +25,11 @@ using rsf::Grid3;
 using rsf::Split;
 using rsf::Taps;
 using rsf::TileDesc;
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-size_t elem_size(int dtype) { return dtype == RSF_F32 ? 4 : 2; }
+using rsf::host::align_up;
+using rsf::host::kAlign;
+using rsf::host::make_coeffs;
+using rsf::host::make_taps;
+using rsf::host::radius_of;
 
 }  // namespace
 
@@ -63,17 +64,15 @@ struct rsf_context {
 
 namespace {
 
-// Per-tile regions: the pair fields P and Q and K*I in the storage type, the
-// phi ping-pong buffer in float, K*1 edge tables, update partials, the
-// per-iteration history and two flags.
+// Batch header (tile table and the three workgroup prefix tables) followed by
+// the tiles' regions.
 struct TileLayout {
     Grid3 g;
     Split sp;
-    size_t P, Q, KI, phiB, cx, cy, cz, partials, hist, flags;
+    size_t base;                 // offset of the tile's region
+    rsf::host::TileRegions T;
 };
 
-// Batch header (tile table and the three workgroup prefix tables) followed by
-// the tiles' regions.
 struct BatchLayout {
     size_t descs, start_xy, start_z, start_u, table_bytes;
     std::vector<TileLayout> tiles;
@@ -96,20 +95,11 @@ BatchLayout plan_layout(const rsf_tile *tiles, int n, int iters, int storage,
     L.pre_u.assign(1, 0);
     for (int t = 0; t < n; ++t) {
         TileLayout T{};
-        T.g = Grid3{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
-                    tiles[t].nx * tiles[t].ny};
+        T.g = rsf::host::grid_of(tiles[t].nx, tiles[t].ny, tiles[t].nz);
         T.sp = splits[t];
-        const size_t v = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz;
-        T.P = off; off += align_up(2 * v * elem_size(storage));
-        T.Q = off; off += align_up(2 * v * elem_size(storage));
-        T.KI = off; off += align_up(v * elem_size(storage));
-        T.phiB = off; off += align_up(v * sizeof(float));
-        T.cx = off; off += align_up((size_t)tiles[t].nx * sizeof(float));
-        T.cy = off; off += align_up((size_t)tiles[t].ny * sizeof(float));
-        T.cz = off; off += align_up((size_t)tiles[t].nz * sizeof(float));
-        T.partials = off; off += align_up((size_t)rsf::u_blocks(T.g, T.sp) * sizeof(double));
-        T.hist = off; off += align_up((size_t)(iters > 0 ? iters : 1) * sizeof(double));
-        T.flags = off; off += align_up(4 * sizeof(int));
+        T.base = off;
+        T.T = rsf::host::tile_regions(T.g, iters, storage);
+        off += T.T.total;
         L.pre_xy.push_back(L.pre_xy.back() + (int)rsf::xy_blocks(T.g, T.sp));
         L.pre_z.push_back(L.pre_z.back() + (int)rsf::z_blocks(T.g, T.sp));
         L.pre_u.push_back(L.pre_u.back() + (int)rsf::u_blocks(T.g, T.sp));
@@ -117,22 +107,6 @@ BatchLayout plan_layout(const rsf_tile *tiles, int n, int iters, int storage,
     }
     L.total = off;
     return L;
-}
-
-int radius_of(float sigma) { return (int)std::ceil(3.0 * (double)sigma - 1e-9); }
-
-// Sampled, truncated, unit-sum Gaussian (Sec. 3 kernel on the grid).
-Taps make_taps(float sigma, int R)
-{
-    Taps t{};
-    double w[2 * rsf::kMaxR + 1];
-    double sum = 0.0;
-    for (int k = -R; k <= R; ++k) {
-        w[k + R] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
-        sum += w[k + R];
-    }
-    for (int k = 0; k < 2 * R + 1; ++k) t.w[k] = (float)(w[k] / sum);
-    return t;
 }
 
 rsf_status fail(rsf_context *ctx, rsf_status st, const std::string &msg)
@@ -179,43 +153,24 @@ hipError_t timed(rsf_context *ctx, int kind, hipStream_t s, F &&fn)
     return e;
 }
 
-bool finite(float v) { return std::isfinite(v); }
+rsf_status check(rsf_context *ctx, const char *why)
+{
+    return why ? fail(ctx, RSF_ERR_INVALID_ARG, why) : RSF_OK;
+}
 
 rsf_status check_dims(rsf_context *ctx, int64_t nx, int64_t ny, int64_t nz)
 {
-    if (nx < 3 || ny < 3 || nz < 3)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "every dimension must be >= 3");
-    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) || nx * ny > ((int64_t)1 << 31) ||
-        nx * ny > INT64_MAX / nz)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "volume too large");
-    return RSF_OK;
+    return check(ctx, rsf::host::dims_error(nx, ny, nz));
 }
 
 rsf_status check_params(rsf_context *ctx, const rsf_params &p)
 {
-    if (!finite(p.sigma) || !finite(p.lambda1) || !finite(p.lambda2) || !finite(p.nu) ||
-        !finite(p.mu) || !finite(p.dt) || !finite(p.eps) || !finite(p.eta))
-        return fail(ctx, RSF_ERR_INVALID_ARG, "parameters must be finite");
-    if (!(p.sigma > 0.f) || radius_of(p.sigma) > rsf::kMaxR)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "sigma must be > 0 with ceil(3 sigma) <= 16");
-    if (!(p.eps > 0.f)) return fail(ctx, RSF_ERR_INVALID_ARG, "eps must be > 0");
-    if (!(p.dt > 0.f)) return fail(ctx, RSF_ERR_INVALID_ARG, "dt must be > 0");
-    if (p.nu < 0.f || p.mu < 0.f) return fail(ctx, RSF_ERR_INVALID_ARG, "nu and mu must be >= 0");
-    if (p.regulariser != RSF_REG_DOUBLE_WELL && p.regulariser != RSF_REG_SINGLE_WELL)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "unknown regulariser");
-    if (p.storage != RSF_F32 && p.storage != RSF_F16 && p.storage != RSF_BF16)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "storage must be RSF_F32, RSF_F16 or RSF_BF16");
-    return RSF_OK;
+    return check(ctx, rsf::host::params_error(p));
 }
 
 rsf_status check_types(rsf_context *ctx, float sigma, int image, int storage)
 {
-    if (image != RSF_F32 && image != RSF_U16)
-        return fail(ctx, RSF_ERR_INVALID_ARG, "volume dtype must be RSF_F32 or RSF_U16");
-    if (!rsf::types_supported(radius_of(sigma), image, storage))
-        return fail(ctx, RSF_ERR_INVALID_ARG,
-                    "this image/storage combination is built for ceil(3 sigma) in 4..12 only");
-    return RSF_OK;
+    return check(ctx, rsf::host::types_error(sigma, image, storage));
 }
 
 rsf_status check_tiles(rsf_context *ctx, const rsf_tile *tiles, int n, bool need_pointers)
@@ -285,36 +240,35 @@ struct Plan {
     char *base;
     TileDesc *descs;             // device
     Batch xy, z, u, tile;
-    int64_t blocks_xy, blocks_z, blocks_u;
+    int64_t blocks_xy, blocks_z, blocks_u;   // grid sizes
 };
 
-Coeffs make_coeffs(const rsf_params &p, double tol)
+Grid3 grid_of(const rsf_tile &t) { return rsf::host::grid_of(t.nx, t.ny, t.nz); }
+
+// Each tile's share of the batch's voxels.
+std::vector<double> shares_of(const rsf_tile *tiles, int n)
 {
-    Coeffs c{};
-    c.l1 = p.lambda1; c.l2 = p.lambda2; c.nu = p.nu; c.mu = p.mu; c.dt = p.dt;
-    c.eps = p.eps;
-    c.eps_over_pi = (float)((double)p.eps / M_PI);
-    c.eps2 = p.eps * p.eps;
-    c.eta = p.eta > 0.f ? p.eta : 1e-10f;
-    c.reg = p.regulariser == RSF_REG_SINGLE_WELL ? 1 : 0;
-    c.tol = tol;
-    return c;
+    double total = 0.0;
+    for (int t = 0; t < n; ++t) total += (double)tiles[t].nx * tiles[t].ny * tiles[t].nz;
+    std::vector<double> sh;
+    for (int t = 0; t < n; ++t)
+        sh.push_back((double)tiles[t].nx * tiles[t].ny * tiles[t].nz / total);
+    return sh;
 }
 
-Split split_for(rsf_context *ctx, const Grid3 &g, int R)
-{
-    auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
-    if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) return it->second;
-    return rsf::default_split(g);
-}
-
+// Tuned split of the shape if there is one, else the default for its share.
 std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R)
 {
+    const std::vector<double> sh = shares_of(tiles, n);
     std::vector<Split> splits;
     for (int t = 0; t < n; ++t) {
-        const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
-                      tiles[t].nx * tiles[t].ny};
-        splits.push_back(split_for(ctx, g, R));
+        const Grid3 g = grid_of(tiles[t]);
+        Split s = rsf::default_split(g, sh[t]);
+        if (ctx) {
+            auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
+            if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) s = it->second;
+        }
+        splits.push_back(s);
     }
     return splits;
 }
@@ -340,22 +294,9 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     TileDesc *hd = reinterpret_cast<TileDesc *>(h + P.L.descs);
     for (int t = 0; t < n; ++t) {
         const TileLayout &T = P.L.tiles[t];
-        TileDesc d{};
-        d.g = T.g;
-        d.sp = T.sp;
-        d.I = tiles[t].volume;
-        d.phi[0] = tiles[t].phi;
-        d.phi[1] = reinterpret_cast<float *>(base + T.phiB);
-        d.P = base + T.P;
-        d.Q = base + T.Q;
-        d.KI = ki_out ? ki_out : static_cast<void *>(base + T.KI);
-        d.cx = reinterpret_cast<float *>(base + T.cx);
-        d.cy = reinterpret_cast<float *>(base + T.cy);
-        d.cz = reinterpret_cast<float *>(base + T.cz);
-        d.partials = reinterpret_cast<double *>(base + T.partials);
-        d.hist = reinterpret_cast<double *>(base + T.hist);
-        d.hist_cap = iters > 0 ? iters : 1;
-        d.flags = reinterpret_cast<int *>(base + T.flags);
+        TileDesc d = rsf::host::tile_desc(T.g, T.sp, tiles[t].volume, tiles[t].phi,
+                                          base + T.base, T.T, iters, nullptr);
+        if (ki_out) d.KI = ki_out;
         if (probe) {
             d.probe_H = probe->H; d.probe_f1 = probe->f1; d.probe_f2 = probe->f2;
             d.probe_Fd = probe->Fd; d.probe_kappa = probe->kappa; d.probe_lap = probe->lap;
@@ -372,15 +313,21 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     ctx->stage_pending = true;
     P.descs = reinterpret_cast<TileDesc *>(base + P.L.descs);
     auto view = [&](size_t start) {
-        return Batch{P.descs, reinterpret_cast<const int *>(base + start), n, 0};
+        return Batch{P.descs, reinterpret_cast<const int *>(base + start), n, {}};
     };
     P.xy = view(P.L.start_xy);
     P.z = view(P.L.start_z);
     P.u = view(P.L.start_u);
-    P.tile = Batch{P.descs, nullptr, n, 0};
-    P.blocks_xy = P.L.pre_xy.back();
-    P.blocks_z = P.L.pre_z.back();
-    P.blocks_u = P.L.pre_u.back();
+    P.tile = Batch{P.descs, nullptr, n, {}};
+    std::vector<Grid3> gs;
+    std::vector<Split> sps;
+    for (const TileLayout &T : P.L.tiles) {
+        gs.push_back(T.g);
+        sps.push_back(T.sp);
+    }
+    P.blocks_xy = rsf::host::balance_xcds(P.xy, rsf::host::PASS_XY, gs, sps, P.R);
+    P.blocks_z = rsf::host::balance_xcds(P.z, rsf::host::PASS_Z, gs, sps, P.R);
+    P.blocks_u = rsf::host::balance_xcds(P.u, rsf::host::PASS_U, gs, sps, P.R);
     return RSF_OK;
 }
 
@@ -400,12 +347,10 @@ rsf_status prologue(rsf_context *ctx, const Plan &P, hipStream_t s)
     return RSF_OK;
 }
 
-// One iteration of every tile; par = which phi buffer holds the current iterate.
-rsf_status iteration(rsf_context *ctx, const Plan &P, int par, bool probe, hipStream_t s)
+// One iteration of every running tile of the batch.
+rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
 {
-    Batch z = P.z, u = P.u;
-    z.par = par;
-    u.par = par;
+    const Batch &z = P.z, &u = P.u;
     HIP_TRY(timed(ctx, RSF_PASS_Z_HEAVISIDE, s, [&] {
                 return rsf::launch_z_heaviside(P.R, P.image, P.storage, z, P.blocks_z, P.taps,
                                                P.c, probe, s);
@@ -466,24 +411,18 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     st = prologue(ctx, P, s);
     if (st != RSF_OK) return st;
     for (int it = 0; it < iters; ++it) {
-        st = iteration(ctx, P, it & 1, false, s);
+        st = iteration(ctx, P, false, s);
         if (st != RSF_OK) return st;
     }
-    if (iters & 1) {
-        // the last iterate is in the workspace buffer
-        for (int t = 0; t < n; ++t) {
-            const size_t bytes = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float);
-            HIP_TRY(hipMemcpyAsync(tiles[t].phi, base + P.L.tiles[t].phiB, bytes,
-                                   hipMemcpyDeviceToDevice, s),
-                    "copy phi");
-        }
-    }
+    // tiles that ended on an odd iteration have it in the workspace buffer
+    if (iters > 0) HIP_TRY(rsf::launch_finish(P.z, P.blocks_z, s), "finish");
     ctx->last_stream = s;
     ctx->last_hist.clear();
     ctx->last_flags.clear();
     for (int t = 0; t < n; ++t) {
-        ctx->last_hist.push_back(reinterpret_cast<const double *>(base + P.L.tiles[t].hist));
-        ctx->last_flags.push_back(reinterpret_cast<const int *>(base + P.L.tiles[t].flags));
+        const TileLayout &T = P.L.tiles[t];
+        ctx->last_hist.push_back(reinterpret_cast<const double *>(base + T.base + T.T.hist));
+        ctx->last_flags.push_back(reinterpret_cast<const int *>(base + T.base + T.T.flags));
     }
     ctx->last_iters = iters;
     ctx->has_last = true;
@@ -503,7 +442,7 @@ rsf_status time_iterations(rsf_context *ctx, const Plan &P, int iters, hipStream
     rsf_status st = RSF_OK;
     e = hipEventRecord(a, s);
     for (int it = 0; st == RSF_OK && e == hipSuccess && it < iters; ++it)
-        st = iteration(ctx, P, it & 1, false, s);
+        st = iteration(ctx, P, false, s);
     if (e == hipSuccess) e = hipEventRecord(b, s);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
@@ -634,14 +573,9 @@ size_t rsf_batch_workspace_bytes(const rsf_tile *tiles, int n, int iters, int st
     try {
         if (!tiles || n < 1 || iters < 0) return 0;
         if (storage != RSF_F32 && storage != RSF_F16 && storage != RSF_BF16) return 0;
-        std::vector<Split> splits;
-        for (int t = 0; t < n; ++t) {
+        for (int t = 0; t < n; ++t)
             if (tiles[t].nx < 3 || tiles[t].ny < 3 || tiles[t].nz < 3) return 0;
-            const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
-                          tiles[t].nx * tiles[t].ny};
-            splits.push_back(rsf::default_split(g));
-        }
-        return plan_layout(tiles, n, iters, storage, splits).total;
+        return plan_layout(tiles, n, iters, storage, splits_for(nullptr, tiles, n, 0)).total;
     } catch (...) {
         return 0;
     }
@@ -762,11 +696,16 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
         const int64_t cand_z[] = {1024, 2048, 4096};
         const int64_t cand_u[] = {512, 1024, 2048};
         int64_t best[3] = {16384, 2048, 1024};
+        // targets are for the whole batch; each tile gets its voxel share
+        const std::vector<double> sh = shares_of(tiles, n_tiles);
         auto apply = [&](const int64_t tg[3]) {
             for (int t = 0; t < n_tiles; ++t) {
-                const Grid3 g{(int)tiles[t].nx, (int)tiles[t].ny, (int)tiles[t].nz,
-                              tiles[t].nx * tiles[t].ny};
-                ctx->tuned[{g.nx, g.ny, g.nz, R}] = rsf::make_split(g, tg[0], tg[1], tg[2]);
+                const Grid3 g = grid_of(tiles[t]);
+                const auto part = [&](int64_t v) {
+                    return (int64_t)std::max(1.0, std::ceil((double)v * sh[t]));
+                };
+                ctx->tuned[{g.nx, g.ny, g.nz, R}] =
+                    rsf::make_split(g, part(tg[0]), part(tg[1]), part(tg[2]));
             }
         };
         float best_ms = -1.f;
@@ -791,7 +730,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                                static_cast<char *>(ctx->ws), s);
                 if (st == RSF_OK) st = prologue(ctx, P, s);
                 float ms = 0.f;
-                if (st == RSF_OK) st = iteration(ctx, P, 0, false, s);   // warm-up
+                if (st == RSF_OK) st = iteration(ctx, P, false, s);   // warm-up
                 if (st == RSF_OK) st = time_iterations(ctx, P, trial_iters, s, &ms);
                 if (st != RSF_OK) break;
                 if (best_ms < 0.f || ms < best_ms) {
@@ -882,7 +821,7 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
         if (st != RSF_OK) return st;
         st = prologue(ctx, P, s);
         if (st != RSF_OK) return st;
-        return iteration(ctx, P, 0, true, s);
+        return iteration(ctx, P, true, s);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }

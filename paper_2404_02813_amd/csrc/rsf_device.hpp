@@ -1,0 +1,125 @@
+// Device helpers shared by every kernel: element conversions, the pair
+// layout, reflection, the XCD-aware workgroup numbering, the tile lookup of a
+// batched launch and the column/z-chunk decomposition of the z passes.
+#pragma once
+
+#include "rsf_internal.hpp"
+
+namespace rsf {
+
+namespace {
+
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kTwoPi = 6.28318530717958647693f;
+
+__device__ __forceinline__ float heaviside(float phi, float eps)
+{
+    // 1/2 (1 + (2/pi) atan(phi/eps)) written as atan2(eps, -phi)/pi, which
+    // keeps full relative precision for large negative phi.
+    return atan2f(eps, -phi) * kInvPi;
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Storage and image element types: fields may be stored as float, FP16 or
+// BF16 (arithmetic is always FP32); the image may be float or uint16, the
+// latter normalised to [0, 1] as u / 65535 on load.
+__device__ __forceinline__ float to_f(float v) { return v; }
+__device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
+__device__ __forceinline__ float to_f(uint16_t v) { return (float)v * (1.f / 65535.f); }
+template <class T>
+__device__ __forceinline__ T from_f(float v) { return (T)v; }   // round to nearest even
+
+// The two fields every pass reads or writes together (Kz*(HI) and Kz*H; g1
+// and g2; their xy convolutions) are stored interleaved, so one 4-byte (FP16,
+// BF16) or 8-byte (FP32) access per lane moves both.
+template <class T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
+// Make `v` opaque to the optimiser: it must be computed here, so a sum that
+// feeds a register ring is not sunk to its distant use (which would keep all
+// of its inputs live instead of one value).
+__device__ __forceinline__ void pin(float &v) { __asm__ volatile("" : "+v"(v)); }
+
+__device__ __forceinline__ int reflect(int i, int n)
+{
+    return i < 0 ? -i : (i > n - 1 ? 2 * (n - 1) - i : i);
+}
+
+// The tile owning workgroup number gb: the last t with start[t] <= gb.
+__device__ __forceinline__ int find_tile(const int *start, int n, int gb)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= gb) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// This workgroup's tile and its workgroup number within the tile; false for
+// a surplus workgroup (the whole workgroup must then return).
+struct Where {
+    int t, lb;
+};
+__device__ __forceinline__ bool locate(const Batch &bt, Where &w)
+{
+    const int k = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const int gb = bt.xcd[k] + j;
+    if (gb >= bt.xcd[k + 1]) return false;
+    w.t = find_tile(bt.start, bt.n, gb);
+    w.lb = gb - bt.start[w.t];
+    return true;
+}
+
+// Workgroup lb of a tile in the update pass.
+struct ZTile {
+    int x, y, z0, z1, tile;
+    bool active;
+};
+
+// Workgroup lb of a tile covers (TX x TY columns) x (one z chunk), z chunk
+// fastest.
+template <int TX, int TY>
+__device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc, int lb)
+{
+    ZTile zt;
+    const int tile = lb;
+    const int nbx = (g.nx + TX - 1) / TX;
+    const int zc = tile % nzc, col = tile / nzc;
+    const int lz = (g.nz + nzc - 1) / nzc;
+    zt.x = (col % nbx) * TX + (threadIdx.x & (TX - 1));
+    zt.y = (col / nbx) * TY + (threadIdx.x / TX);
+    zt.z0 = zc * lz;
+    zt.z1 = min(zt.z0 + lz, g.nz);
+    zt.tile = tile;
+    zt.active = zt.x < g.nx && zt.y < g.ny;
+    return zt;
+}
+
+// Workgroup lb of a tile in the z passes: kThreads consecutive columns
+// (y nx + x, so every access is contiguous across row ends) times one z
+// chunk, z chunk fastest.
+struct ZCols {
+    int col, z0, z1;
+    bool active;
+};
+__device__ __forceinline__ ZCols z_cols(const Grid3 &g, int nzc, int lb)
+{
+    ZCols zc;
+    const int c = lb % nzc, cb = lb / nzc;
+    const int lz = (g.nz + nzc - 1) / nzc;
+    zc.col = cb * kThreads + (int)threadIdx.x;
+    zc.z0 = c * lz;
+    zc.z1 = min(zc.z0 + lz, g.nz);
+    zc.active = zc.col < g.sxy;
+    return zc;
+}
+
+}  // namespace
+
+}  // namespace rsf

@@ -15,9 +15,8 @@
 namespace rsf {
 
 constexpr int kMaxR = 16;          // largest Gaussian radius (sigma <= 16/3)
-constexpr int kZx = 64;            // z pass: columns per block along x
-constexpr int kZy = 4;             // z pass: columns per block along y
-constexpr int kThreads = 256;      // z pass block
+constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
+constexpr int kThreads = 256;      // z pass block: consecutive columns
 constexpr int kUx = 64;            // update pass: columns per block along x
 constexpr int kUy = 8;             // update pass: columns per block along y
 constexpr int kUThreads = kUx * kUy;
@@ -54,8 +53,8 @@ struct TileDesc {
     float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
     double *partials;       // one sum |dphi| per update-pass block
     double *hist;           // sum |dphi| per iteration run
-    int hist_cap;           // entries of hist
-    int *flags;             // [0] stopped early, [1] iterations run
+    int hist_cap;           // entries of hist = iterations asked of this tile
+    int *flags;             // [0] 0 running, 1 stopped by tol, 2 done; [1] iterations run
     // one-step probe outputs (float fields), null when unused
     float *probe_H, *probe_f1, *probe_f2, *probe_Fd, *probe_kappa, *probe_lap, *probe_R,
         *probe_E;
@@ -70,14 +69,20 @@ struct Coeffs {
     double tol;                     // stop a tile once sum|dphi| / voxels < tol (0: never)
 };
 
-// A pass over a batch: the tiles, the pass's workgroup prefix table (n + 1
-// entries: tile t owns workgroups [start[t], start[t+1])), and which phi
-// buffer holds the current iterate.
+// A pass over a batch: the tiles and the pass's workgroup prefix table (n + 1
+// entries: tile t owns workgroups [start[t], start[t+1])).  A tile's current
+// iterate n (flags[1]) is in phi[n & 1], so tiles of one batch may be at
+// different iterations.
+//
+// Workgroups are dispatched to the XCDs round robin (hardware workgroup b on
+// XCD b % 8).  XCD k takes the contiguous range [xcd[k], xcd[k+1]) of the
+// batch's workgroups, the ranges cut for equal estimated cost; the grid is 8
+// times the longest range and the surplus workgroups exit at once.
 struct Batch {
     const TileDesc *tiles;
     const int *start;
     int n;
-    int par;
+    int xcd[kXcds + 1];
 };
 
 // Workgroup counts of one tile under a split.
@@ -86,9 +91,12 @@ __host__ __device__ inline int64_t xy_blocks(const Grid3 &g, const Split &s)
 {
     return (int64_t)nbx64(g.nx) * s.xy * g.nz;
 }
+// z passes: workgroups of kThreads consecutive columns (y nx + x) times a z
+// chunk.
+__host__ __device__ inline int64_t z_cols(const Grid3 &g) { return (g.sxy + kThreads - 1) / kThreads; }
 __host__ __device__ inline int64_t z_blocks(const Grid3 &g, const Split &s)
 {
-    return (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy) * s.z;
+    return z_cols(g) * s.z;
 }
 __host__ __device__ inline int64_t u_blocks(const Grid3 &g, const Split &s)
 {
@@ -98,7 +106,13 @@ __host__ __device__ inline int64_t u_blocks(const Grid3 &g, const Split &s)
 // Split of one volume aiming at the given workgroup counts per pass (the
 // autotuner varies them); every chunk is non-empty and at least 8 long.
 Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_target);
-Split default_split(const Grid3 &g);
+// Default split of a tile holding fraction `share` of its batch's voxels.
+Split default_split(const Grid3 &g, double share = 1.0);
+// Update-pass workgroups of a tile under any valid split are at most this.
+__host__ __device__ inline int64_t u_blocks_max(const Grid3 &g)
+{
+    return (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy) * ((g.nz + 7) / 8);
+}
 bool split_valid(const Grid3 &g, const Split &s);
 
 bool types_supported(int R, int image_dtype, int storage_dtype);
@@ -124,8 +138,11 @@ hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const B
 hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const Batch &b,
                            int64_t blocks, const Taps &t, const Coeffs &c, bool probe,
                            hipStream_t s);
-// One workgroup per tile: fixed-order FP64 sum of the partials.
+// One workgroup per tile: fixed-order FP64 sum of the partials; counts the
+// iteration and stops the tile at its tolerance or its last iteration.
 hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s);
+// Copy an odd final iterate from phi[1] to phi[0] (workgroups of the z pass).
+hipError_t launch_finish(const Batch &b, int64_t blocks, hipStream_t s);
 
 // Per-radius, per-type launchers behind the dispatchers (rsf_kernels.hpp).
 template <int R, class IT, class ST>

@@ -19,7 +19,10 @@
 // needs.  Every pass is one launch over a batch of tiles; workgroups are
 // numbered so that each of the 8 XCDs works on one contiguous range, keeping
 // halo re-reads within one L2.
-#include "rsf_internal.hpp"
+#include <algorithm>
+#include <cmath>
+
+#include "rsf_device.hpp"
 
 namespace rsf {
 
@@ -68,64 +71,33 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(Batch bt, Coeffs c)
     if (threadIdx.x == 0) {
         const int k = d.flags[1];
         if (k < d.hist_cap) d.hist[k] = sh[0];
+        *reinterpret_cast<double *>(d.flags + 2) = sh[0];   // last sum, 8-byte aligned
         d.flags[1] = k + 1;
         const double voxels = (double)d.g.nx * d.g.ny * d.g.nz;
         if (c.tol > 0.0 && sh[0] < c.tol * voxels) d.flags[0] = 1;
+        else if (k + 1 >= d.hist_cap) d.flags[0] = 2;   // all its iterations done
     }
+}
+
+// After the last iteration: a tile whose final iterate n is odd has it in the
+// workspace buffer phi[1]; copy it to the caller's phi[0].  Workgroups as in
+// the stage-1 z pass.
+__global__ __launch_bounds__(kThreads) void finish_kernel(Batch bt)
+{
+    Where wh;
+    if (!locate(bt, wh)) return;
+    const TileDesc &d = bt.tiles[wh.t];
+    if (!(d.flags[1] & 1)) return;
+    const Grid3 g = d.g;
+    const ZCols zt = z_cols(g, d.sp.z, wh.lb);
+    if (!zt.active) return;
+    const int col = zt.col;
+    const float *__restrict__ src = d.phi[1];
+    float *__restrict__ dst = d.phi[0];
+    for (int z = zt.z0; z < zt.z1; ++z) (dst + (int64_t)z * g.sxy)[col] = (src + (int64_t)z * g.sxy)[col];
 }
 
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// Splits
-// ---------------------------------------------------------------------------
-
-// The fewest chunks giving at least `want_blocks` over `cols` columns, each
-// chunk at least `least` long; re-derived so every chunk is non-empty.
-static int chunks(int64_t n, int64_t cols, int64_t want_blocks, int64_t least)
-{
-    int64_t want = (want_blocks + cols - 1) / cols;
-    const int64_t most = (n + least - 1) / least;
-    if (want > most) want = most;
-    if (want < 1) want = 1;
-    const int64_t len = (n + want - 1) / want;
-    return (int)((n + len - 1) / len);
-}
-
-Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_target)
-{
-    Split s;
-    const int64_t strips = nbx64(g.nx);
-    s.xy = chunks(g.ny, strips * g.nz, xy_waves, 8);
-    s.z = chunks(g.nz, (int64_t)((g.nx + kZx - 1) / kZx) * ((g.ny + kZy - 1) / kZy), z_target, 8);
-    s.u = chunks(g.nz, (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy), u_target, 8);
-    return s;
-}
-
-// xy: enough row chunks for ~16K waves but chunks no shorter than needed for
-// 128-row chunks; z: ~2K workgroups; update: ~1K workgroups.
-Split default_split(const Grid3 &g)
-{
-    Split s = make_split(g, 16384, 2048, 1024);
-    const int base = (g.ny + 127) / 128;
-    if (s.xy < base) {
-        const int64_t len = (g.ny + base - 1) / base;
-        s.xy = (int)((g.ny + len - 1) / len);
-    }
-    return s;
-}
-
-static bool chunks_ok(int n, int c)
-{
-    if (c < 1 || c > n) return false;
-    const int len = (n + c - 1) / c;
-    return (c - 1) * len < n;
-}
-
-bool split_valid(const Grid3 &g, const Split &s)
-{
-    return chunks_ok(g.ny, s.xy) && chunks_ok(g.nz, s.z) && chunks_ok(g.nz, s.u);
-}
 
 // ---------------------------------------------------------------------------
 // Launchers
@@ -140,6 +112,12 @@ hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s)
 hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s)
 {
     hipLaunchKernelGGL(reduce_kernel, dim3(b.n), dim3(kThreads), 0, s, b, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Batch &b, int64_t blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -3,86 +3,11 @@
 // units that instantiate them for a range of radii (rsf_inst_*.hip).
 #pragma once
 
-#include "rsf_internal.hpp"
+#include "rsf_device.hpp"
 
 namespace rsf {
 
 namespace {
-
-
-constexpr float kInvPi = 0.318309886183790671538f;
-constexpr float kTwoPi = 6.28318530717958647693f;
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ float heaviside(float phi, float eps)
-{
-    // 1/2 (1 + (2/pi) atan(phi/eps)) written as atan2(eps, -phi)/pi, which
-    // keeps full relative precision for large negative phi.
-    return atan2f(eps, -phi) * kInvPi;
-}
-
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Storage and image element types: fields may be stored as float, FP16 or
-// BF16 (arithmetic is always FP32); the image may be float or uint16, the
-// latter normalised to [0, 1] as u / 65535 on load.
-__device__ __forceinline__ float to_f(float v) { return v; }
-__device__ __forceinline__ float to_f(_Float16 v) { return (float)v; }
-__device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
-__device__ __forceinline__ float to_f(uint16_t v) { return (float)v * (1.f / 65535.f); }
-template <class T>
-__device__ __forceinline__ T from_f(float v) { return (T)v; }   // round to nearest even
-
-// The two fields every pass reads or writes together (Kz*(HI) and Kz*H; g1
-// and g2; their xy convolutions) are stored interleaved, so one 4-byte (FP16,
-// BF16) or 8-byte (FP32) access per lane moves both.
-template <class T>
-struct alignas(2 * sizeof(T)) Pair {
-    T a, b;
-};
-
-// Make `v` opaque to the optimiser: it must be computed here, so a sum that
-// feeds a register ring is not sunk to its distant use (which would keep all
-// of its inputs live instead of one value).
-__device__ __forceinline__ void pin(float &v) { __asm__ volatile("" : "+v"(v)); }
-
-__device__ __forceinline__ int reflect(int i, int n)
-{
-    return i < 0 ? -i : (i > n - 1 ? 2 * (n - 1) - i : i);
-}
-
-// Workgroup b runs on XCD b % 8.  Give XCD k the contiguous range
-// [k*per + min(k, rem), ...) of the batch's workgroup numbers, so spatial
-// neighbours (and each tile) share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int n)
-{
-    const int per = n / kXcds, rem = n % kXcds;
-    const int x = b % kXcds, local = b / kXcds;
-    return x * per + min(x, rem) + local;
-}
-
-// The tile owning workgroup number gb: the last t with start[t] <= gb.
-__device__ __forceinline__ int find_tile(const int *start, int n, int gb)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= gb) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// This workgroup's tile and its workgroup number within the tile.
-struct Where {
-    int t, lb;
-};
-__device__ __forceinline__ Where locate(const Batch &bt)
-{
-    const int gb = xcd_tile(blockIdx.x, gridDim.x);
-    const int t = find_tile(bt.start, bt.n, gb);
-    return Where{t, gb - bt.start[t]};
-}
 
 // ---------------------------------------------------------------------------
 // xy pass as a march along y.  One wave owns a 64-wide strip of one z slice
@@ -103,7 +28,8 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     constexpr int RW = 64 + 2 * R;
     __shared__ float row[2][NF][RW];
 
-    const Where wh = locate(bt);
+    Where wh;
+    if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
     if (d.flags[0]) return;
     const Grid3 g = d.g;
@@ -249,34 +175,6 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 // compile-time slots by unrolling the march in steps of 2R+1.
 // ---------------------------------------------------------------------------
 
-struct ZTile {
-    int x, y, z0, z1, tile;
-    bool active;
-};
-
-// Workgroup lb of a tile covers (TX x TY columns) x (one z chunk), z chunk
-// fastest.
-template <int TX, int TY>
-__device__ __forceinline__ ZTile z_tile_t(const Grid3 &g, int nzc, int lb)
-{
-    ZTile zt;
-    const int tile = lb;
-    const int nbx = (g.nx + TX - 1) / TX;
-    const int zc = tile % nzc, col = tile / nzc;
-    const int lz = (g.nz + nzc - 1) / nzc;
-    zt.x = (col % nbx) * TX + (threadIdx.x & (TX - 1));
-    zt.y = (col / nbx) * TY + (threadIdx.x / TX);
-    zt.z0 = zc * lz;
-    zt.z1 = min(zt.z0 + lz, g.nz);
-    zt.tile = tile;
-    zt.active = zt.x < g.nx && zt.y < g.ny;
-    return zt;
-}
-
-__device__ __forceinline__ ZTile z_tile(const Grid3 &g, int nzc, int lb)
-{
-    return z_tile_t<kZx, kZy>(g, nzc, lb);
-}
 
 // Conv ring.  fetch(z) loads the raw inputs of slice z (0 <= z < nz) and
 // cook(raw, z) turns them into the two convolved quantities; each slice is
@@ -335,14 +233,15 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
 template <int R, class ST>
 __global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t)
 {
-    const Where wh = locate(bt);
+    Where wh;
+    if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
     const Grid3 g = d.g;
     const ST *__restrict__ in = static_cast<const ST *>(d.P);
     ST *__restrict__ out = static_cast<ST *>(d.KI);
-    const ZTile zt = z_tile(g, d.sp.z, wh.lb);
+    const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
-    const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
+    const int col = zt.col;   // nx * ny < 2^31 - 1024
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) { return make_float2(to_f((in + (int64_t)z * g.sxy)[col]), 0.f); },
@@ -354,18 +253,19 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t)
 template <int R, bool PROBE, class ST, class IT>
 __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t, Coeffs c)
 {
-    const Where wh = locate(bt);
+    Where wh;
+    if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
     if (d.flags[0]) return;
     const Grid3 g = d.g;
-    const float *__restrict__ phi = d.phi[bt.par];
+    const float *__restrict__ phi = d.phi[d.flags[1] & 1];   // iterate n is in phi[n & 1]
     const IT *__restrict__ I = static_cast<const IT *>(d.I);
     Pair<ST> *__restrict__ tp = static_cast<Pair<ST> *>(d.P);
     float *__restrict__ probeH = d.probe_H;
     const float eps = c.eps;
-    const ZTile zt = z_tile(g, d.sp.z, wh.lb);
+    const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
-    const int col = zt.y * g.nx + zt.x;   // nx * ny < 2^31
+    const int col = zt.col;   // nx * ny < 2^31 - 1024
     z_march<R, 2>(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
@@ -432,27 +332,24 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
     __shared__ float sq[NQ][4][QS];   // n_x, V_x, n_y, V_y
     __shared__ double wsum[NT / 64];
 
-    const Where wh = locate(bt);
+    Where wh;
+    if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
+    // a stopped tile keeps its last iterate where it is (the whole block
+    // leaves; its partial is not read)
+    if (d.flags[0]) return;
     const Grid3 g = d.g;
     const Pair<ST> *__restrict__ tp = static_cast<const Pair<ST> *>(d.P);
-    const float *__restrict__ phi = d.phi[bt.par];
-    float *__restrict__ phi_out = d.phi[bt.par ^ 1];
+    const int cur = d.flags[1] & 1;   // iterate n is in phi[n & 1]
+    const float *__restrict__ phi = d.phi[cur];
+    float *__restrict__ phi_out = d.phi[cur ^ 1];
     const ZTile zt = z_tile_t<TX, TY>(g, d.sp.u, wh.lb);
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1), ty = tid / TX;
     const int x0 = zt.x - tx, y0 = zt.y - ty;
-    const bool stopped = d.flags[0] != 0;
     double acc = 0.0;
 
-    if (stopped) {
-        // a stopped tile keeps phi: copy it so the ping-pong stays consistent
-        if (zt.active) {
-            const int col = zt.y * g.nx + zt.x;
-            for (int z = zt.z0; z < zt.z1; ++z)
-                (phi_out + (int64_t)z * g.sxy)[col] = (phi + (int64_t)z * g.sxy)[col];
-        }
-    } else {
+    {
         // phi tile loads: reflected in-slice offsets of this thread's points
         int loff[NLD];
         bool lok[NLD];

@@ -221,3 +221,57 @@ class TileWorkload:
 # halo, cut from a 1024x1024x512 phantom of 1500 tubes r 1-4; 100 iterations.
 TILES_64 = TileWorkload("tiles64_s3_it100", (512, 1024, 1024), 1500, 1.0, 4.0, seed=3,
                         n_tiles=64, edges=(96, 128, 160, 192, 256), halo=9, iters=100)
+
+
+@dataclass(frozen=True)
+class ServeWorkload:
+    """A stream of tile requests cut from one uint16 volume: interior edge
+    lengths drawn per axis from `edges`, sigma from `sigmas`, iterations
+    uniform in [it_lo, it_hi], a ceil(3 sigma) halo on every side, box phi0,
+    Poisson arrivals (rate set by the caller)."""
+    name: str
+    shape: tuple            # volume (nz, ny, nx)
+    n_tubes: int
+    r_min: float
+    r_max: float
+    seed: int
+    n_requests: int
+    edges: tuple
+    sigmas: tuple
+    it_lo: int
+    it_hi: int
+    storage: str = "f16"
+    lambda1: float = 1.0
+    lambda2: float = 1.0
+    nu: float = 0.001
+    mu: float = 1.0
+    dt: float = 0.1
+    eps: float = 1.0
+
+    def volume(self) -> np.ndarray:
+        return u16_phantom(self.shape, self.n_tubes, self.r_min, self.r_max, self.seed)
+
+    def requests(self, n: int | None = None):
+        """[(origin_zyx, extent_zyx, sigma, halo, iters)] in arrival order."""
+        rng = rng_for(self.seed + 200)
+        out = []
+        for _ in range(int(n if n is not None else self.n_requests)):
+            sigma = float(rng.choice(self.sigmas))
+            halo = int(math.ceil(3.0 * sigma - 1e-9))
+            ext = [int(rng.choice(self.edges)) + 2 * halo for _ in range(3)]
+            org = [int(rng.integers(0, d - e + 1)) for d, e in zip(self.shape, ext)]
+            iters = int(rng.integers(self.it_lo, self.it_hi + 1))
+            out.append((tuple(org), tuple(ext), sigma, halo, iters))
+        return out
+
+    def params(self, sigma: float) -> dict:
+        return dict(sigma=sigma, lambda1=self.lambda1, lambda2=self.lambda2, nu=self.nu,
+                    mu=self.mu, dt=self.dt, eps=self.eps)
+
+
+# 2000 requests cut from the 1024x1024x512 uint16 volume (1500 tubes r 1-4,
+# seed 4): interior edges {64, 96, ..., 384} per axis, sigma in {2, 3, 4},
+# 50-150 iterations, FP16 storage.
+SERVE_2000 = ServeWorkload("serve2000_u16_f16", (512, 1024, 1024), 1500, 1.0, 4.0, seed=4,
+                           n_requests=2000, edges=tuple(range(64, 385, 32)),
+                           sigmas=(2.0, 3.0, 4.0), it_lo=50, it_hi=150)

@@ -15,6 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsf.so")
 
+RSF_NOT_READY = 1
 RSF_OK = 0
 RSF_ERR_INVALID_ARG = -1
 RSF_ERR_OUT_OF_MEMORY = -2
@@ -34,7 +35,10 @@ RSF_REG_SINGLE_WELL = 1
 EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
-           "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset")
+           "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
+           "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
+           "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
+           "rsf_server_destroy")
 
 PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce")
 
@@ -64,6 +68,33 @@ class rsf_tile(ctypes.Structure):
 
 class rsf_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int * 6), ("ms", ctypes.c_double * 6)]
+
+
+class rsf_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
+                ("segment_bytes", ctypes.c_size_t), ("chunk_iters", ctypes.c_int),
+                ("max_resident", ctypes.c_int)]
+
+
+class rsf_request(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("volume_dtype", ctypes.c_int),
+                ("params", rsf_params), ("iters", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+class rsf_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters_run", ctypes.c_int),
+                ("last_sum_abs", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class rsf_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("pending", ctypes.c_int), ("resident", ctypes.c_int),
+                ("peak_resident", ctypes.c_int), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t), ("bytes_reserved", ctypes.c_size_t),
+                ("chunks", ctypes.c_uint64), ("voxel_iters", ctypes.c_double)]
 
 
 PROBE_NAMES = ("H", "f1", "f2", "Fd", "kappa", "lap", "R", "E", "phi_next")
@@ -118,6 +149,24 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.restype = i
     L.rsf_autotune_reset.argtypes = [vp]
     L.rsf_autotune_reset.restype = None
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.rsf_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(rsf_server_config)]
+    L.rsf_server_create.restype = i
+    L.rsf_server_submit.argtypes = [vp, ctypes.POINTER(rsf_request), u64p]
+    L.rsf_server_submit.restype = i
+    L.rsf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(rsf_result)]
+    L.rsf_server_poll.restype = i
+    L.rsf_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double,
+                                  ctypes.POINTER(rsf_result)]
+    L.rsf_server_wait.restype = i
+    L.rsf_server_drain.argtypes = [vp]
+    L.rsf_server_drain.restype = i
+    L.rsf_server_get_stats.argtypes = [vp, ctypes.POINTER(rsf_server_stats)]
+    L.rsf_server_get_stats.restype = i
+    L.rsf_server_last_error.argtypes = [vp]
+    L.rsf_server_last_error.restype = ctypes.c_char_p
+    L.rsf_server_destroy.argtypes = [vp]
+    L.rsf_server_destroy.restype = None
     L.rsf_profile_enable.argtypes = [vp, i]
     L.rsf_profile_enable.restype = i
     L.rsf_profile_read.argtypes = [vp, ctypes.POINTER(rsf_profile)]
@@ -381,3 +430,126 @@ class Context:
 
     def profile_read(self) -> dict:
         return rsf_profile_read(self.handle)
+
+
+# ---------------------------------------------------------------------------
+# Request server
+# ---------------------------------------------------------------------------
+
+def _server_check(srv, status: int) -> None:
+    if status not in (RSF_OK, RSF_NOT_READY):
+        msg = lib().rsf_server_last_error(srv).decode(errors="replace") if srv else ""
+        raise RsfError(status, msg)
+
+
+def rsf_server_create(budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
+                      segment_bytes: int = 0, device: int = 0) -> ctypes.c_void_p:
+    cfg = rsf_server_config(device, int(budget_bytes), int(segment_bytes), int(chunk_iters),
+                            int(max_resident))
+    h = ctypes.c_void_p()
+    st = lib().rsf_server_create(ctypes.byref(h), ctypes.byref(cfg))
+    if st != RSF_OK:
+        raise RsfError(st, "rsf_server_create failed")
+    return h
+
+
+def rsf_server_submit(srv, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
+                      iters: int, tol: float = 0.0) -> int:
+    _field(volume, "volume", "image")
+    _field(phi, "phi")
+    if volume.shape != phi.shape:
+        raise ValueError("volume and phi must have the same shape")
+    nz, ny, nx = phi.shape
+    req = rsf_request(volume.data_ptr(), phi.data_ptr(), nx, ny, nz, _IMAGE_DTYPES[volume.dtype],
+                      params, int(iters), float(tol))
+    t = ctypes.c_uint64()
+    _server_check(srv, lib().rsf_server_submit(srv, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def _result_dict(r: rsf_result) -> dict:
+    return {k: getattr(r, k) for k, _ in rsf_result._fields_}
+
+
+def rsf_server_poll(srv, ticket: int):
+    r = rsf_result()
+    st = lib().rsf_server_poll(srv, ticket, ctypes.byref(r))
+    _server_check(srv, st)
+    return None if st == RSF_NOT_READY else _result_dict(r)
+
+
+def rsf_server_wait(srv, ticket: int, timeout_s: float = -1.0):
+    r = rsf_result()
+    st = lib().rsf_server_wait(srv, ticket, float(timeout_s), ctypes.byref(r))
+    _server_check(srv, st)
+    return None if st == RSF_NOT_READY else _result_dict(r)
+
+
+def rsf_server_drain(srv) -> None:
+    _server_check(srv, lib().rsf_server_drain(srv))
+
+
+def rsf_server_get_stats(srv) -> dict:
+    s = rsf_server_stats()
+    _server_check(srv, lib().rsf_server_get_stats(srv, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in rsf_server_stats._fields_}
+
+
+def rsf_server_last_error(srv) -> str:
+    return lib().rsf_server_last_error(srv).decode(errors="replace")
+
+
+def rsf_server_destroy(srv) -> None:
+    lib().rsf_server_destroy(srv)
+
+
+class Server:
+    """Owning wrapper of an rsf_server.  Keeps a reference to each request's
+    tensors until its result has been read, so they outlive the device work."""
+
+    def __init__(self, budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
+                 segment_bytes: int = 0, device: int = 0):
+        self.handle = rsf_server_create(budget_bytes, chunk_iters, max_resident, segment_bytes,
+                                        device)
+        self._held = {}
+
+    def submit(self, volume, phi, params, iters, tol=0.0) -> int:
+        t = rsf_server_submit(self.handle, volume, phi, params, iters, tol)
+        self._held[t] = (volume, phi)
+        return t
+
+    def poll(self, ticket):
+        r = rsf_server_poll(self.handle, ticket)
+        if r is not None:
+            self._held.pop(ticket, None)
+        return r
+
+    def wait(self, ticket, timeout_s=-1.0):
+        r = rsf_server_wait(self.handle, ticket, timeout_s)
+        if r is not None:
+            self._held.pop(ticket, None)
+        return r
+
+    def drain(self):
+        rsf_server_drain(self.handle)
+
+    def stats(self) -> dict:
+        return rsf_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            rsf_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

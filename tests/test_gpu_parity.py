@@ -394,8 +394,8 @@ def batch_inputs(seed=51):
 
 
 def test_batch_equals_each_tile_alone(rsf):
-    """A tile's result (and its sum|dphi| history) is bitwise the same alone
-    and in a batch of uneven tiles."""
+    """A tile's phi is bitwise the same alone and in a batch of uneven tiles
+    (its sum|dphi| history up to the grouping of the FP64 partials)."""
     mod, ctx = rsf
     say("batch vs alone (bitwise)")
     vols, phis = batch_inputs()
@@ -410,7 +410,9 @@ def test_batch_equals_each_tile_alone(rsf):
         _, run, _, ha = ctx.stats(cap=12)
         torch.cuda.synchronize()
         assert torch.equal(alone, batch[k]), k
-        assert run == 12 and ha == hb[k]
+        # the FP64 sums group their partials per update workgroup, which
+        # depends on the tile's share of the batch: equal up to that rounding
+        assert run == 12 and ha == pytest.approx(hb[k], rel=1e-12, abs=0.0)
 
 
 def test_batch_matches_oracle(rsf):
