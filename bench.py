@@ -24,10 +24,18 @@ sys.path.insert(0, ROOT)
 METRIC = "Gvoxel-iter/s at 512^3 sigma=3 (% HBM peak); p50/p99 tile latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
-def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4) -> dict:
+def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4, paper: bool = False) -> dict:
     """Algorithmic HBM bytes per voxel for one launch of each pass: the reads
-    and writes the pass must make, each field once (phi is always FP32)."""
+    and writes the pass must make, each field once (phi is always FP32).
+    paper: the Sec. 4.2 force with sigma2 = 0 (no second Gaussian stage; the
+    force itself is FP32)."""
     i, s = image_bytes, storage_bytes
+    if paper:
+        return {
+            "z_heaviside": 4 + i + 2 * s,   # phi, I -> Kz*(HI), Kz*H
+            "xy_fits": 3 * s + i + 4,       # Kz*(HI), Kz*H, K*I, I -> F_d
+            "z_update": 12,                 # F_d, phi -> phi'
+        }
     return {
         "z_heaviside": 4 + i + 2 * s,   # phi, I -> Kz*(HI), Kz*H
         "xy_fits": 5 * s,               # Kz*(HI), Kz*H, K*I -> g1, g2
@@ -40,18 +48,21 @@ PASS_BYTES = pass_bytes()               # FP32 image and fields
 ITER_BYTES = sum(PASS_BYTES.values())   # 72 B per voxel-iteration
 COPY_BYTES = 1 << 30
 
-# name -> (workload, image dtype, storage dtype)
+# name -> (workload, image dtype, storage dtype, force form)
 def workloads():
     from paper_2404_02813_amd import inputs
     big = inputs.Workload("mixed1024x1024x512_s4_it150", (512, 1024, 1024), 1500, 1.0, 4.0,
                           seed=4, iters=150, sigma=4.0)
     return {
-        inputs.LARGE_512.name: (inputs.LARGE_512, "f32", "f32"),
-        inputs.SMALL_64.name: (inputs.SMALL_64, "f32", "f32"),
-        inputs.LARGE_512.name + "_f16": (inputs.LARGE_512, "f32", "f16"),
-        big.name + "_u16_f16": (big, "u16", "f16"),
-        big.name + "_u16_bf16": (big, "u16", "bf16"),
-        big.name + "_u16_f32": (big, "u16", "f32"),
+        inputs.LARGE_512.name: (inputs.LARGE_512, "f32", "f32", "rsf"),
+        inputs.SMALL_64.name: (inputs.SMALL_64, "f32", "f32", "rsf"),
+        inputs.LARGE_512.name + "_f16": (inputs.LARGE_512, "f32", "f16", "rsf"),
+        big.name + "_u16_f16": (big, "u16", "f16", "rsf"),
+        big.name + "_u16_bf16": (big, "u16", "bf16", "rsf"),
+        big.name + "_u16_f32": (big, "u16", "f32", "rsf"),
+        # the force of Sec. 4.2 with sigma2 = 0
+        inputs.LARGE_512.name + "_paper": (inputs.LARGE_512, "f32", "f32", "paper"),
+        big.name + "_u16_f16_paper": (big, "u16", "f16", "paper"),
     }
 
 KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
@@ -144,7 +155,7 @@ def ingest_counters(fetch_dir: str, write_dir: str, workload: str, copy_bytes: i
     return data
 
 
-def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = ""):
+def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = "", force: int = 0):
     """The FP64 oracle on a centred crop (at most 192 per axis) of the same
     image and phi0 (bounded sample)."""
     import numpy as np
@@ -155,7 +166,7 @@ def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = ""):
     sl = tuple(slice((s - n) // 2, (s - n) // 2 + n) for s, n in zip(I.shape, ext))
     Ic = np.ascontiguousarray(I[sl], dtype=np.float64)
     pc = np.ascontiguousarray(phi0[sl], dtype=np.float64)
-    p = oracle.params_array(**w.params(), eta=1e-10)
+    p = oracle.params_array(**w.params(), eta=1e-10, force=force)
     t0 = time.perf_counter()
     oracle.evolve(Ic, pc, p, 1)
     t1 = time.perf_counter()
@@ -248,7 +259,7 @@ def run_tiles(args, w) -> int:
     t_loop = timed_once(lambda: [ctx.evolve_ex(v, p, params, w.iters) for v, p in zip(vols, ph)])
     loop_result = ph
     t_tune = time.perf_counter()
-    ctx.autotune(vols, phi0, params, trial_iters=3)
+    chosen = ctx.autotune(vols, phi0, params, trial_iters=3)
     t_tune = time.perf_counter() - t_tune
 
     for _ in range(W):
@@ -293,6 +304,7 @@ def run_tiles(args, w) -> int:
         "per_tile_loop_value": rate(t_loop),
         "gain_over_loop": round(t_loop / (elapsed / K), 3),
         "autotune_s": round(t_tune, 2),
+        "autotune_targets": list(chosen),
         "batch_equals_loop_bitwise": bool(same),
         "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
         "copy_gbs": round(copy_gbs, 1),
@@ -349,10 +361,22 @@ def run_serve(args, w) -> int:
     def vi(r):
         return float(np.prod(r[1])) * r[4]
 
-    def serve(stream, arrivals, keep=()):
+    def parse_sched(spec):
+        """'all' | 'arrival:<Mvoxels>' | 'shortest:<Mvoxels>'"""
+        if spec == "all":
+            return 0, rsf.RSF_ORDER_ARRIVAL
+        kind, mvox = spec.split(":")
+        order = {"arrival": rsf.RSF_ORDER_ARRIVAL, "shortest": rsf.RSF_ORDER_SHORTEST}[kind]
+        return int(float(mvox) * 1e6), order
+
+    scheds = args.sched.split(",")
+
+    def serve(stream, arrivals, keep=(), sched="all"):
         """Submit stream[i] at arrivals[i] (monotonic seconds); returns
         per-request results and the outputs of the requests in `keep`."""
-        srv = rsf.Server(budget_bytes=budget, chunk_iters=args.chunk_iters)
+        bv, order = parse_sched(sched)
+        srv = rsf.Server(budget_bytes=budget, chunk_iters=args.chunk_iters, batch_voxels=bv,
+                         order=order)
         tickets = [None] * len(stream)
         results = [None] * len(stream)
         kept = {}
@@ -398,12 +422,22 @@ def run_serve(args, w) -> int:
     gaps = rng.exponential(1.0 / lam, size=len(reqs))
     keep = set(int(k) for k in rng.choice(len(reqs), size=min(args.check, len(reqs)),
                                              replace=False))
-    t0 = time.monotonic() + 0.05
-    arrivals = list(t0 + np.cumsum(gaps) - gaps[0])
-    res, kept, st = serve(reqs, arrivals, keep)
+    sweep = []
+    for k, sched in enumerate(scheds):
+        print(f"[serve] stream with schedule {sched}", file=sys.stderr, flush=True)
+        t0 = time.monotonic() + 0.05
+        arr = list(t0 + np.cumsum(gaps) - gaps[0])
+        res_k, kept_k, st_k = serve(reqs, arr, keep if k == 0 else (), sched)
+        lat_k = np.array([r["t_done"] - a for r, a in zip(res_k, arr)])
+        span_k = max(r["t_done"] for r in res_k) - arr[0]
+        sweep.append({"schedule": sched,
+                      "p50_ms": round(float(np.percentile(lat_k, 50)) * 1e3, 2),
+                      "p99_ms": round(float(np.percentile(lat_k, 99)) * 1e3, 2),
+                      "gvoxel_iter_s": round(sum(vi(r) for r in reqs) / span_k / 1e9, 3),
+                      "peak_resident": st_k["peak_resident"]})
+        if k == 0:
+            res, kept, st, arrivals, lat, span = res_k, kept_k, st_k, arr, lat_k, span_k
     ok = all(r["status"] == 0 for r in res)
-    lat = np.array([r["t_done"] - a for r, a in zip(res, arrivals)])
-    span = max(r["t_done"] for r in res) - arrivals[0]
     gvi_stream = sum(vi(r) for r in reqs) / span / 1e9
 
     # (3) FIFO one at a time over the saturation sample
@@ -458,6 +492,8 @@ def run_serve(args, w) -> int:
                                "gvoxel_iter_s": round(sum(vi(r) for r in reqs[:sample]) / t_fifo
                                                       / 1e9, 3)},
         "gain_over_fifo": round(rate_sat / rate_fifo, 3),
+        "schedule": scheds[0],
+        "schedule_sweep": sweep,
         "stream_peak_resident": st["peak_resident"],
         "stream_peak_gb": round(st["peak_bytes"] / 2**30, 2),
         "alone_vs_mix_bitwise": f"{same}/{len(kept)}",
@@ -490,6 +526,9 @@ def main() -> int:
                     help="served workload: requests timed for the saturated and FIFO rates")
     ap.add_argument("--chunk-iters", type=int, default=4, help="served workload: server chunk")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM budget")
+    ap.add_argument("--sched", default="all",
+                    help="served workload: schedule(s), comma-separated, the first reported: "
+                         "all | arrival:<Mvoxels> | shortest:<Mvoxels>")
     ap.add_argument("--check", type=int, default=20,
                     help="served workload: requests re-run alone and compared")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -518,12 +557,13 @@ def main() -> int:
         return run_tiles(args, inputs.TILES_64)
     if args.workload == inputs.SERVE_2000.name:
         return run_serve(args, inputs.SERVE_2000)
-    w, image_t, storage_t = workloads()[args.workload]
+    w, image_t, storage_t, force_t = workloads()[args.workload]
     if args.iters > 0:
         import dataclasses
         w = dataclasses.replace(w, iters=args.iters)
     K, W = max(1, args.steps), max(0, args.warmup)
-    pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2)
+    paper = force_t == "paper"
+    pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2, paper)
 
     t_gen = time.perf_counter()
     if image_t == "u16":
@@ -534,7 +574,8 @@ def main() -> int:
     vol = torch.from_numpy(I_host).cuda()
     phi0 = torch.from_numpy(phi0_host).cuda()
     t_gen = time.perf_counter() - t_gen
-    params = rsf.make_params(**w.params(), storage=storage_t)
+    params = rsf.make_params(**w.params(), storage=storage_t,
+                             force=rsf.RSF_FORCE_PAPER if paper else rsf.RSF_FORCE_RSF)
     phis = [torch.empty_like(phi0) for _ in range(K)]
     ctx = rsf.Context(0)
     scratch = torch.empty_like(phi0)
@@ -580,6 +621,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "shape_zyx": list(w.shape), "sigma": w.sigma,
                    "image": image_t, "storage": storage_t,
+                   "force": "sec4.2_sigma2_0" if paper else "rsf_ei",
                    "iters": w.iters, "n_tubes": w.n_tubes, "lambda1": w.lambda1,
                    "lambda2": w.lambda2, "nu": w.nu, "mu": w.mu, "dt": w.dt, "eps": w.eps,
                    "regulariser": "double_well", "parallelism": "single_gpu"},
@@ -597,7 +639,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         img = I_host.astype("float64") / 65535.0 if image_t == "u16" else I_host
-        out["cpu_baseline"] = cpu_baseline(w, img, phi0_host, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, img, phi0_host, args.cpu_seconds,
+                                           force=1 if paper else 0)
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 

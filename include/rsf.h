@@ -79,6 +79,21 @@ typedef enum {
     RSF_REG_SINGLE_WELL = 1
 } rsf_regulariser;
 
+/* Data force.
+ *   RSF_FORCE_RSF (default): lambda1 e1 - lambda2 e2 with the fitting
+ *       energies e_i = I^2 (K*1) - 2 I (K*f_i) + K*(f_i^2) of the RSF model
+ *       the paper builds on, the same sigma for the fits and the force;
+ *       two Gaussian stages per iteration.
+ *   RSF_FORCE_PAPER: the expansion of Sec. 4.2 (voxel level parallelism),
+ *       F+- = K2*I^2 - 2 r+- K2*I + r+-^2 with K2 the Gaussian of scale
+ *       sigma2, and lambda1 F+ - lambda2 F-.  With sigma2 = 0 (every 3D run
+ *       of the paper, Sec. 5) K2 is the identity and F+- = (I - r+-)^2: one
+ *       Gaussian stage per iteration.  r+ = f1, r- = f2. */
+typedef enum {
+    RSF_FORCE_RSF = 0,
+    RSF_FORCE_PAPER = 1
+} rsf_force;
+
 /* Parameters of one evolution (Sec. 2-3 notation: alpha = nu, beta carried
  * by lambda1 = lambda2, mu weighs the regulariser). */
 typedef struct {
@@ -92,6 +107,9 @@ typedef struct {
     float eta;        /* floor inside |grad phi| of the normal; <= 0 -> 1e-10 */
     int regulariser;  /* rsf_regulariser                                      */
     int storage;      /* rsf_dtype of the intermediate fields (F32/F16/BF16)  */
+    int force;        /* rsf_force                                            */
+    float sigma2;     /* scale of the force kernel for RSF_FORCE_PAPER; only
+                         0 (the value of the paper's 3D runs) is built        */
 } rsf_params;
 
 /* Results of the last evolution on a context. */
@@ -175,7 +193,16 @@ rsf_status rsf_evolve_batch(rsf_context *ctx, const rsf_tile *tiles, int n_tiles
  * last bits.  Synchronises `stream`; allocates a scratch copy of phi for the
  * duration of the call; invalidates the statistics of the last evolution. */
 rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
-                        const rsf_params *params, int trial_iters, void *stream);
+                        const rsf_params *params, int trial_iters, int64_t *chosen,
+                        void *stream);
+
+/* Workgroup targets of a whole batch (xy waves, z-pass workgroups, update-
+ * pass workgroups) from which untuned splits are derived, each tile taking
+ * its share of the batch's voxels; 0 keeps the built-in value (16384, 2048,
+ * 1024).  rsf_autotune starts its search from these and reports the targets
+ * it chose in chosen[0..2] (may be NULL).  Results do not depend on them. */
+rsf_status rsf_set_split_targets(rsf_context *ctx, int64_t xy_waves, int64_t z_blocks,
+                                 int64_t u_blocks);
 
 /* Forget all autotuned splits of the context. */
 void rsf_autotune_reset(rsf_context *ctx);
@@ -254,12 +281,25 @@ rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out);
  * ---------------------------------------------------------------------- */
 typedef struct rsf_server rsf_server;
 
+/* Which resident tiles run in a chunk when batch_voxels caps the batch:
+ * RSF_ORDER_ARRIVAL takes them oldest first, RSF_ORDER_SHORTEST by least
+ * remaining work (iterations left times voxels), ties by arrival.  The rest
+ * wait, resident, for a later chunk. */
+typedef enum {
+    RSF_ORDER_ARRIVAL = 0,
+    RSF_ORDER_SHORTEST = 1
+} rsf_order;
+
 typedef struct {
     int device;            /* HIP device ordinal                               */
     size_t budget_bytes;   /* HBM for request workspaces (admission limit)     */
     size_t segment_bytes;  /* arena growth step; 0 = 8 GiB                     */
     int chunk_iters;       /* iterations per scheduling chunk; 0 = 4           */
     int max_resident;      /* most tiles resident at once; 0 = 256 (<= 4096)  */
+    int64_t batch_voxels;  /* run tiles (in `order`) until their voxels reach
+                              this per chunk; 0 = every resident tile runs    */
+    int order;             /* rsf_order                                        */
+    int64_t split_targets[3]; /* as rsf_set_split_targets; 0 = built-in       */
 } rsf_server_config;
 
 typedef struct {

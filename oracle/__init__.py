@@ -114,8 +114,14 @@ def conv3d(u, sigma: float, real: str = "f64") -> np.ndarray:
     return out
 
 
-def params_array(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10) -> np.ndarray:
-    return np.array([sigma, lambda1, lambda2, nu, mu, dt, eps, eta], dtype=np.float64)
+FORCE_RSF = 0     # RSF fitting energies e_i with the same sigma
+FORCE_PAPER = 1   # the Sec. 4.2 expansion with its own sigma2 (0 = identity)
+
+
+def params_array(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10, force=FORCE_RSF,
+                 sigma2=0.0) -> np.ndarray:
+    return np.array([sigma, lambda1, lambda2, nu, mu, dt, eps, eta, force, sigma2],
+                    dtype=np.float64)
 
 
 def step(I, phi, params, reg: int = DOUBLE_WELL, real: str = "f64"):

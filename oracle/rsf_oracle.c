@@ -32,6 +32,12 @@
  *     again with all four convolutions done literally, and
  *     F_d = lambda1 e1 - lambda2 e2 (the force of Sec. 3, F = -[F+ - F-],
  *     with beta carried by lambda1 = lambda2).
+ *   - Or (force = 1) the expansion the paper gives for its directional force
+ *     in Sec. 4.2 (voxel level parallelism):
+ *       F+-(x) = [K2*I^2](x) - 2 r+-(x) [K2*I](x) + r+-(x)^2,
+ *     with K2 the Gaussian of scale sigma2 built like K (sigma2 = 0, the
+ *     value of every 3D run in Sec. 5, makes K2 the identity), r+ = f1,
+ *     r- = f2, and F_d = lambda1 F+ - lambda2 F-.
  *   - kappa = div(grad phi / |grad phi|_eta), |g|_eta = sqrt(|g|^2 + eta):
  *     the smoothing term S of Sec. 2.2 read as mean curvature.
  *   - R(phi) = lap(phi) + div(D(|grad phi|) grad phi), the distance
@@ -211,12 +217,15 @@ static REAL reg_rate(REAL s, REAL s_eta, int reg)
 
 typedef struct {
     double sigma, lambda1, lambda2, nu, mu, dt, eps, eta;
+    int force;          /* 0: RSF e_i; 1: Sec. 4.2 expansion with sigma2 */
+    double sigma2;
 } oracle_params;
 
 static void read_params(const double *p, oracle_params *q)
 {
     q->sigma = p[0]; q->lambda1 = p[1]; q->lambda2 = p[2]; q->nu = p[3];
     q->mu = p[4]; q->dt = p[5]; q->eps = p[6]; q->eta = p[7];
+    q->force = (int)p[8]; q->sigma2 = p[9];
 }
 
 /* Scratch for one iteration. */
@@ -247,6 +256,7 @@ static void work_free(work_t *s)
  * (double, may be NULL) receive this step's intermediate values.
  * Returns sum |phi_next - phi| in double. */
 static double rsf_step(const REAL *I, const REAL *phi, REAL *phi_next, const REAL *K1,
+                       const REAL *K2I, const REAL *K2I2,
                        i64 nx, i64 ny, i64 nz, const oracle_params *p, int reg,
                        const REAL *w, int R, work_t *s, double **probe)
 {
@@ -274,6 +284,14 @@ static double rsf_step(const REAL *I, const REAL *phi, REAL *phi_next, const REA
         s->f2[i] = s->A2[i] / s->B2[i];
     }
 
+    if (p->force == 1) {
+        /* Directional forces of Sec. 4.2: F+- = K2*I^2 - 2 r+- K2*I + r+-^2. */
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < N; ++i) {
+            s->e1[i] = K2I2[i] - (REAL)2 * s->f1[i] * K2I[i] + s->f1[i] * s->f1[i];
+            s->e2[i] = K2I2[i] - (REAL)2 * s->f2[i] * K2I[i] + s->f2[i] * s->f2[i];
+        }
+    } else {
     /* Fitting energies e_i = I^2 K1 - 2 I K*f_i + K*f_i^2: four literal
      * convolutions. */
     conv3d(s->f1, s->c1, s->tmp, nx, ny, nz, w, R);
@@ -290,6 +308,7 @@ static double rsf_step(const REAL *I, const REAL *phi, REAL *phi_next, const REA
 #pragma omp parallel for schedule(static)
     for (i64 i = 0; i < N; ++i)
         s->e2[i] = I[i] * I[i] * K1[i] - (REAL)2 * I[i] * s->c1[i] + s->c2[i];
+    }
 
     /* Curvature, regulariser, Dirac-weighted update (Sec. 2, Sec. 3). */
     double *slice_sum = (double *)calloc((size_t)nz, sizeof(double));
@@ -350,9 +369,34 @@ static void ones_conv(REAL *K1, REAL *tmp, i64 nx, i64 ny, i64 nz, const REAL *w
     free(one);
 }
 
-/* params = {sigma, lambda1, lambda2, nu, mu, dt, eps, eta}; reg 0 = single
- * well, 1 = double well.  probe[10] = {H, f1, f2, e1, e2, kappa, lap, R, E, delta},
- * any entry may be NULL.  One iteration from phi into phi_next. */
+/* K2*I and K2*I^2 of the Sec. 4.2 force, constant over the iterations:
+ * literal convolutions with the sigma2 Gaussian, or I and I^2 themselves for
+ * sigma2 = 0.  Returns 0 on success. */
+static int force_fields(const REAL *I, REAL *K2I, REAL *K2I2, REAL *tmp, i64 nx, i64 ny, i64 nz,
+                        double sigma2)
+{
+    const i64 N = nx * ny * nz;
+    REAL *sq = alloc_field(N);
+    if (!sq) return -2;
+    for (i64 i = 0; i < N; ++i) sq[i] = I[i] * I[i];
+    if (sigma2 == 0.0) {
+        for (i64 i = 0; i < N; ++i) { K2I[i] = I[i]; K2I2[i] = sq[i]; }
+    } else {
+        int R2;
+        REAL *w2 = make_weights(sigma2, &R2);
+        if (!w2) { free(sq); return -1; }
+        conv3d(I, K2I, tmp, nx, ny, nz, w2, R2);
+        conv3d(sq, K2I2, tmp, nx, ny, nz, w2, R2);
+        free(w2);
+    }
+    free(sq);
+    return 0;
+}
+
+/* params = {sigma, lambda1, lambda2, nu, mu, dt, eps, eta, force, sigma2};
+ * reg 0 = single well, 1 = double well.  probe[10] = {H, f1, f2, e1, e2,
+ * kappa, lap, R, E, delta} (e1, e2 hold F+, F- for force 1), any entry may
+ * be NULL.  One iteration from phi into phi_next. */
 int oracle_step(const double *I_in, const double *phi_in, double *phi_out,
                 i64 nx, i64 ny, i64 nz, const double *params, int reg,
                 double **probe, double *sum_abs)
@@ -372,10 +416,19 @@ int oracle_step(const double *I_in, const double *phi_in, double *phi_out,
     }
     for (i64 i = 0; i < N; ++i) { I[i] = (REAL)I_in[i]; phi[i] = (REAL)phi_in[i]; }
     ones_conv(K1, s.tmp, nx, ny, nz, w, R);
-    double t = rsf_step(I, phi, nxt, K1, nx, ny, nz, &p, reg, w, R, &s, probe);
+    REAL *K2I = NULL, *K2I2 = NULL;
+    if (p.force == 1) {
+        K2I = alloc_field(N);
+        K2I2 = alloc_field(N);
+        if (!K2I || !K2I2 || force_fields(I, K2I, K2I2, s.tmp, nx, ny, nz, p.sigma2) != 0) {
+            work_free(&s); free(I); free(phi); free(nxt); free(K1); free(w); free(K2I); free(K2I2);
+            return -2;
+        }
+    }
+    double t = rsf_step(I, phi, nxt, K1, K2I, K2I2, nx, ny, nz, &p, reg, w, R, &s, probe);
     for (i64 i = 0; i < N; ++i) phi_out[i] = (double)nxt[i];
     if (sum_abs) *sum_abs = t;
-    work_free(&s); free(I); free(phi); free(nxt); free(K1); free(w);
+    work_free(&s); free(I); free(phi); free(nxt); free(K1); free(w); free(K2I); free(K2I2);
     return 0;
 }
 
@@ -399,12 +452,21 @@ int oracle_evolve(const double *I_in, double *phi_io, i64 nx, i64 ny, i64 nz,
     }
     for (i64 i = 0; i < N; ++i) { I[i] = (REAL)I_in[i]; a[i] = (REAL)phi_io[i]; }
     ones_conv(K1, s.tmp, nx, ny, nz, w, R);
+    REAL *K2I = NULL, *K2I2 = NULL;
+    if (p.force == 1) {
+        K2I = alloc_field(N);
+        K2I2 = alloc_field(N);
+        if (!K2I || !K2I2 || force_fields(I, K2I, K2I2, s.tmp, nx, ny, nz, p.sigma2) != 0) {
+            work_free(&s); free(I); free(a); free(b); free(K1); free(w); free(K2I); free(K2I2);
+            return -2;
+        }
+    }
     for (int n = 0; n < iters; ++n) {
-        double t = rsf_step(I, a, b, K1, nx, ny, nz, &p, reg, w, R, &s, NULL);
+        double t = rsf_step(I, a, b, K1, K2I, K2I2, nx, ny, nz, &p, reg, w, R, &s, NULL);
         if (s_hist) s_hist[n] = t;
         REAL *q = a; a = b; b = q;
     }
     for (i64 i = 0; i < N; ++i) phi_io[i] = (double)a[i];
-    work_free(&s); free(I); free(a); free(b); free(K1); free(w);
+    work_free(&s); free(I); free(a); free(b); free(K1); free(w); free(K2I); free(K2I2);
     return 0;
 }

@@ -60,6 +60,8 @@ struct rsf_context {
     std::vector<Rec> recs;
     // autotuned splits by tile shape and radius
     std::map<std::vector<int64_t>, Split> tuned;
+    // workgroup targets of a batch when no tuned split applies
+    rsf::Targets targets = rsf::kDefaultTargets;
 };
 
 namespace {
@@ -263,7 +265,7 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
     std::vector<Split> splits;
     for (int t = 0; t < n; ++t) {
         const Grid3 g = grid_of(tiles[t]);
-        Split s = rsf::default_split(g, sh[t]);
+        Split s = rsf::default_split(g, sh[t], ctx ? ctx->targets : rsf::kDefaultTargets);
         if (ctx) {
             auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
             if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) s = it->second;
@@ -356,19 +358,24 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
                                                P.c, probe, s);
             }),
             "z(H)");
+    const bool paper = P.c.force == RSF_FORCE_PAPER;
     HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_FITS, P.image, P.storage, P.xy, P.blocks_xy,
-                                      P.taps, P.c, probe, s);
+                return rsf::launch_xy(P.R, paper ? rsf::XY_PAPER : rsf::XY_FITS, P.image,
+                                      P.storage, P.xy, P.blocks_xy, P.taps, P.c, probe, s);
             }),
             "xy(fits)");
-    HIP_TRY(timed(ctx, RSF_PASS_XY_FORCE, s, [&] {
-                return rsf::launch_xy(P.R, rsf::XY_TWO, P.image, P.storage, P.xy, P.blocks_xy,
-                                      P.taps, P.c, probe, s);
-            }),
-            "xy(g)");
+    // the Sec. 4.2 force with sigma2 = 0 needs no second Gaussian stage
+    if (!paper)
+        HIP_TRY(timed(ctx, RSF_PASS_XY_FORCE, s, [&] {
+                    return rsf::launch_xy(P.R, rsf::XY_TWO, P.image, P.storage, P.xy,
+                                          P.blocks_xy, P.taps, P.c, probe, s);
+                }),
+                "xy(g)");
     HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s, [&] {
-                return rsf::launch_z_update(P.R, P.image, P.storage, u, P.blocks_u, P.taps, P.c,
-                                            probe, s);
+                return paper ? rsf::launch_z_update_paper(P.image, P.storage, u, P.blocks_u, P.c,
+                                                          probe, s)
+                             : rsf::launch_z_update(P.R, P.image, P.storage, u, P.blocks_u,
+                                                    P.taps, P.c, probe, s);
             }),
             "z(update)");
     HIP_TRY(timed(ctx, RSF_PASS_REDUCE, s, [&] { return rsf::launch_reduce(P.tile, P.c, s); }),
@@ -459,6 +466,7 @@ rsf_params default_params(float sigma, float l1, float l2, float nu, float mu, f
     rsf_params p{};
     p.sigma = sigma; p.lambda1 = l1; p.lambda2 = l2; p.nu = nu; p.mu = mu; p.dt = dt;
     p.eps = eps; p.eta = 1e-10f; p.regulariser = RSF_REG_DOUBLE_WELL; p.storage = RSF_F32;
+    p.force = RSF_FORCE_RSF; p.sigma2 = 0.f;
     return p;
 }
 
@@ -654,8 +662,22 @@ rsf_status rsf_get_tile_stats(rsf_context *ctx, int tile, rsf_stats *out, double
     }
 }
 
+rsf_status rsf_set_split_targets(rsf_context *ctx, int64_t xy_waves, int64_t z_blocks,
+                                 int64_t u_blocks)
+{
+    if (!ctx) return RSF_ERR_INVALID_ARG;
+    if (xy_waves < 0 || z_blocks < 0 || u_blocks < 0 || xy_waves > (1 << 24) ||
+        z_blocks > (1 << 24) || u_blocks > (1 << 24))
+        return fail(ctx, RSF_ERR_INVALID_ARG, "targets must be in 0..2^24");
+    ctx->targets.xy = xy_waves ? xy_waves : rsf::kDefaultTargets.xy;
+    ctx->targets.z = z_blocks ? z_blocks : rsf::kDefaultTargets.z;
+    ctx->targets.u = u_blocks ? u_blocks : rsf::kDefaultTargets.u;
+    return RSF_OK;
+}
+
 rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
-                        const rsf_params *params, int trial_iters, void *stream)
+                        const rsf_params *params, int trial_iters, int64_t *chosen,
+                        void *stream)
 {
     float *scratch = nullptr;
     try {
@@ -691,11 +713,12 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 return hip_fail(ctx, e, "autotune copy");
             }
         }
-        // coordinate search over the three per-pass workgroup targets
-        const int64_t cand_xy[] = {4096, 8192, 16384, 32768};
-        const int64_t cand_z[] = {1024, 2048, 4096};
-        const int64_t cand_u[] = {512, 1024, 2048};
-        int64_t best[3] = {16384, 2048, 1024};
+        // coordinate search over the three per-pass workgroup targets,
+        // starting from the context's
+        const int64_t cand_xy[] = {2048, 4096, 8192, 16384, 32768};
+        const int64_t cand_z[] = {256, 512, 1024, 2048, 4096};
+        const int64_t cand_u[] = {128, 256, 512, 1024, 2048};
+        int64_t best[3] = {ctx->targets.xy, ctx->targets.z, ctx->targets.u};
         // targets are for the whole batch; each tile gets its voxel share
         const std::vector<double> sh = shares_of(tiles, n_tiles);
         auto apply = [&](const int64_t tg[3]) {
@@ -711,7 +734,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
         float best_ms = -1.f;
         for (int axis = 0; axis < 3; ++axis) {
             const int64_t *cands = axis == 0 ? cand_xy : (axis == 1 ? cand_z : cand_u);
-            const int nc = axis == 0 ? 4 : 3;
+            const int nc = 5;
             int64_t keep = best[axis];
             for (int c = 0; c < nc; ++c) {
                 int64_t tg[3] = {best[0], best[1], best[2]};
@@ -741,8 +764,14 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
             if (st != RSF_OK) break;
             best[axis] = keep;
         }
-        if (st == RSF_OK) apply(best);
-        else {
+        if (st == RSF_OK) {
+            apply(best);
+            if (chosen) {
+                chosen[0] = best[0];
+                chosen[1] = best[1];
+                chosen[2] = best[2];
+            }
+        } else {
             for (int t = 0; t < n_tiles; ++t)
                 ctx->tuned.erase({tiles[t].nx, tiles[t].ny, tiles[t].nz, R});
         }

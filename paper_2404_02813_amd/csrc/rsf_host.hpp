@@ -48,6 +48,7 @@ inline Coeffs make_coeffs(const rsf_params &p, double tol)
     c.eps2 = p.eps * p.eps;
     c.eta = p.eta > 0.f ? p.eta : 1e-10f;
     c.reg = p.regulariser == RSF_REG_SINGLE_WELL ? 1 : 0;
+    c.force = p.force;
     c.tol = tol;
     return c;
 }
@@ -78,6 +79,10 @@ inline const char *params_error(const rsf_params &p)
         return "unknown regulariser";
     if (p.storage != RSF_F32 && p.storage != RSF_F16 && p.storage != RSF_BF16)
         return "storage must be RSF_F32, RSF_F16 or RSF_BF16";
+    if (p.force != RSF_FORCE_RSF && p.force != RSF_FORCE_PAPER) return "unknown force";
+    if (!fin(p.sigma2) || p.sigma2 < 0.f) return "sigma2 must be finite and >= 0";
+    if (p.force == RSF_FORCE_PAPER && p.sigma2 != 0.f)
+        return "RSF_FORCE_PAPER is built for sigma2 = 0 only";
     return nullptr;
 }
 

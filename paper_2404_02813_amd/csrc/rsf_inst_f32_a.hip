@@ -9,4 +9,5 @@ RSF_INSTANTIATE(3, float, float)
 RSF_INSTANTIATE(4, float, float)
 RSF_INSTANTIATE(5, float, float)
 RSF_INSTANTIATE(6, float, float)
+RSF_INSTANTIATE_PAPER(float, float)
 }  // namespace rsf

@@ -12,4 +12,5 @@ RSF_INSTANTIATE(9, float, __bf16)
 RSF_INSTANTIATE(10, float, __bf16)
 RSF_INSTANTIATE(11, float, __bf16)
 RSF_INSTANTIATE(12, float, __bf16)
+RSF_INSTANTIATE_PAPER(float, __bf16)
 }  // namespace rsf

@@ -12,4 +12,5 @@ RSF_INSTANTIATE(9, float, _Float16)
 RSF_INSTANTIATE(10, float, _Float16)
 RSF_INSTANTIATE(11, float, _Float16)
 RSF_INSTANTIATE(12, float, _Float16)
+RSF_INSTANTIATE_PAPER(float, _Float16)
 }  // namespace rsf

@@ -12,4 +12,5 @@ RSF_INSTANTIATE(9, uint16_t, __bf16)
 RSF_INSTANTIATE(10, uint16_t, __bf16)
 RSF_INSTANTIATE(11, uint16_t, __bf16)
 RSF_INSTANTIATE(12, uint16_t, __bf16)
+RSF_INSTANTIATE_PAPER(uint16_t, __bf16)
 }  // namespace rsf

@@ -66,6 +66,7 @@ struct Coeffs {
     float eps, eps_over_pi, eps2;   // delta = eps_over_pi / (eps2 + phi^2)
     float eta;
     int reg;                        // 0 double well, 1 single well
+    int force;                      // 0 RSF e_i (sigma), 1 Sec. 4.2 form with sigma2 = 0
     double tol;                     // stop a tile once sum|dphi| / voxels < tol (0: never)
 };
 
@@ -103,11 +104,19 @@ __host__ __device__ inline int64_t u_blocks(const Grid3 &g, const Split &s)
     return (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy) * s.u;
 }
 
+// Workgroups a whole batch aims at per pass: xy waves, z-pass workgroups,
+// update-pass workgroups.
+struct Targets {
+    int64_t xy, z, u;
+};
+constexpr Targets kDefaultTargets{16384, 2048, 1024};
+
 // Split of one volume aiming at the given workgroup counts per pass (the
 // autotuner varies them); every chunk is non-empty and at least 8 long.
 Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_target);
-// Default split of a tile holding fraction `share` of its batch's voxels.
-Split default_split(const Grid3 &g, double share = 1.0);
+// Split of a tile holding fraction `share` of its batch's voxels: that share
+// of the batch's targets.
+Split default_split(const Grid3 &g, double share = 1.0, const Targets &tg = kDefaultTargets);
 // Update-pass workgroups of a tile under any valid split are at most this.
 __host__ __device__ inline int64_t u_blocks_max(const Grid3 &g)
 {
@@ -119,8 +128,9 @@ bool types_supported(int R, int image_dtype, int storage_dtype);
 
 // xy pass modes: XY_ONE reads the image and writes one field (P), for K*I;
 // XY_FITS reads the pair P and K*I and writes the pair Q; XY_TWO reads the
-// pair Q and writes the pair P.
-enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2 };
+// pair Q and writes the pair P; XY_PAPER reads the pair P, K*I and the image
+// and writes the Sec. 4.2 force (sigma2 = 0) to Q as float.
+enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2, XY_PAPER = 3 };
 
 // One workgroup per tile: K*1 edge tables, flags cleared.
 hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s);
@@ -138,6 +148,9 @@ hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const B
 hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const Batch &b,
                            int64_t blocks, const Taps &t, const Coeffs &c, bool probe,
                            hipStream_t s);
+// The update reading the Sec. 4.2 force (sigma2 = 0) that XY_PAPER wrote.
+hipError_t launch_z_update_paper(int image_dtype, int storage_dtype, const Batch &b,
+                                 int64_t blocks, const Coeffs &c, bool probe, hipStream_t s);
 // One workgroup per tile: fixed-order FP64 sum of the partials; counts the
 // iteration and stops the tile at its tolerance or its last iteration.
 hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s);
@@ -156,5 +169,8 @@ hipError_t launch_z_heaviside_r(const Batch &b, int64_t blocks, const Taps &t, c
 template <int R, class IT, class ST>
 hipError_t launch_z_update_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
                              bool probe, hipStream_t s);
+template <class IT, class ST>
+hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs &c, bool probe,
+                                   hipStream_t s);
 
 }  // namespace rsf

@@ -195,4 +195,16 @@ hipError_t launch_z_update(int R, int it, int st, const Batch &b, int64_t blocks
 #undef C
 }
 
+hipError_t launch_z_update_paper(int it, int st, const Batch &b, int64_t blocks, const Coeffs &c,
+                                 bool probe, hipStream_t s)
+{
+    if (it == F32 && st == F32) return launch_z_update_paper_r<float, float>(b, blocks, c, probe, s);
+    if (it == U16 && st == F16) return launch_z_update_paper_r<uint16_t, _Float16>(b, blocks, c, probe, s);
+    if (it == U16 && st == BF16) return launch_z_update_paper_r<uint16_t, __bf16>(b, blocks, c, probe, s);
+    if (it == U16 && st == F32) return launch_z_update_paper_r<uint16_t, float>(b, blocks, c, probe, s);
+    if (it == F32 && st == F16) return launch_z_update_paper_r<float, _Float16>(b, blocks, c, probe, s);
+    if (it == F32 && st == BF16) return launch_z_update_paper_r<float, __bf16>(b, blocks, c, probe, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace rsf

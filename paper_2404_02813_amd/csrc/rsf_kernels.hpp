@@ -19,10 +19,12 @@ namespace {
 
 // XY_ONE reads the image (IN) and writes one field P (ST), for K*I; XY_FITS
 // reads the pair P and K*I and writes the pair Q; XY_TWO reads the pair Q and
-// writes the pair P.
-template <int R, int MODE, class IN, class ST>
+// writes the pair P; XY_PAPER reads the pair P, K*I and the image (IMG) and
+// writes the force of Sec. 4.2 with sigma2 = 0 to Q as float.
+template <int R, int MODE, class IN, class ST, class IMG = float>
 __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 {
+    constexpr bool FITS = MODE == XY_FITS || MODE == XY_PAPER;
     constexpr int NF = MODE == XY_ONE ? 1 : 2;
     constexpr int W = 2 * R + 1;
     constexpr int RW = 64 + 2 * R;
@@ -34,8 +36,8 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     if (d.flags[0]) return;
     const Grid3 g = d.g;
     const int nyc = d.sp.xy;
-    const void *__restrict__ in_ = MODE == XY_ONE ? d.I : (MODE == XY_FITS ? d.P : d.Q);
-    void *__restrict__ out_ = MODE == XY_FITS ? d.Q : d.P;
+    const void *__restrict__ in_ = MODE == XY_ONE ? d.I : (FITS ? d.P : d.Q);
+    void *__restrict__ out_ = FITS ? d.Q : d.P;
     const int nbx = (g.nx + 63) / 64;
     const int tile = wh.lb;
     const int xs = tile % nbx, rest = tile / nbx;
@@ -110,14 +112,17 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     }
     float cxz = 0.f;
     const int xc = min(x, g.nx - 1);
-    const ST *ki_slice = MODE == XY_FITS ? static_cast<const ST *>(d.KI) + zb : nullptr;
+    const ST *ki_slice = FITS ? static_cast<const ST *>(d.KI) + zb : nullptr;
+    const IMG *im_slice = MODE == XY_PAPER ? static_cast<const IMG *>(d.I) + zb : nullptr;
     const float *cyp = d.cy;
-    if (MODE == XY_FITS) cxz = d.cx[xc] * d.cz[z];
-    float ki_next = MODE == XY_FITS ? to_f(ki_slice[y0 * g.nx + xc]) : 0.f;
-    float cy_next = MODE == XY_FITS ? cyp[y0] : 0.f;
-    float *probe_f1 = d.probe_f1, *probe_f2 = d.probe_f2;
+    if (FITS) cxz = d.cx[xc] * d.cz[z];
+    float ki_next = FITS ? to_f(ki_slice[y0 * g.nx + xc]) : 0.f;
+    float im_next = MODE == XY_PAPER ? to_f(im_slice[y0 * g.nx + xc]) : 0.f;
+    float cy_next = FITS ? cyp[y0] : 0.f;
+    float *probe_f1 = d.probe_f1, *probe_f2 = d.probe_f2, *probe_fd = d.probe_Fd;
     ST *o1_s = static_cast<ST *>(out_) + zb;
     Pair<ST> *o2_s = static_cast<Pair<ST> *>(out_) + zb;
+    float *of_s = static_cast<float *>(out_) + zb;
     for (int yb = y0; yb < y1; yb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -125,13 +130,15 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
             if (y < y1) {
                 const Raw cur = nxt;
                 nxt = fetch(y + R + 1);
-                float ki = 0.f, cyv = 0.f;
-                if (MODE == XY_FITS) {
+                float ki = 0.f, cyv = 0.f, im = 0.f;
+                if (FITS) {
                     ki = ki_next;
                     cyv = cy_next;
+                    im = im_next;
                     if (y + 1 < y1) {
                         ki_next = to_f(ki_slice[(y + 1) * g.nx + xc]);
                         cy_next = cyp[y + 1];
+                        if (MODE == XY_PAPER) im_next = to_f(im_slice[(y + 1) * g.nx + xc]);
                     }
                 }
                 // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
@@ -146,15 +153,24 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                 }
                 if (x < g.nx) {
                     const int v = y * g.nx + x;      // offset within the slice
-                    if (MODE == XY_FITS) {
-                        // region fits (Sec. 3 local_intensity), force-convolution inputs
+                    if (FITS) {
+                        // region fits (Sec. 3 local_intensity)
                         const float K1 = cxz * cyv;
                         const float A2 = ki - acc_a;
                         const float B2 = K1 - acc_b;
                         const float f1 = acc_a * rcp(acc_b);
                         const float f2 = A2 * rcp(B2);
-                        o2_s[v] = Pair<ST>{from_f<ST>(c.l1 * f1 - c.l2 * f2),
-                                           from_f<ST>(c.l1 * f1 * f1 - c.l2 * f2 * f2)};
+                        if (MODE == XY_PAPER) {
+                            // F+- = (I - r+-)^2 (Sec. 4.2 expansion, sigma2 = 0)
+                            const float d1 = im - f1, d2 = im - f2;
+                            const float Fd = c.l1 * d1 * d1 - c.l2 * d2 * d2;
+                            of_s[v] = Fd;
+                            if (probe_fd) probe_fd[zb + v] = Fd;
+                        } else {
+                            // force-convolution inputs g1, g2
+                            o2_s[v] = Pair<ST>{from_f<ST>(c.l1 * f1 - c.l2 * f2),
+                                               from_f<ST>(c.l1 * f1 * f1 - c.l2 * f2 * f2)};
+                        }
                         if (probe_f1) probe_f1[zb + v] = f1;
                         if (probe_f2) probe_f2[zb + v] = f2;
                     } else if (NF == 2) {
@@ -319,7 +335,11 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
 // Slot reuse is safe: phi(z+3) overwrites phi(z-3), last read in step z-2;
 // n, V of z+2 overwrite those of z-1, last read in step z-1; a barrier
 // separates each pair.
-template <int R, bool PROBE, class ST, class IT>
+//
+// PAPER: the force of Sec. 4.2 with sigma2 = 0 was formed by the xy pass and
+// is read pointwise (float F_d in Q); there is no stage-2 ring and no image
+// read, and R only sets the unroll.
+template <int R, bool PROBE, class ST, class IT, bool PAPER = false>
 __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t, Coeffs ua)
 {
     constexpr int TX = kUx, TY = kUy, NT = kUThreads;
@@ -441,39 +461,50 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
 
         constexpr int W = 2 * R + 1;
         float ra[W], rb[W];
+        if constexpr (!PAPER) {
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) {
-            const int z = z0 - R + j;
-            const float2 v = (z >= 0 && z < g.nz) ? pair_at(z) : make_float2(0.f, 0.f);
-            ra[j] = v.x;
-            rb[j] = v.y;
+            for (int j = 0; j < 2 * R; ++j) {
+                const int z = z0 - R + j;
+                const float2 v = (z >= 0 && z < g.nz) ? pair_at(z) : make_float2(0.f, 0.f);
+                ra[j] = v.x;
+                rb[j] = v.y;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         // one-step-ahead prefetch of the next phi slice, conv inputs and image
+        // (PAPER: the force field instead)
+        const float *fdp = static_cast<const float *>(d.Q);
         PhiRaw phi_nxt = fetch_phi(z0 + 3);
-        float2 t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : make_float2(0.f, 0.f);
-        float I_nxt = z0 < zt.z1 ? at(img, z0) : 0.f;
+        float2 t_nxt = make_float2(0.f, 0.f);
+        if constexpr (!PAPER) t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : make_float2(0.f, 0.f);
+        float I_nxt = z0 < zt.z1 ? (PAPER ? at(fdp, z0) : at(img, z0)) : 0.f;
         for (int zb = z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
                     store_phi(phi_nxt, z + 3);
-                    ra[(s + 2 * R) % W] = t_nxt.x;
-                    rb[(s + 2 * R) % W] = t_nxt.y;
-                    const float Iv = I_nxt;
+                    if constexpr (!PAPER) {
+                        ra[(s + 2 * R) % W] = t_nxt.x;
+                        rb[(s + 2 * R) % W] = t_nxt.y;
+                    }
+                    const float Iv = I_nxt;   // PAPER: F_d of slice z
                     phi_nxt = fetch_phi(z + 4);
-                    const int zn = z + R + 1;
-                    t_nxt = zn < g.nz ? pair_at(zn) : make_float2(0.f, 0.f);
-                    if (z + 1 < zt.z1) I_nxt = at(img, z + 1);
+                    if constexpr (!PAPER) {
+                        const int zn = z + R + 1;
+                        t_nxt = zn < g.nz ? pair_at(zn) : make_float2(0.f, 0.f);
+                    }
+                    if (z + 1 < zt.z1) I_nxt = PAPER ? at(fdp, z + 1) : at(img, z + 1);
                     __syncthreads();
                     float nzpp, vzpp;
                     q_phase(z + 2, nzpp, vzpp);
                     float KG1 = 0.f, KG2 = 0.f;
+                    if constexpr (!PAPER) {
 #pragma unroll
-                    for (int k = 0; k < W; ++k) {
-                        KG1 = fmaf(t.w[k], ra[(s + k) % W], KG1);
-                        KG2 = fmaf(t.w[k], rb[(s + k) % W], KG2);
+                        for (int k = 0; k < W; ++k) {
+                            KG1 = fmaf(t.w[k], ra[(s + k) % W], KG1);
+                            KG2 = fmaf(t.w[k], rb[(s + k) % W], KG2);
+                        }
                     }
                     if (zt.active) {
                         const int64_t zo = (int64_t)z * g.sxy;
@@ -490,8 +521,13 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                         const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
                                            0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
                                            0.5f * (vzp - vzm);
-                        const float K1 = cxy * czp[z];
-                        const float Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
+                        float Fd;
+                        if constexpr (PAPER) {
+                            Fd = Iv;
+                        } else {
+                            const float K1 = cxy * czp[z];
+                            Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
+                        }
                         const float Rt = lap + divV;
                         const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                         const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
@@ -547,6 +583,9 @@ hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, 
     case XY_FITS:
         hipLaunchKernelGGL((xy_kernel<R, XY_FITS, ST, ST>), grid, dim3(64), 0, s, b, t, c);
         break;
+    case XY_PAPER:
+        hipLaunchKernelGGL((xy_kernel<R, XY_PAPER, ST, ST, IT>), grid, dim3(64), 0, s, b, t, c);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -587,6 +626,26 @@ hipError_t launch_z_update_r(const Batch &b, int64_t blocks, const Taps &t, cons
                            c);
     return hipGetLastError();
 }
+
+// The update of the Sec. 4.2 force (sigma2 = 0): one instance per type pair.
+template <class IT, class ST>
+hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs &c, bool probe,
+                                   hipStream_t s)
+{
+    const dim3 grid((unsigned)blocks);
+    const Taps t{};
+    if (probe)
+        hipLaunchKernelGGL((z_update_kernel<1, true, ST, IT, true>), grid, dim3(kUThreads), 0, s,
+                           b, t, c);
+    else
+        hipLaunchKernelGGL((z_update_kernel<1, false, ST, IT, true>), grid, dim3(kUThreads), 0, s,
+                           b, t, c);
+    return hipGetLastError();
+}
+
+#define RSF_INSTANTIATE_PAPER(IT, ST)                                                      \
+    template hipError_t launch_z_update_paper_r<IT, ST>(const Batch &, int64_t, const Coeffs &, \
+                                                        bool, hipStream_t);
 
 // Instantiate every pass launcher for radius RR, image type IT, storage ST.
 #define RSF_INSTANTIATE(RR, IT, ST)                                                           \

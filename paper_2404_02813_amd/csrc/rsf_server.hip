@@ -72,28 +72,33 @@ struct Tile {
     bool started = false;         // set-up launched
     bool stopped = false;         // the device stopped it (tolerance)
     int64_t finish_chunk = -1;    // chunk holding its finish pass
+    int64_t chosen = -1;          // last chunk it was picked to iterate in
     double t_submit = 0, t_admit = 0;
 };
 
 // Tiles that may share launches: same radius, types and coefficients.
 using GroupKey = std::tuple<int, int, int, float, float, float, float, float, float, float, int,
-                            double, float>;
+                            double, float, int, float>;
 
 GroupKey key_of(const Tile &t)
 {
     const rsf_params &p = t.req.params;
     return GroupKey{t.R,        t.req.volume_dtype, p.storage, p.lambda1, p.lambda2,
                     p.nu,       p.mu,               p.dt,      p.eps,     p.eta,
-                    p.regulariser, t.req.tol,       p.sigma};
+                    p.regulariser, t.req.tol,       p.sigma,   p.force,   p.sigma2};
 }
 
 // One ring entry: pinned staging and device copy of a chunk's tile tables,
 // and the pinned copy of the flag slots taken at the chunk's end.
+constexpr int kGroupStreams = 3;           // streams for concurrent groups
+
 struct RingEntry {
     void *stage = nullptr;
     void *table = nullptr;
     void *flags_host = nullptr;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;                // chunk done (main stream)
+    hipEvent_t up_ev = nullptr;             // table uploaded
+    hipEvent_t join_ev[kGroupStreams] = {}; // group streams done
     size_t bytes = 0;
 };
 
@@ -108,7 +113,9 @@ struct Chunk {
 
 struct rsf_server {
     rsf_server_config cfg{};
+    rsf::Targets targets = rsf::kDefaultTargets;
     hipStream_t stream = nullptr;
+    hipStream_t gstream[kGroupStreams] = {};
     int *flags_dev = nullptr;      // kSlotBytes per slot
     RingEntry ring[kDepth];
     Arena arena{0, 0, kAlign};
@@ -289,6 +296,29 @@ bool launch_chunk(rsf_server *s, std::string &why)
     ch.id = id;
     ch.ring = ri;
 
+    // The tiles that iterate in this chunk: all of them, or (with a voxel
+    // cap) the first in the configured order until the cap is reached.
+    std::vector<Tile *> cand;
+    for (auto &t : s->resident)
+        if (t->finish_chunk < 0 && t->remaining > 0 && !t->stopped) cand.push_back(t.get());
+    if (s->cfg.batch_voxels > 0) {
+        auto vox = [](const Tile *t) { return (double)t->g.nx * t->g.ny * t->g.nz; };
+        if (s->cfg.order == RSF_ORDER_SHORTEST)
+            std::stable_sort(cand.begin(), cand.end(), [&](const Tile *a, const Tile *b) {
+                const double wa = vox(a) * a->remaining, wb = vox(b) * b->remaining;
+                return wa < wb || (wa == wb && a->ticket < b->ticket);
+            });
+        else
+            std::stable_sort(cand.begin(), cand.end(),
+                             [](const Tile *a, const Tile *b) { return a->ticket < b->ticket; });
+        double sum = 0.0;
+        size_t keep = 0;
+        while (keep < cand.size() && (keep == 0 || sum < (double)s->cfg.batch_voxels))
+            sum += vox(cand[keep++]);
+        cand.resize(keep);
+    }
+    for (Tile *t : cand) t->chosen = id;
+
     std::map<GroupKey, std::vector<Tile *>> groups;
     for (auto &t : s->resident)
         if (t->finish_chunk < 0) groups[key_of(*t)].push_back(t.get());
@@ -308,7 +338,7 @@ bool launch_chunk(rsf_server *s, std::string &why)
     for (auto &kv : groups) {
         std::vector<Tile *> run, fresh, fin;
         for (Tile *t : kv.second)
-            if (t->remaining > 0 && !t->stopped) (t->started ? run : fresh).push_back(t);
+            if (t->chosen == id) (t->started ? run : fresh).push_back(t);
         const int n_old = (int)run.size();
         run.insert(run.end(), fresh.begin(), fresh.end());
         int iters = 0;
@@ -325,7 +355,7 @@ bool launch_chunk(rsf_server *s, std::string &why)
         for (Tile *t : fin) vox_fin += (double)t->g.nx * t->g.ny * t->g.nz;
         auto desc_of = [&](Tile *t, double total) {
             const double share = (double)t->g.nx * t->g.ny * t->g.nz / total;
-            const Split sp = rsf::default_split(t->g, share);
+            const Split sp = rsf::default_split(t->g, share, s->targets);
             int *flags = reinterpret_cast<int *>(reinterpret_cast<char *>(s->flags_dev) +
                                                  (size_t)t->slot * kSlotBytes);
             return tile_desc(t->g, sp, t->req.volume, t->req.phi, t->base, t->T, t->req.iters,
@@ -416,7 +446,17 @@ bool launch_chunk(rsf_server *s, std::string &why)
     if (tw.off && !ok(hipMemcpyAsync(re.table, re.stage, tw.off, hipMemcpyHostToDevice, st),
                       "upload tile table"))
         return false;
-    for (const Launch &L : launches) {
+    // Groups share no tiles: each runs on its own stream (they overlap and
+    // fill each other's launch tails), after the table upload; the main
+    // stream joins them before copying the flags back.  The next chunk's
+    // upload follows that join, so a tile's chunks never overlap.
+    const int nstreams = std::min<int>((int)launches.size(), kGroupStreams);
+    if (nstreams > 1 && !ok(hipEventRecord(re.up_ev, st), "hipEventRecord(upload)")) return false;
+    for (int k = 0; k < nstreams && nstreams > 1; ++k)
+        if (!ok(hipStreamWaitEvent(s->gstream[k], re.up_ev, 0), "hipStreamWaitEvent")) return false;
+    for (size_t gi = 0; gi < launches.size(); ++gi) {
+        const Launch &L = launches[gi];
+        hipStream_t st = nstreams > 1 ? s->gstream[gi % kGroupStreams] : s->stream;
         if (L.n_new > 0) {
             if (!ok(rsf::launch_setup(L.new_tile.b, L.taps, L.R, st), "set-up")) return false;
             if (!ok(rsf::launch_xy(L.R, rsf::XY_ONE, L.image, L.storage, L.new_xy.b,
@@ -427,18 +467,21 @@ bool launch_chunk(rsf_server *s, std::string &why)
                     "K*I (z)"))
                 return false;
         }
+        const bool paper = L.c.force == RSF_FORCE_PAPER;
         for (int it = 0; it < L.iters; ++it) {
             if (!ok(rsf::launch_z_heaviside(L.R, L.image, L.storage, L.run_z.b, L.run_z.blocks,
                                             L.taps, L.c, false, st),
                     "z(H)") ||
-                !ok(rsf::launch_xy(L.R, rsf::XY_FITS, L.image, L.storage, L.run_xy.b,
-                                   L.run_xy.blocks, L.taps, L.c, false, st),
+                !ok(rsf::launch_xy(L.R, paper ? rsf::XY_PAPER : rsf::XY_FITS, L.image, L.storage,
+                                   L.run_xy.b, L.run_xy.blocks, L.taps, L.c, false, st),
                     "xy(fits)") ||
-                !ok(rsf::launch_xy(L.R, rsf::XY_TWO, L.image, L.storage, L.run_xy.b,
-                                   L.run_xy.blocks, L.taps, L.c, false, st),
-                    "xy(g)") ||
-                !ok(rsf::launch_z_update(L.R, L.image, L.storage, L.run_u.b, L.run_u.blocks,
-                                         L.taps, L.c, false, st),
+                (!paper && !ok(rsf::launch_xy(L.R, rsf::XY_TWO, L.image, L.storage, L.run_xy.b,
+                                              L.run_xy.blocks, L.taps, L.c, false, st),
+                               "xy(g)")) ||
+                !ok(paper ? rsf::launch_z_update_paper(L.image, L.storage, L.run_u.b,
+                                                       L.run_u.blocks, L.c, false, st)
+                          : rsf::launch_z_update(L.R, L.image, L.storage, L.run_u.b,
+                                                 L.run_u.blocks, L.taps, L.c, false, st),
                     "z(update)") ||
                 !ok(rsf::launch_reduce(L.run_tile.b, L.c, st), "reduce"))
                 return false;
@@ -446,6 +489,10 @@ bool launch_chunk(rsf_server *s, std::string &why)
         if (L.n_fin > 0 && !ok(rsf::launch_finish(L.fin_z.b, L.fin_z.blocks, st), "finish"))
             return false;
     }
+    for (int k = 0; k < nstreams && nstreams > 1; ++k)
+        if (!ok(hipEventRecord(re.join_ev[k], s->gstream[k]), "hipEventRecord(join)") ||
+            !ok(hipStreamWaitEvent(st, re.join_ev[k], 0), "hipStreamWaitEvent(join)"))
+            return false;
     ch.slots_copied = s->cfg.max_resident;
     if (!ok(hipMemcpyAsync(re.flags_host, s->flags_dev, (size_t)ch.slots_copied * kSlotBytes,
                            hipMemcpyDeviceToHost, st),
@@ -588,7 +635,15 @@ void free_server(rsf_server *s)
         if (re.flags_host) (void)hipHostFree(re.flags_host);
         if (re.table) (void)hipFree(re.table);
         if (re.ev) (void)hipEventDestroy(re.ev);
+        if (re.up_ev) (void)hipEventDestroy(re.up_ev);
+        for (hipEvent_t ev : re.join_ev)
+            if (ev) (void)hipEventDestroy(ev);
     }
+    for (hipStream_t gs : s->gstream)
+        if (gs) {
+            (void)hipStreamSynchronize(gs);
+            (void)hipStreamDestroy(gs);
+        }
     for (void *p : s->segments) (void)hipFree(p);
     if (s->flags_dev) (void)hipFree(s->flags_dev);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -604,8 +659,11 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
     if (!out) return RSF_ERR_INVALID_ARG;
     *out = nullptr;
     if (!cfg || cfg->budget_bytes == 0) return RSF_ERR_INVALID_ARG;
-    if (cfg->chunk_iters < 0 || cfg->max_resident < 0 || cfg->max_resident > kMaxResident)
+    if (cfg->chunk_iters < 0 || cfg->max_resident < 0 || cfg->max_resident > kMaxResident ||
+        cfg->batch_voxels < 0 || (cfg->order != RSF_ORDER_ARRIVAL && cfg->order != RSF_ORDER_SHORTEST))
         return RSF_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (cfg->split_targets[k] < 0 || cfg->split_targets[k] > (1 << 24)) return RSF_ERR_INVALID_ARG;
     rsf_server *s = nullptr;
     try {
         int count = 0;
@@ -616,6 +674,9 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
         if (s->cfg.chunk_iters == 0) s->cfg.chunk_iters = 4;
         if (s->cfg.max_resident == 0) s->cfg.max_resident = 256;
         if (s->cfg.segment_bytes == 0) s->cfg.segment_bytes = (size_t)8 << 30;
+        if (cfg->split_targets[0] > 0) s->targets.xy = cfg->split_targets[0];
+        if (cfg->split_targets[1] > 0) s->targets.z = cfg->split_targets[1];
+        if (cfg->split_targets[2] > 0) s->targets.u = cfg->split_targets[2];
         s->arena = Arena(s->cfg.budget_bytes, align_up(s->cfg.segment_bytes), kAlign);
         auto bad = [&](hipError_t e) {
             if (e == hipSuccess) return false;
@@ -624,6 +685,8 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
         };
         if (bad(hipSetDevice(cfg->device))) return RSF_ERR_DEVICE;
         if (bad(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking))) return RSF_ERR_DEVICE;
+        for (hipStream_t &gs : s->gstream)
+            if (bad(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking))) return RSF_ERR_DEVICE;
         const size_t fbytes = (size_t)s->cfg.max_resident * kSlotBytes;
         if (bad(hipMalloc(&s->flags_dev, fbytes))) return RSF_ERR_OUT_OF_MEMORY;
         if (bad(hipMemset(s->flags_dev, 0, fbytes))) return RSF_ERR_DEVICE;
@@ -633,8 +696,11 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
             if (bad(hipHostMalloc(&re.stage, tbytes, hipHostMallocDefault)) ||
                 bad(hipHostMalloc(&re.flags_host, fbytes, hipHostMallocDefault)) ||
                 bad(hipMalloc(&re.table, tbytes)) ||
-                bad(hipEventCreateWithFlags(&re.ev, hipEventDisableTiming)))
+                bad(hipEventCreateWithFlags(&re.ev, hipEventDisableTiming)) ||
+                bad(hipEventCreateWithFlags(&re.up_ev, hipEventDisableTiming)))
                 return RSF_ERR_OUT_OF_MEMORY;
+            for (hipEvent_t &ev : re.join_ev)
+                if (bad(hipEventCreateWithFlags(&ev, hipEventDisableTiming))) return RSF_ERR_DEVICE;
         }
         for (int i = s->cfg.max_resident - 1; i >= 0; --i) s->free_slots.push_back(i);
         s->worker = std::thread(worker_main, s);

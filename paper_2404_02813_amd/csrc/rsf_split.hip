@@ -30,13 +30,15 @@ Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_t
 }
 
 // A tile holding fraction `share` of a batch's voxels gets that fraction of
-// the batch's workgroups: xy ~16K waves (rows in chunks of at most 128),
-// z ~2K workgroups, update ~1K workgroups.  Fewer chunks per tile means fewer
+// the batch's workgroup targets (by default xy ~16K waves, rows in chunks of
+// at most 128; z ~2K workgroups; update ~1K workgroups).  Fewer chunks per tile means fewer
 // halo slices re-read, so small tiles in a big batch run unchunked.
-Split default_split(const Grid3 &g, double share)
+Split default_split(const Grid3 &g, double share, const Targets &tg)
 {
-    const auto part = [&](double n) { return (int64_t)std::max(1.0, std::ceil(n * share)); };
-    Split s = make_split(g, part(16384), part(2048), part(1024));
+    const auto part = [&](int64_t n) {
+        return (int64_t)std::max(1.0, std::ceil((double)n * share));
+    };
+    Split s = make_split(g, part(tg.xy), part(tg.z), part(tg.u));
     const int base = (g.ny + 127) / 128;
     if (s.xy < base) {
         const int64_t len = (g.ny + base - 1) / base;

@@ -32,10 +32,14 @@ RSF_U16 = 3
 RSF_REG_DOUBLE_WELL = 0
 RSF_REG_SINGLE_WELL = 1
 
+RSF_FORCE_RSF = 0
+RSF_FORCE_PAPER = 1
+
 EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
            "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
+           "rsf_set_split_targets",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
@@ -53,7 +57,8 @@ class rsf_params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_float), ("lambda1", ctypes.c_float),
                 ("lambda2", ctypes.c_float), ("nu", ctypes.c_float), ("mu", ctypes.c_float),
                 ("dt", ctypes.c_float), ("eps", ctypes.c_float), ("eta", ctypes.c_float),
-                ("regulariser", ctypes.c_int), ("storage", ctypes.c_int)]
+                ("regulariser", ctypes.c_int), ("storage", ctypes.c_int),
+                ("force", ctypes.c_int), ("sigma2", ctypes.c_float)]
 
 
 class rsf_stats(ctypes.Structure):
@@ -70,10 +75,15 @@ class rsf_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int * 6), ("ms", ctypes.c_double * 6)]
 
 
+RSF_ORDER_ARRIVAL = 0
+RSF_ORDER_SHORTEST = 1
+
+
 class rsf_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
                 ("segment_bytes", ctypes.c_size_t), ("chunk_iters", ctypes.c_int),
-                ("max_resident", ctypes.c_int)]
+                ("max_resident", ctypes.c_int), ("batch_voxels", ctypes.c_int64),
+                ("order", ctypes.c_int), ("split_targets", ctypes.c_int64 * 3)]
 
 
 class rsf_request(ctypes.Structure):
@@ -145,8 +155,10 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_double), i]
     L.rsf_get_tile_stats.restype = i
     L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
-                               vp]
+                               ctypes.POINTER(ctypes.c_int64), vp]
     L.rsf_autotune.restype = i
+    L.rsf_set_split_targets.argtypes = [vp, i64, i64, i64]
+    L.rsf_set_split_targets.restype = i
     L.rsf_autotune_reset.argtypes = [vp]
     L.rsf_autotune_reset.restype = None
     u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -207,9 +219,11 @@ def _field(t: torch.Tensor, name: str, dtype=torch.float32) -> torch.Tensor:
 
 
 def make_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta=1e-10,
-                regulariser=RSF_REG_DOUBLE_WELL, storage="f32") -> rsf_params:
+                regulariser=RSF_REG_DOUBLE_WELL, storage="f32", force=RSF_FORCE_RSF,
+                sigma2=0.0) -> rsf_params:
     st = _STORAGE[storage] if isinstance(storage, str) else int(storage)
-    return rsf_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta, regulariser, st)
+    return rsf_params(sigma, lambda1, lambda2, nu, mu, dt, eps, eta, regulariser, st, force,
+                      sigma2)
 
 
 def rsf_create(device: int = 0) -> ctypes.c_void_p:
@@ -303,11 +317,18 @@ def _tiles(volumes, phis):
 
 
 def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
-                 stream=None) -> None:
-    """Pick and keep per-shape workgroup splits by timing (phis untouched)."""
+                 stream=None) -> tuple:
+    """Pick and keep per-shape workgroup splits by timing (phis untouched);
+    returns the chosen (xy, z, update) workgroup targets."""
     arr, vdt = _tiles(volumes, phis)
+    chosen = (ctypes.c_int64 * 3)()
     _check(ctx, lib().rsf_autotune(ctx, arr, len(volumes), vdt, ctypes.byref(params),
-                                   int(trial_iters), _stream(stream)))
+                                   int(trial_iters), chosen, _stream(stream)))
+    return tuple(chosen)
+
+
+def rsf_set_split_targets(ctx, xy_waves: int = 0, z_blocks: int = 0, u_blocks: int = 0) -> None:
+    _check(ctx, lib().rsf_set_split_targets(ctx, int(xy_waves), int(z_blocks), int(u_blocks)))
 
 
 def rsf_autotune_reset(ctx) -> None:
@@ -412,7 +433,10 @@ class Context:
         rsf_evolve_batch(self.handle, volumes, phis, params, iters, tol, workspace, stream)
 
     def autotune(self, volumes, phis, params, trial_iters=3, stream=None):
-        rsf_autotune(self.handle, volumes, phis, params, trial_iters, stream)
+        return rsf_autotune(self.handle, volumes, phis, params, trial_iters, stream)
+
+    def set_split_targets(self, xy_waves=0, z_blocks=0, u_blocks=0):
+        rsf_set_split_targets(self.handle, xy_waves, z_blocks, u_blocks)
 
     def autotune_reset(self):
         rsf_autotune_reset(self.handle)
@@ -443,9 +467,11 @@ def _server_check(srv, status: int) -> None:
 
 
 def rsf_server_create(budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
-                      segment_bytes: int = 0, device: int = 0) -> ctypes.c_void_p:
+                      segment_bytes: int = 0, device: int = 0, batch_voxels: int = 0,
+                      order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0)) -> ctypes.c_void_p:
     cfg = rsf_server_config(device, int(budget_bytes), int(segment_bytes), int(chunk_iters),
-                            int(max_resident))
+                            int(max_resident), int(batch_voxels), int(order),
+                            (ctypes.c_int64 * 3)(*[int(v) for v in split_targets]))
     h = ctypes.c_void_p()
     st = lib().rsf_server_create(ctypes.byref(h), ctypes.byref(cfg))
     if st != RSF_OK:
@@ -508,9 +534,10 @@ class Server:
     tensors until its result has been read, so they outlive the device work."""
 
     def __init__(self, budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
-                 segment_bytes: int = 0, device: int = 0):
+                 segment_bytes: int = 0, device: int = 0, batch_voxels: int = 0,
+                 order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0)):
         self.handle = rsf_server_create(budget_bytes, chunk_iters, max_resident, segment_bytes,
-                                        device)
+                                        device, batch_voxels, order, split_targets)
         self._held = {}
 
     def submit(self, volume, phi, params, iters, tol=0.0) -> int:

@@ -22,6 +22,13 @@ PHI_TOL = 1e-3
 SIGN_AGREE = 0.9999
 
 
+def phi_tol(storage):
+    """max|dphi| bar after N iterations: 1e-3 (FP32 arithmetic; FP32 or FP16
+    storage).  BF16 storage keeps 8 significand bits: the bar scales with its
+    unit roundoff over FP16's, 2^-8 / 2^-11 = 8."""
+    return PHI_TOL * (8.0 if storage == "bf16" else 1.0)
+
+
 def say(msg):
     print(f"[gpu-case] {msg}", flush=True)
     sys.stdout.flush()
@@ -365,7 +372,7 @@ def test_mixed_precision_evolution(rsf, storage, image):
     want, _ = oracle.evolve(I, phi0, oracle.params_array(**p, eta=1e-10), iters)
     dmax, agree = parity(got, want)
     say(f"  max|dphi|={dmax:.3e} agree={agree:.7f}")
-    assert dmax <= PHI_TOL and agree >= SIGN_AGREE
+    assert dmax <= phi_tol(storage) and agree >= SIGN_AGREE
 
 
 def test_mixed_precision_radius_limits(rsf):

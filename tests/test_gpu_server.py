@@ -181,3 +181,25 @@ def test_server_rejects_bad_requests(rsf):
             srv.poll(12345)
         assert e.value.status == mod.RSF_ERR_INVALID_ARG
         assert srv.stats()["submitted"] == 0
+
+
+@pytest.mark.parametrize("order", ["arrival", "shortest"])
+def test_server_voxel_cap_schedules(rsf, order):
+    """With a per-chunk voxel cap only some resident tiles iterate in each
+    chunk (by arrival or by least remaining work); results are unchanged."""
+    mod, ctx = rsf
+    say(f"server: voxel cap, order {order}")
+    reqs = requests(mod, 1000)
+    outs = [rq["phi0"].clone() for rq in reqs]
+    torch.cuda.synchronize()
+    o = mod.RSF_ORDER_ARRIVAL if order == "arrival" else mod.RSF_ORDER_SHORTEST
+    with mod.Server(budget_bytes=8 << 30, chunk_iters=3, batch_voxels=150_000, order=o) as srv:
+        tickets = [srv.submit(rq["vol"], o_, rq["params"], rq["iters"])
+                   for rq, o_ in zip(reqs, outs)]
+        results = [srv.wait(t, 120.0) for t in tickets]
+    if order == "shortest":
+        # the least work (iterations x voxels) finishes first
+        work = [rq["iters"] * rq["phi0"].numel() for rq in reqs]
+        first = int(np.argmin([r["t_done"] for r in results]))
+        assert work[first] == min(work)
+    check_equal_alone(ctx, reqs, outs, results)

@@ -406,3 +406,100 @@ def test_float_variant_is_close_on_double_well():
     a, _ = oracle.evolve(I, phi0, p, 20, real="f64")
     b, _ = oracle.evolve(I, phi0, p, 20, real="f32")
     assert np.max(np.abs(a - b)) < 1e-4
+
+
+# --- The Sec. 4.2 force (force = 1, sigma2) -----------------------------------
+
+def PP(sigma2=0.0, **kw):
+    p = P(**kw)
+    p[8] = oracle.FORCE_PAPER
+    p[9] = sigma2
+    return p
+
+
+def test_paper_force_sigma2_zero_is_pointwise_square():
+    """With sigma2 = 0 the kernel of the directional force is a point mass,
+    so its integral over y collapses to |I(x) - r(x)|^2 (direct evaluation of
+    the integral definition with a delta kernel)."""
+    shape = (9, 11, 10)
+    r = rng(21)
+    I = r.uniform(0, 1, size=shape)
+    phi = smooth_field(shape, 22)
+    _, f, _ = oracle.step(I, phi, PP(0.0, sigma=1.5))
+    delta = np.zeros((3, 3, 3))
+    delta[1, 1, 1] = 1.0
+    for key, fit in (("e1", f["f1"]), ("e2", f["f2"])):
+        want = np.zeros(shape)
+        for z in range(shape[0]):
+            for y in range(shape[1]):
+                for x in range(shape[2]):
+                    acc = 0.0
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                zz, yy, xx = z + dz, y + dy, x + dx
+                                if 0 <= zz < shape[0] and 0 <= yy < shape[1] and 0 <= xx < shape[2]:
+                                    acc += delta[dz + 1, dy + 1, dx + 1] * (I[zz, yy, xx] - fit[z, y, x]) ** 2
+                    want[z, y, x] = acc
+        assert np.max(np.abs(f[key] - want)) < 1e-14
+
+
+def test_paper_force_expansion_equals_integral_in_the_interior():
+    """Sec. 4.2 expands the directional force integral sum_y K2(x-y)|I(y) -
+    r(x)|^2 into K2*I^2 - 2 r K2*I + r^2; the two agree wherever the whole
+    kernel lies inside the volume (unit-sum weights).  Brute force of the
+    integral with the separable sigma2 Gaussian built from scipy's taps."""
+    shape = (13, 13, 13)
+    sigma2 = 1.0
+    r = rng(23)
+    I = r.uniform(0, 1, size=shape)
+    phi = smooth_field(shape, 24)
+    _, f, _ = oracle.step(I, phi, PP(sigma2, sigma=1.2))
+    g = scipy_taps(sigma2)
+    R2 = (len(g) - 1) // 2
+    for key, fit in (("e1", f["f1"]), ("e2", f["f2"])):
+        for (z, y, x) in [(6, 6, 6), (3, 4, 5), (9, 8, 3), (R2, R2, R2), (12 - R2, 6, 12 - R2)]:
+            acc = 0.0
+            for a in range(-R2, R2 + 1):
+                for b in range(-R2, R2 + 1):
+                    for c in range(-R2, R2 + 1):
+                        acc += g[a + R2] * g[b + R2] * g[c + R2] * (I[z + a, y + b, x + c] - fit[z, y, x]) ** 2
+            assert abs(f[key][z, y, x] - acc) < 1e-13, (key, z, y, x)
+
+
+def test_paper_force_chan_vese_limit():
+    """sigma -> infinity with sigma2 = 0: the fits become the region means
+    and the force becomes lambda1 (I - c+)^2 - lambda2 (I - c-)^2, the
+    Chan-Vese force the paper starts from (Sec. 3)."""
+    shape = (12, 12, 12)
+    r = rng(25)
+    I = r.uniform(0, 1, size=shape)
+    phi = smooth_field(shape, 26)
+    _, f, _ = oracle.step(I, phi, PP(0.0, sigma=500.0, lambda1=1.0, lambda2=2.0))
+    H = f["H"]
+    cp = np.sum(H * I) / np.sum(H)
+    cm = np.sum((1 - H) * I) / np.sum(1 - H)
+    assert np.max(np.abs(f["e1"] - (I - cp) ** 2)) < 2e-3
+    assert np.max(np.abs(f["e2"] - (I - cm) ** 2)) < 2e-3
+
+
+def test_paper_force_drives_front_onto_edge():
+    m = 12
+    I, phi0 = edge_setup(m, shift=3.0)
+    c0 = crossing(phi0[2, 3])
+    phi, _ = oracle.evolve(I, phi0, PP(0.0, sigma=2.0, lambda1=100.0, lambda2=100.0), 100)
+    c1 = crossing(phi[2, 3])
+    assert c1 < c0 - 2.5
+    assert abs(c1 - (m - 0.5)) < 0.25
+
+
+def test_paper_force_constant_image_and_reversal():
+    shape = (10, 12, 9)
+    phi = smooth_field(shape, 27)
+    nxt, f, _ = oracle.step(np.full(shape, 0.6), phi, PP(0.0, sigma=1.5, mu=0.0, nu=0.0))
+    assert np.max(np.abs(f["e1"])) < 1e-13 and np.max(np.abs(nxt - phi)) < 1e-13
+    # I -> 1 - I maps r -> 1 - r and leaves (I - r)^2, hence the step, unchanged
+    I = rng(28).uniform(0, 1, size=shape)
+    a, _, _ = oracle.step(I, phi, PP(0.0, sigma=1.5))
+    b, _, _ = oracle.step(1.0 - I, phi, PP(0.0, sigma=1.5))
+    assert np.max(np.abs(a - b)) < 1e-12
