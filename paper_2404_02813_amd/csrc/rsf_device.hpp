@@ -21,6 +21,18 @@ __device__ __forceinline__ float heaviside(float phi, float eps)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// The tile table hands the kernels generic pointers.  Recasting them to the
+// global address space lets the compiler use global instead of flat memory
+// instructions: flat ones also count against the LDS wait counter, so every
+// LDS wait would also wait for the loads prefetched a step ahead.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T *p)
+{
+    return (gptr<T>)p;
+}
+
 // Storage and image element types: fields may be stored as float, FP16 or
 // BF16 (arithmetic is always FP32); the image may be float or uint16, the
 // latter normalised to [0, 1] as u / 65535 on load.
@@ -38,6 +50,35 @@ template <class T>
 struct alignas(2 * sizeof(T)) Pair {
     T a, b;
 };
+
+// Pair element i as one vector access (4 or 8 bytes per lane).
+template <class T>
+using Vec2 = T __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ float2 ld_pair(gptr<const Pair<T>> p, int64_t i)
+{
+    const Vec2<T> v = ((gptr<const Vec2<T>>)p)[i];
+    return make_float2(to_f(v.x), to_f(v.y));
+}
+
+// The raw element pair, converted only where it is used: converting right
+// after the load would make the load's consumer wait for it there, and a
+// load issued a step ahead would no longer overlap anything.
+template <class T>
+__device__ __forceinline__ Vec2<T> ld_pair_raw(gptr<const Pair<T>> p, int64_t i)
+{
+    return ((gptr<const Vec2<T>>)p)[i];
+}
+
+template <class T>
+__device__ __forceinline__ void st_pair(gptr<Pair<T>> p, int64_t i, float a, float b)
+{
+    Vec2<T> v;
+    v.x = from_f<T>(a);
+    v.y = from_f<T>(b);
+    ((gptr<Vec2<T>>)p)[i] = v;
+}
 
 // Make `v` opaque to the optimiser: it must be computed here, so a sum that
 // feeds a register ring is not sunk to its distant use (which would keep all

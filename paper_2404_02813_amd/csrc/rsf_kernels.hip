@@ -87,13 +87,13 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(Batch bt)
     Where wh;
     if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
-    if (!(d.flags[1] & 1)) return;
+    if (!(glb(d.flags)[1] & 1)) return;
     const Grid3 g = d.g;
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
     const int col = zt.col;
-    const float *__restrict__ src = d.phi[1];
-    float *__restrict__ dst = d.phi[0];
+    const gptr<const float> src = glb(d.phi[1]);
+    const gptr<float> dst = glb(d.phi[0]);
     for (int z = zt.z0; z < zt.z1; ++z) (dst + (int64_t)z * g.sxy)[col] = (src + (int64_t)z * g.sxy)[col];
 }
 

@@ -3,6 +3,8 @@
 // units that instantiate them for a range of radii (rsf_inst_*.hip).
 #pragma once
 
+#include <type_traits>
+
 #include "rsf_device.hpp"
 
 namespace rsf {
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     Where wh;
     if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
-    if (d.flags[0]) return;
+    if (glb(d.flags)[0]) return;
     const Grid3 g = d.g;
     const int nyc = d.sp.xy;
     const void *__restrict__ in_ = MODE == XY_ONE ? d.I : (FITS ? d.P : d.Q);
@@ -50,9 +52,13 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 
     // A row's loads are issued one step before the row is staged, so the
     // global latency overlaps the previous row's arithmetic.
+    // raw elements of one row (lanes j and j + 64), converted when staged
     struct Raw {
-        float a[2], b[2];
+        Vec2<IN> p[2];
+        IN s[2];
     };
+    const gptr<const Pair<IN>> in2 = glb(static_cast<const Pair<IN> *>(in_));
+    const gptr<const IN> in1 = glb(static_cast<const IN *>(in_));
     auto fetch = [&](int y) {
         Raw r;
         // uniform row bases, 32-bit lane offsets
@@ -61,18 +67,13 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            r.a[h] = 0.f;
-            r.b[h] = 0.f;
+            r.p[h] = Vec2<IN>{};
+            r.s[h] = IN{};
             const int j = lane + 64 * h;
             const int gx = x0 - R + j;
             if (yok && j < RW && gx >= 0 && gx < g.nx) {
-                if (NF == 2) {
-                    const Pair<IN> v = (static_cast<const Pair<IN> *>(in_) + rowo)[gx];
-                    r.a[h] = to_f(v.a);
-                    r.b[h] = to_f(v.b);
-                } else {
-                    r.a[h] = to_f((static_cast<const IN *>(in_) + rowo)[gx]);
-                }
+                if (NF == 2) r.p[h] = ld_pair_raw<IN>(in2 + rowo, gx);
+                else r.s[h] = (in1 + rowo)[gx];
             }
         }
         return r;
@@ -83,8 +84,12 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         for (int h = 0; h < 2; ++h) {
             const int j = lane + 64 * h;
             if (j < RW) {
-                row[slot][0][j] = r.a[h];
-                if (NF == 2) row[slot][NF - 1][j] = r.b[h];
+                if (NF == 2) {
+                    row[slot][0][j] = to_f(r.p[h].x);
+                    row[slot][NF - 1][j] = to_f(r.p[h].y);
+                } else {
+                    row[slot][0][j] = to_f(r.s[h]);
+                }
             }
         }
         __syncthreads();
@@ -112,17 +117,18 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     }
     float cxz = 0.f;
     const int xc = min(x, g.nx - 1);
-    const ST *ki_slice = FITS ? static_cast<const ST *>(d.KI) + zb : nullptr;
-    const IMG *im_slice = MODE == XY_PAPER ? static_cast<const IMG *>(d.I) + zb : nullptr;
-    const float *cyp = d.cy;
-    if (FITS) cxz = d.cx[xc] * d.cz[z];
-    float ki_next = FITS ? to_f(ki_slice[y0 * g.nx + xc]) : 0.f;
-    float im_next = MODE == XY_PAPER ? to_f(im_slice[y0 * g.nx + xc]) : 0.f;
+    const gptr<const ST> ki_slice = glb(static_cast<const ST *>(d.KI)) + zb;
+    const gptr<const IMG> im_slice = glb(static_cast<const IMG *>(d.I)) + zb;
+    const gptr<const float> cyp = glb(d.cy);
+    if (FITS) cxz = glb(d.cx)[xc] * glb(d.cz)[z];
+    ST ki_next = FITS ? ki_slice[y0 * g.nx + xc] : ST{};
+    IMG im_next = MODE == XY_PAPER ? im_slice[y0 * g.nx + xc] : IMG{};
     float cy_next = FITS ? cyp[y0] : 0.f;
-    float *probe_f1 = d.probe_f1, *probe_f2 = d.probe_f2, *probe_fd = d.probe_Fd;
-    ST *o1_s = static_cast<ST *>(out_) + zb;
-    Pair<ST> *o2_s = static_cast<Pair<ST> *>(out_) + zb;
-    float *of_s = static_cast<float *>(out_) + zb;
+    const gptr<float> probe_f1 = glb(d.probe_f1), probe_f2 = glb(d.probe_f2),
+                      probe_fd = glb(d.probe_Fd);
+    const gptr<ST> o1_s = glb(static_cast<ST *>(out_)) + zb;
+    const gptr<Pair<ST>> o2_s = glb(static_cast<Pair<ST> *>(out_)) + zb;
+    const gptr<float> of_s = glb(static_cast<float *>(out_)) + zb;
     for (int yb = y0; yb < y1; yb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
@@ -131,14 +137,16 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                 const Raw cur = nxt;
                 nxt = fetch(y + R + 1);
                 float ki = 0.f, cyv = 0.f, im = 0.f;
+                ST ki_raw = ST{};
+                IMG im_raw = IMG{};
                 if (FITS) {
-                    ki = ki_next;
+                    ki_raw = ki_next;
                     cyv = cy_next;
-                    im = im_next;
+                    im_raw = im_next;
                     if (y + 1 < y1) {
-                        ki_next = to_f(ki_slice[(y + 1) * g.nx + xc]);
+                        ki_next = ki_slice[(y + 1) * g.nx + xc];
                         cy_next = cyp[y + 1];
-                        if (MODE == XY_PAPER) im_next = to_f(im_slice[(y + 1) * g.nx + xc]);
+                        if (MODE == XY_PAPER) im_next = im_slice[(y + 1) * g.nx + xc];
                     }
                 }
                 // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
@@ -154,6 +162,8 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                 if (x < g.nx) {
                     const int v = y * g.nx + x;      // offset within the slice
                     if (FITS) {
+                        ki = to_f(ki_raw);
+                        im = to_f(im_raw);
                         // region fits (Sec. 3 local_intensity)
                         const float K1 = cxz * cyv;
                         const float A2 = ki - acc_a;
@@ -168,13 +178,13 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                             if (probe_fd) probe_fd[zb + v] = Fd;
                         } else {
                             // force-convolution inputs g1, g2
-                            o2_s[v] = Pair<ST>{from_f<ST>(c.l1 * f1 - c.l2 * f2),
-                                               from_f<ST>(c.l1 * f1 * f1 - c.l2 * f2 * f2)};
+                            st_pair<ST>(o2_s, v, c.l1 * f1 - c.l2 * f2,
+                                        c.l1 * f1 * f1 - c.l2 * f2 * f2);
                         }
                         if (probe_f1) probe_f1[zb + v] = f1;
                         if (probe_f2) probe_f2[zb + v] = f2;
                     } else if (NF == 2) {
-                        o2_s[v] = Pair<ST>{from_f<ST>(acc_a), from_f<ST>(acc_b)};
+                        st_pair<ST>(o2_s, v, acc_a, acc_b);
                     } else {
                         o1_s[v] = from_f<ST>(acc_a);
                     }
@@ -192,6 +202,13 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 // ---------------------------------------------------------------------------
 
 
+// Raw stage-1 inputs of one voxel: phi and the image element.
+template <class IT>
+struct PhiImg {
+    float phi;
+    IT img;
+};
+
 // Conv ring.  fetch(z) loads the raw inputs of slice z (0 <= z < nz) and
 // cook(raw, z) turns them into the two convolved quantities; each slice is
 // fetched one step before it is cooked so the load latency overlaps the
@@ -202,17 +219,18 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
 {
     constexpr int W = 2 * R + 1;
     float ra[W], rb[W];
-    auto get = [&](int z) { return (z >= 0 && z < nz) ? fetch(z) : make_float2(0.f, 0.f); };
-    auto use = [&](float2 raw, int z) {
+    using Raw = decltype(fetch(0));
+    auto get = [&](int z) { return (z >= 0 && z < nz) ? fetch(z) : Raw{}; };
+    auto use = [&](const Raw &raw, int z) {
         float2 v = (z >= 0 && z < nz) ? cook(raw, z) : make_float2(0.f, 0.f);
         pin(v.x);
         if (NF == 2) pin(v.y);
         return v;
     };
-    float2 nxt = get(z0 - R);
+    Raw nxt = get(z0 - R);
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) {
-        const float2 cur = nxt;
+        const Raw cur = nxt;
         nxt = get(z0 - R + j + 1);
         const float2 v = use(cur, z0 - R + j);
         ra[j] = v.x;
@@ -225,7 +243,7 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
             const int z = zb + s;
             if (z < z1) {
                 const int zn = z + R;
-                const float2 cur = nxt;
+                const Raw cur = nxt;
                 nxt = get(zn + 1);
                 const float2 v = use(cur, zn);
                 ra[(s + 2 * R) % W] = v.x;
@@ -253,15 +271,15 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t)
     if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
     const Grid3 g = d.g;
-    const ST *__restrict__ in = static_cast<const ST *>(d.P);
-    ST *__restrict__ out = static_cast<ST *>(d.KI);
+    const gptr<const ST> in = glb(static_cast<const ST *>(d.P));
+    const gptr<ST> out = glb(static_cast<ST *>(d.KI));
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
     const int col = zt.col;   // nx * ny < 2^31 - 1024
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
-        [&](int z) { return make_float2(to_f((in + (int64_t)z * g.sxy)[col]), 0.f); },
-        [&](float2 raw, int) { return raw; },
+        [&](int z) { return (in + (int64_t)z * g.sxy)[col]; },
+        [&](ST raw, int) { return make_float2(to_f(raw), 0.f); },
         [&](int z, float va, float) { (out + (int64_t)z * g.sxy)[col] = from_f<ST>(va); });
 }
 
@@ -272,12 +290,12 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t,
     Where wh;
     if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
-    if (d.flags[0]) return;
+    if (glb(d.flags)[0]) return;
     const Grid3 g = d.g;
-    const float *__restrict__ phi = d.phi[d.flags[1] & 1];   // iterate n is in phi[n & 1]
-    const IT *__restrict__ I = static_cast<const IT *>(d.I);
-    Pair<ST> *__restrict__ tp = static_cast<Pair<ST> *>(d.P);
-    float *__restrict__ probeH = d.probe_H;
+    const gptr<const float> phi = glb(d.phi[glb(d.flags)[1] & 1]);   // iterate n is in phi[n & 1]
+    const gptr<const IT> I = glb(static_cast<const IT *>(d.I));
+    const gptr<Pair<ST>> tp = glb(static_cast<Pair<ST> *>(d.P));
+    const gptr<float> probeH = glb(d.probe_H);
     const float eps = c.eps;
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
@@ -286,15 +304,15 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t,
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
             const int64_t zo = (int64_t)z * g.sxy;
-            return make_float2((phi + zo)[col], to_f((I + zo)[col]));
+            return PhiImg<IT>{(phi + zo)[col], (I + zo)[col]};
         },
-        [&](float2 raw, int z) {
-            const float H = heaviside(raw.x, eps);
+        [&](const PhiImg<IT> &raw, int z) {
+            const float H = heaviside(raw.phi, eps);
             if (PROBE && probeH) (probeH + (int64_t)z * g.sxy)[col] = H;
-            return make_float2(H * raw.y, H);
+            return make_float2(H * to_f(raw.img), H);
         },
         [&](int z, float va, float vb) {
-            (tp + (int64_t)z * g.sxy)[col] = Pair<ST>{from_f<ST>(va), from_f<ST>(vb)};
+            st_pair<ST>(tp + (int64_t)z * g.sxy, col, va, vb);
         });
 }
 
@@ -357,12 +375,12 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
     const TileDesc &d = bt.tiles[wh.t];
     // a stopped tile keeps its last iterate where it is (the whole block
     // leaves; its partial is not read)
-    if (d.flags[0]) return;
+    if (glb(d.flags)[0]) return;
     const Grid3 g = d.g;
-    const Pair<ST> *__restrict__ tp = static_cast<const Pair<ST> *>(d.P);
-    const int cur = d.flags[1] & 1;   // iterate n is in phi[n & 1]
-    const float *__restrict__ phi = d.phi[cur];
-    float *__restrict__ phi_out = d.phi[cur ^ 1];
+    const gptr<const Pair<ST>> tp = glb(static_cast<const Pair<ST> *>(d.P));
+    const int cur = glb(d.flags)[1] & 1;   // iterate n is in phi[n & 1]
+    const gptr<const float> phi = glb(d.phi[cur]);
+    const gptr<float> phi_out = glb(d.phi[cur ^ 1]);
     const ZTile zt = z_tile_t<TX, TY>(g, d.sp.u, wh.lb);
     const int tid = threadIdx.x;
     const int tx = tid & (TX - 1), ty = tid / TX;
@@ -390,7 +408,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // clamp before reflecting to keep every address inside the volume.
         auto fetch_phi = [&](int j) {
             PhiRaw r;
-            const float *base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
+            const gptr<const float> base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
 #pragma unroll
             for (int k = 0; k < NLD; ++k) r.v[k] = lok[k] ? base[loff[k]] : 0.f;
             return r;
@@ -441,14 +459,10 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         };
 
         const int col = min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
-        const float cxy = d.cx[min(zt.x, g.nx - 1)] * d.cy[min(zt.y, g.ny - 1)];
-        const float *czp = d.cz;
-        const IT *img = static_cast<const IT *>(d.I);
-        auto at = [&](const auto *base, int z) { return to_f((base + (int64_t)z * g.sxy)[col]); };
-        auto pair_at = [&](int z) {
-            const Pair<ST> v = (tp + (int64_t)z * g.sxy)[col];
-            return make_float2(to_f(v.a), to_f(v.b));
-        };
+        const float cxy = glb(d.cx)[min(zt.x, g.nx - 1)] * glb(d.cy)[min(zt.y, g.ny - 1)];
+        const gptr<const float> czp = glb(d.cz);
+        const gptr<const IT> img = glb(static_cast<const IT *>(d.I));
+        auto pair_at = [&](int z) { return ld_pair_raw<ST>(tp + (int64_t)z * g.sxy, col); };
         const int z0 = zt.z0;
         // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
 #pragma unroll
@@ -465,19 +479,23 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) {
                 const int z = z0 - R + j;
-                const float2 v = (z >= 0 && z < g.nz) ? pair_at(z) : make_float2(0.f, 0.f);
-                ra[j] = v.x;
-                rb[j] = v.y;
+                const Vec2<ST> v = (z >= 0 && z < g.nz) ? pair_at(z) : Vec2<ST>{};
+                ra[j] = to_f(v.x);
+                rb[j] = to_f(v.y);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
         // one-step-ahead prefetch of the next phi slice, conv inputs and image
         // (PAPER: the force field instead)
-        const float *fdp = static_cast<const float *>(d.Q);
+        const gptr<const float> fdp = glb(static_cast<const float *>(d.Q));
         PhiRaw phi_nxt = fetch_phi(z0 + 3);
-        float2 t_nxt = make_float2(0.f, 0.f);
-        if constexpr (!PAPER) t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : make_float2(0.f, 0.f);
-        float I_nxt = z0 < zt.z1 ? (PAPER ? at(fdp, z0) : at(img, z0)) : 0.f;
+        Vec2<ST> t_nxt{};
+        if constexpr (!PAPER) t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : Vec2<ST>{};
+        // raw image (PAPER: the float force), converted where used
+        using IRaw = typename std::conditional<PAPER, float, IT>::type;
+        const gptr<const IRaw> ip = PAPER ? (gptr<const IRaw>)fdp : (gptr<const IRaw>)img;
+        auto iraw = [&](int z) { return (ip + (int64_t)z * g.sxy)[col]; };
+        IRaw I_nxt = z0 < zt.z1 ? iraw(z0) : IRaw{};
         for (int zb = z0; zb < zt.z1; zb += W) {
 #pragma unroll
             for (int s = 0; s < W; ++s) {
@@ -485,16 +503,16 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 if (z < zt.z1) {
                     store_phi(phi_nxt, z + 3);
                     if constexpr (!PAPER) {
-                        ra[(s + 2 * R) % W] = t_nxt.x;
-                        rb[(s + 2 * R) % W] = t_nxt.y;
+                        ra[(s + 2 * R) % W] = to_f(t_nxt.x);
+                        rb[(s + 2 * R) % W] = to_f(t_nxt.y);
                     }
-                    const float Iv = I_nxt;   // PAPER: F_d of slice z
+                    const IRaw I_cur = I_nxt;   // PAPER: F_d of slice z
                     phi_nxt = fetch_phi(z + 4);
                     if constexpr (!PAPER) {
                         const int zn = z + R + 1;
-                        t_nxt = zn < g.nz ? pair_at(zn) : make_float2(0.f, 0.f);
+                        t_nxt = zn < g.nz ? pair_at(zn) : Vec2<ST>{};
                     }
-                    if (z + 1 < zt.z1) I_nxt = PAPER ? at(fdp, z + 1) : at(img, z + 1);
+                    if (z + 1 < zt.z1) I_nxt = iraw(z + 1);
                     __syncthreads();
                     float nzpp, vzpp;
                     q_phase(z + 2, nzpp, vzpp);
@@ -521,6 +539,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                         const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
                                            0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
                                            0.5f * (vzp - vzm);
+                        const float Iv = to_f(I_cur);
                         float Fd;
                         if constexpr (PAPER) {
                             Fd = Iv;
@@ -535,11 +554,11 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                         (phi_out + zo)[col] = nxt;
                         acc += fabs((double)nxt - (double)cphi);
                         if (PROBE) {
-                            if (d.probe_Fd) (d.probe_Fd + zo)[col] = Fd;
-                            if (d.probe_kappa) (d.probe_kappa + zo)[col] = kappa;
-                            if (d.probe_lap) (d.probe_lap + zo)[col] = lap;
-                            if (d.probe_R) (d.probe_R + zo)[col] = Rt;
-                            if (d.probe_E) (d.probe_E + zo)[col] = E;
+                            if (d.probe_Fd) (glb(d.probe_Fd) + zo)[col] = Fd;
+                            if (d.probe_kappa) (glb(d.probe_kappa) + zo)[col] = kappa;
+                            if (d.probe_lap) (glb(d.probe_lap) + zo)[col] = lap;
+                            if (d.probe_R) (glb(d.probe_R) + zo)[col] = Rt;
+                            if (d.probe_E) (glb(d.probe_E) + zo)[col] = E;
                         }
                     }
                     nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
@@ -558,7 +577,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         double sum = 0.0;
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) sum += wsum[w];
-        d.partials[wh.lb] = sum;
+        glb(d.partials)[wh.lb] = sum;
     }
 }
 
