@@ -67,6 +67,7 @@ def workloads():
 
 KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
                   "paper_2404_02813_amd/csrc/rsf_kernels.hpp",
+                  "paper_2404_02813_amd/csrc/rsf_device.hpp",
                   "paper_2404_02813_amd/csrc/rsf_internal.hpp"]
 
 
@@ -99,11 +100,19 @@ KERNEL_PASS = (("z_heaviside_kernel<", "z_heaviside"), ("xy_kernel<", None),
 
 
 def _pass_of(kernel_name: str):
-    """Map a device kernel name to its pass (xy mode 1 = force, 2 = fits)."""
+    """Map a device kernel name (demangled, or mangled as rocprofv3 leaves
+    FP16 instances) to its pass (xy mode 1 = force, 2 and 3 = fits)."""
     import re
-    m = re.search(r"xy_kernel<\d+, (\d)>", kernel_name)
+    m = re.search(r"xy_kernel<\d+, (\d)", kernel_name) or \
+        re.search(r"xy_kernelILi\d+ELi(\d)E", kernel_name)
     if m:
-        return {"1": "xy_force", "2": "xy_fits"}.get(m.group(1))
+        return {"1": "xy_force", "2": "xy_fits", "3": "xy_fits"}.get(m.group(1))
+    m = re.search(r"z_heaviside_kernelILi\d+ELb(\d)E", kernel_name)
+    if m:
+        return "z_heaviside" if m.group(1) == "0" else None
+    m = re.search(r"z_update_kernelILi\d+ELb(\d)E", kernel_name)
+    if m:
+        return "z_update" if m.group(1) == "0" else None
     for key, name in KERNEL_PASS:
         if key in kernel_name and "true" not in kernel_name.split(key, 1)[1][:12]:
             return name
