@@ -216,6 +216,29 @@ rsf_status rsf_get_tile_stats(rsf_context *ctx, int tile, rsf_stats *out, double
  * sum|phi_{n+1} - phi_n| in double (the convergence reduction). */
 rsf_status rsf_get_stats(rsf_context *ctx, rsf_stats *out, double *s_hist, int cap);
 
+/* Volume-level driver (Sec. 4.1, volume level parallelism).  Splits the
+ * volume into sub-volumes whose cores cut each axis into near-equal parts of
+ * at most `block` voxels, extends each core by a curtain of `curtain`
+ * voxels (0: ceil(3 max(sigma, sigma2))) on every side shared with a
+ * neighbour, evolves the sub-volumes independently (each from its slice of
+ * phi, `iters` iterations, in batches of at most `budget_bytes` of copies
+ * and workspace; 0 = all at once), and merges them into phi by linear
+ * interpolation across each 2*curtain-wide overlap: along an axis the
+ * weight of a sub-volume ramps linearly from 1/(4C) to 1 - 1/(4C) across
+ * the overlap and its neighbour's weight is the complement; corners take the
+ * product of the per-axis weights, so the weights of all sub-volumes sum to
+ * one.  With a single sub-volume the result is rsf_evolve_ex's.
+ * Every core must be at least 2 * curtain long (RSF_ERR_INVALID_ARG);
+ * a sub-volume larger than the budget gives RSF_ERR_BUDGET.  Allocates an
+ * FP32 merge buffer of the volume's size and the sub-volume copies for the
+ * duration of the call; synchronises `stream`; phi is untouched on a
+ * validation error.  Tolerance-based stopping and statistics are not
+ * offered here. */
+rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                             int64_t nx, int64_t ny, int64_t nz, int64_t block, int64_t curtain,
+                             const rsf_params *params, int iters, size_t budget_bytes,
+                             void *stream);
+
 /* One zero-padded Gaussian convolution out = K * in (Sec. 3 kernel), the
  * separable passes the evolution uses.  in, out: device floats, distinct;
  * every dimension >= 3. */

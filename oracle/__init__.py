@@ -158,3 +158,70 @@ def evolve(I, phi0, params, iters: int, reg: int = DOUBLE_WELL, real: str = "f64
     if rc != 0:
         raise ValueError(f"oracle_evolve failed ({rc})")
     return phi, hist[: int(iters)]
+
+
+# ---------------------------------------------------------------------------
+# Volume-level parallelism (Sec. 4.1): sub-volumes with curtains, evolved
+# independently, merged by linear interpolation across the curtains.
+# ---------------------------------------------------------------------------
+
+def volume_cores(n: int, block: int):
+    """Core boundaries along one axis: ceil(n / block) near-equal parts."""
+    nb = -(-n // block)
+    return [k * n // nb for k in range(nb + 1)]
+
+
+def axis_weights(n: int, cuts, k: int, curtain: int) -> np.ndarray:
+    """Weight of part k at each coordinate 0..n-1: one inside its core, zero
+    outside its core +- curtain, and across each 2*curtain-wide overlap with
+    a neighbour a linear ramp whose complement is the neighbour's weight."""
+    c = np.arange(n, dtype=np.float64)
+    lo, hi = cuts[k], cuts[k + 1]
+    w = ((c >= lo) & (c < hi)).astype(np.float64)
+    C = float(curtain)
+    if k > 0:                       # overlap [lo - C, lo + C) with part k - 1
+        m = (c >= lo - C) & (c < lo + C)
+        w[m] = (c[m] - (lo - C) + 0.5) / (2.0 * C)
+    if k + 2 < len(cuts):           # overlap [hi - C, hi + C) with part k + 1
+        m = (c >= hi - C) & (c < hi + C)
+        w[m] = ((hi + C) - c[m] - 0.5) / (2.0 * C)
+    return w
+
+
+def volume_boxes(shape, block: int, curtain: int):
+    """[(slices, weight array)] of every sub-volume of a [nz][ny][nx] volume."""
+    per_axis = []
+    for n in shape:
+        cuts = volume_cores(n, block)
+        parts = []
+        for k in range(len(cuts) - 1):
+            lo = max(0, cuts[k] - curtain)
+            hi = min(n, cuts[k + 1] + curtain)
+            parts.append((slice(lo, hi), axis_weights(n, cuts, k, curtain)[lo:hi]))
+        per_axis.append(parts)
+    boxes = []
+    for pz in per_axis[0]:
+        for py in per_axis[1]:
+            for px in per_axis[2]:
+                w = pz[1][:, None, None] * py[1][None, :, None] * px[1][None, None, :]
+                boxes.append(((pz[0], py[0], px[0]), w))
+    return boxes
+
+
+def merge_boxes(shape, boxes, fields) -> np.ndarray:
+    """Sum of weight x field over the sub-volumes (the linear-interpolation
+    merge of Sec. 4.1), in FP64."""
+    out = np.zeros(shape, dtype=np.float64)
+    for (sl, w), f in zip(boxes, fields):
+        out[sl] += w * f
+    return out
+
+
+def evolve_volume(I, phi0, params, iters: int, block: int, curtain: int,
+                  reg: int = DOUBLE_WELL):
+    """Evolve every curtained sub-volume on its own with `evolve`, then merge."""
+    I = _f64(I)
+    phi0 = _f64(phi0)
+    boxes = volume_boxes(phi0.shape, block, curtain)
+    fields = [evolve(I[sl], phi0[sl], params, iters, reg)[0] for sl, _ in boxes]
+    return merge_boxes(phi0.shape, boxes, fields)

@@ -789,6 +789,160 @@ void rsf_autotune_reset(rsf_context *ctx)
     if (ctx) ctx->tuned.clear();
 }
 
+rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                             int64_t nx, int64_t ny, int64_t nz, int64_t block, int64_t curtain,
+                             const rsf_params *params, int iters, size_t budget_bytes, void *stream)
+{
+    std::vector<void *> owned;
+    auto release = [&] {
+        for (void *p : owned) (void)hipFree(p);
+        owned.clear();
+    };
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (!volume || !phi || !params) return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
+        rsf_status st = check_dims(ctx, nx, ny, nz);
+        if (st != RSF_OK) return st;
+        st = check_params(ctx, *params);
+        if (st != RSF_OK) return st;
+        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        if (st != RSF_OK) return st;
+        if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
+        if (block < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "block must be >= 1");
+        if (curtain < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "curtain must be >= 0");
+        const int C = (int)(curtain > 0 ? curtain
+                                         : std::ceil(3.0 * std::max(params->sigma, params->sigma2) -
+                                                     1e-9));
+        // near-equal cores per axis; neighbours overlap by 2C around each core face
+        const int64_t n3[3] = {nx, ny, nz};
+        std::vector<int64_t> cuts[3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t nb = (n3[a] + block - 1) / block;
+            for (int64_t k = 0; k <= nb; ++k) cuts[a].push_back(k * n3[a] / nb);
+            if (nb > 1 && n3[a] / nb < 2 * C)
+                return fail(ctx, RSF_ERR_INVALID_ARG,
+                            "every core must be at least twice the curtain: raise block or lower "
+                            "curtain");
+        }
+        std::vector<rsf::SubBox> boxes;
+        for (size_t kz = 0; kz + 1 < cuts[2].size(); ++kz)
+            for (size_t ky = 0; ky + 1 < cuts[1].size(); ++ky)
+                for (size_t kx = 0; kx + 1 < cuts[0].size(); ++kx) {
+                    rsf::SubBox b{};
+                    const size_t k[3] = {kx, ky, kz};
+                    for (int a = 0; a < 3; ++a) {
+                        const int64_t c0 = cuts[a][k[a]], c1 = cuts[a][k[a] + 1];
+                        const int64_t lo = std::max<int64_t>(0, c0 - C);
+                        const int64_t hi = std::min<int64_t>(n3[a], c1 + C);
+                        b.lo[a] = (int)lo;
+                        b.ext[a] = (int)(hi - lo);
+                        b.core_lo[a] = (int)c0;
+                        b.core_hi[a] = (int)c1;
+                        b.nb_lo[a] = k[a] > 0;
+                        b.nb_hi[a] = k[a] + 2 < cuts[a].size();
+                    }
+                    boxes.push_back(b);
+                }
+        // group the boxes so each group's copies and workspace fit the budget
+        const size_t elem = volume_dtype == RSF_U16 ? 2 : 4;
+        auto box_bytes = [&](const rsf::SubBox &b) {
+            const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
+            const Grid3 g = rsf::host::grid_of(b.ext[0], b.ext[1], b.ext[2]);
+            return align_up(v * elem) + align_up(v * 4) +
+                   rsf::host::tile_regions(g, iters, params->storage).total + 2 * kAlign;
+        };
+        std::vector<std::pair<size_t, size_t>> groups;   // [first, last)
+        size_t first = 0, sum = 0, largest = 0;
+        for (size_t i = 0; i < boxes.size(); ++i) {
+            const size_t bb = box_bytes(boxes[i]);
+            if (budget_bytes && bb > budget_bytes)
+                return fail(ctx, RSF_ERR_BUDGET, "one sub-volume alone exceeds the budget");
+            if (budget_bytes && sum + bb > budget_bytes) {
+                groups.push_back({first, i});
+                first = i;
+                sum = 0;
+            }
+            sum += bb;
+            largest = std::max(largest, sum);
+        }
+        groups.push_back({first, boxes.size()});
+        st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t nvox = nx * ny * nz;
+        float *acc = nullptr;
+        HIP_TRY(hipMalloc(&acc, (size_t)nvox * sizeof(float)), "hipMalloc(merge accumulator)");
+        owned.push_back(acc);
+        // tile copies of the largest group (images then phis)
+        size_t copy_bytes = 0;
+        for (auto &gr : groups) {
+            size_t c = 0;
+            for (size_t i = gr.first; i < gr.second; ++i) {
+                const size_t v = (size_t)boxes[i].ext[0] * boxes[i].ext[1] * boxes[i].ext[2];
+                c += align_up(v * elem) + align_up(v * 4);
+            }
+            copy_bytes = std::max(copy_bytes, c);
+        }
+        char *copies = nullptr;
+        {
+            const hipError_t e = hipMalloc(&copies, copy_bytes);
+            if (e != hipSuccess) {
+                release();
+                return hip_fail(ctx, e, "hipMalloc(sub-volume copies)");
+            }
+            owned.push_back(copies);
+        }
+        auto step = [&](hipError_t e, const char *what) -> rsf_status {
+            if (e == hipSuccess) return RSF_OK;
+            (void)hipStreamSynchronize(s);
+            release();
+            return hip_fail(ctx, e, what);
+        };
+        st = step(rsf::launch_fill(acc, nvox, 0.f, s), "fill");
+        if (st != RSF_OK) return st;
+        for (auto &gr : groups) {
+            std::vector<rsf_tile> tiles;
+            size_t off = 0;
+            for (size_t i = gr.first; i < gr.second; ++i) {
+                const rsf::SubBox &b = boxes[i];
+                const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
+                void *img = copies + off;
+                off += align_up(v * elem);
+                float *ph = reinterpret_cast<float *>(copies + off);
+                off += align_up(v * 4);
+                st = step(rsf::launch_gather(volume, img, (int)elem, nx, ny, b, s), "gather image");
+                if (st == RSF_OK) st = step(rsf::launch_gather(phi, ph, 4, nx, ny, b, s), "gather phi");
+                if (st != RSF_OK) return st;
+                tiles.push_back(rsf_tile{img, ph, b.ext[0], b.ext[1], b.ext[2]});
+            }
+            st = evolve_impl(ctx, tiles.data(), (int)tiles.size(), volume_dtype, *params, iters,
+                             0.0, nullptr, 0, stream);
+            if (st != RSF_OK) {
+                (void)hipStreamSynchronize(s);
+                release();
+                return st;
+            }
+            for (size_t i = gr.first; i < gr.second; ++i) {
+                st = step(rsf::launch_merge(acc, tiles[i - gr.first].phi, nx, ny, boxes[i], C, s),
+                          "merge");
+                if (st != RSF_OK) return st;
+            }
+        }
+        st = step(hipMemcpyAsync(phi, acc, (size_t)nvox * sizeof(float), hipMemcpyDeviceToDevice, s),
+                  "copy merged phi");
+        if (st != RSF_OK) return st;
+        const hipError_t e = hipStreamSynchronize(s);
+        release();
+        ctx->has_last = false;   // per-tile statistics of the groups are not kept
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+        return RSF_OK;
+    } catch (...) {
+        release();
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
 rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx, int64_t ny,
                        int64_t nz, float sigma, void *stream)
 {

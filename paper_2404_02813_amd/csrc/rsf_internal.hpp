@@ -157,6 +157,22 @@ hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s);
 // Copy an odd final iterate from phi[1] to phi[0] (workgroups of the z pass).
 hipError_t launch_finish(const Batch &b, int64_t blocks, hipStream_t s);
 
+// Volume-level driver (Sec. 4.1): one sub-volume box of a large volume.
+struct SubBox {
+    int lo[3], ext[3];              // x, y, z origin and extent in the volume
+    int core_lo[3], core_hi[3];     // its core (the part it owns outright)
+    int nb_lo[3], nb_hi[3];         // 1 when a neighbour shares the face
+};
+// Copy box `b` of the volume (elements of elem_bytes, 2 or 4) into a dense
+// tile buffer.
+hipError_t launch_gather(const void *src, void *dst, int elem_bytes, int64_t nx, int64_t ny,
+                         const SubBox &b, hipStream_t s);
+// acc += w * tile over box b, w the product of per-axis linear ramps across
+// the 2C-wide overlaps with the box's neighbours (the curtain).
+hipError_t launch_merge(float *acc, const float *tile, int64_t nx, int64_t ny, const SubBox &b,
+                        int curtain, hipStream_t s);
+hipError_t launch_fill(float *dst, int64_t n, float v, hipStream_t s);
+
 // Per-radius, per-type launchers behind the dispatchers (rsf_kernels.hpp).
 template <int R, class IT, class ST>
 hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,

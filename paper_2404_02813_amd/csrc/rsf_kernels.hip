@@ -97,11 +97,106 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(Batch bt)
     for (int z = zt.z0; z < zt.z1; ++z) (dst + (int64_t)z * g.sxy)[col] = (src + (int64_t)z * g.sxy)[col];
 }
 
+// ---------------------------------------------------------------------------
+// Volume-level driver: gather a sub-volume, merge it back (Sec. 4.1)
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void gather_kernel(const T *src, T *dst, int64_t nx,
+                                                          int64_t ny, SubBox b)
+{
+    const int64_t n = (int64_t)b.ext[0] * b.ext[1] * b.ext[2];
+    const gptr<const T> s = glb(src);
+    const gptr<T> d = glb(dst);
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int64_t x = i % b.ext[0], yz = i / b.ext[0];
+        const int64_t y = yz % b.ext[1], z = yz / b.ext[1];
+        d[i] = s[((z + b.lo[2]) * ny + (y + b.lo[1])) * nx + (x + b.lo[0])];
+    }
+}
+
+// Weight of a box at volume coordinate c along one axis: 1 inside its core,
+// a linear ramp across the 2C voxels straddling each core face it shares
+// with a neighbour (the neighbour's ramp is its complement, so the weights
+// of all boxes sum to one).
+__device__ __forceinline__ float ramp(int c, int core_lo, int core_hi, int nb_lo, int nb_hi, int C)
+{
+    const float inv = 1.f / (2.f * (float)C);
+    if (nb_lo && c < core_lo + C) return ((float)(c - (core_lo - C)) + 0.5f) * inv;
+    if (nb_hi && c >= core_hi - C) return ((float)((core_hi + C) - c) - 0.5f) * inv;
+    return 1.f;
+}
+
+__global__ __launch_bounds__(kThreads) void merge_kernel(float *acc, const float *tile, int64_t nx,
+                                                         int64_t ny, SubBox b, int C)
+{
+    const int64_t n = (int64_t)b.ext[0] * b.ext[1] * b.ext[2];
+    const gptr<float> a = glb(acc);
+    const gptr<const float> t = glb(tile);
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int x = (int)(i % b.ext[0]);
+        const int64_t yz = i / b.ext[0];
+        const int y = (int)(yz % b.ext[1]), z = (int)(yz / b.ext[1]);
+        const int gx = x + b.lo[0], gy = y + b.lo[1], gz = z + b.lo[2];
+        const float w = ramp(gx, b.core_lo[0], b.core_hi[0], b.nb_lo[0], b.nb_hi[0], C) *
+                        ramp(gy, b.core_lo[1], b.core_hi[1], b.nb_lo[1], b.nb_hi[1], C) *
+                        ramp(gz, b.core_lo[2], b.core_hi[2], b.nb_lo[2], b.nb_hi[2], C);
+        a[((int64_t)gz * ny + gy) * nx + gx] += w * t[i];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void fill_kernel(float *dst, int64_t n, float v)
+{
+    const gptr<float> d = glb(dst);
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        d[i] = v;
+}
+
+unsigned stride_grid(int64_t n)
+{
+    const int64_t g = (n + kThreads - 1) / kThreads;
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_gather(const void *src, void *dst, int elem_bytes, int64_t nx, int64_t ny,
+                         const SubBox &b, hipStream_t s)
+{
+    const int64_t n = (int64_t)b.ext[0] * b.ext[1] * b.ext[2];
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(gather_kernel<float>, dim3(stride_grid(n)), dim3(kThreads), 0, s,
+                           static_cast<const float *>(src), static_cast<float *>(dst), nx, ny, b);
+    else if (elem_bytes == 2)
+        hipLaunchKernelGGL(gather_kernel<uint16_t>, dim3(stride_grid(n)), dim3(kThreads), 0, s,
+                           static_cast<const uint16_t *>(src), static_cast<uint16_t *>(dst), nx, ny,
+                           b);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(float *acc, const float *tile, int64_t nx, int64_t ny, const SubBox &b,
+                        int curtain, hipStream_t s)
+{
+    const int64_t n = (int64_t)b.ext[0] * b.ext[1] * b.ext[2];
+    hipLaunchKernelGGL(merge_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, acc, tile, nx, ny,
+                       b, curtain);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *dst, int64_t n, float v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, dst, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s)
 {

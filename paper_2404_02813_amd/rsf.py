@@ -39,7 +39,7 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
            "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
-           "rsf_set_split_targets",
+           "rsf_set_split_targets", "rsf_evolve_volume",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
@@ -157,6 +157,9 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
                                ctypes.POINTER(ctypes.c_int64), vp]
     L.rsf_autotune.restype = i
+    L.rsf_evolve_volume.argtypes = [vp, vp, i, vp, i64, i64, i64, i64, i64,
+                                    ctypes.POINTER(rsf_params), i, ctypes.c_size_t, vp]
+    L.rsf_evolve_volume.restype = i
     L.rsf_set_split_targets.argtypes = [vp, i64, i64, i64]
     L.rsf_set_split_targets.restype = i
     L.rsf_autotune_reset.argtypes = [vp]
@@ -327,6 +330,22 @@ def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
     return tuple(chosen)
 
 
+def rsf_evolve_volume(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
+                      iters: int, block: int, curtain: int = 0, budget_bytes: int = 0,
+                      stream=None) -> None:
+    """Sub-volumes with curtains, evolved independently, merged by linear
+    interpolation (phi in place)."""
+    _field(volume, "volume", "image")
+    _field(phi, "phi")
+    if volume.shape != phi.shape:
+        raise ValueError("volume and phi must have the same shape")
+    nz, ny, nx = phi.shape
+    _check(ctx, lib().rsf_evolve_volume(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                        phi.data_ptr(), nx, ny, nz, int(block), int(curtain),
+                                        ctypes.byref(params), int(iters), int(budget_bytes),
+                                        _stream(stream)))
+
+
 def rsf_set_split_targets(ctx, xy_waves: int = 0, z_blocks: int = 0, u_blocks: int = 0) -> None:
     _check(ctx, lib().rsf_set_split_targets(ctx, int(xy_waves), int(z_blocks), int(u_blocks)))
 
@@ -434,6 +453,11 @@ class Context:
 
     def autotune(self, volumes, phis, params, trial_iters=3, stream=None):
         return rsf_autotune(self.handle, volumes, phis, params, trial_iters, stream)
+
+    def evolve_volume(self, volume, phi, params, iters, block, curtain=0, budget_bytes=0,
+                      stream=None):
+        rsf_evolve_volume(self.handle, volume, phi, params, iters, block, curtain, budget_bytes,
+                          stream)
 
     def set_split_targets(self, xy_waves=0, z_blocks=0, u_blocks=0):
         rsf_set_split_targets(self.handle, xy_waves, z_blocks, u_blocks)
