@@ -88,7 +88,10 @@ typedef enum {
  *       F+- = K2*I^2 - 2 r+- K2*I + r+-^2 with K2 the Gaussian of scale
  *       sigma2, and lambda1 F+ - lambda2 F-.  With sigma2 = 0 (every 3D run
  *       of the paper, Sec. 5) K2 is the identity and F+- = (I - r+-)^2: one
- *       Gaussian stage per iteration.  r+ = f1, r- = f2. */
+ *       Gaussian stage per iteration.  With sigma2 > 0, K2*I and K2*I^2 are
+ *       computed once per evolution and need two more workspace fields
+ *       (size the workspace with rsf_workspace_bytes_params).  r+ = f1,
+ *       r- = f2. */
 typedef enum {
     RSF_FORCE_RSF = 0,
     RSF_FORCE_PAPER = 1
@@ -108,8 +111,10 @@ typedef struct {
     int regulariser;  /* rsf_regulariser                                      */
     int storage;      /* rsf_dtype of the intermediate fields (F32/F16/BF16)  */
     int force;        /* rsf_force                                            */
-    float sigma2;     /* scale of the force kernel for RSF_FORCE_PAPER; only
-                         0 (the value of the paper's 3D runs) is built        */
+    float sigma2;     /* scale of the force kernel for RSF_FORCE_PAPER (0 =
+                         the identity, the value of the paper's 3D runs);
+                         ceil(3 sigma2) <= 16, and 4..12 for the FP16/BF16/
+                         uint16 type combinations                            */
 } rsf_params;
 
 /* Results of the last evolution on a context. */
@@ -170,6 +175,14 @@ typedef struct {
 
 /* Bytes of device workspace rsf_evolve_batch needs for these tiles. */
 size_t rsf_batch_workspace_bytes(const rsf_tile *tiles, int n_tiles, int iters, int storage);
+
+/* As rsf_workspace_bytes / rsf_batch_workspace_bytes, but for the full
+ * parameter set: counts the two extra fields the Sec. 4.2 force needs when
+ * sigma2 > 0.  0 for invalid parameters or dims. */
+size_t rsf_workspace_bytes_params(int64_t nx, int64_t ny, int64_t nz, int iters,
+                                  const rsf_params *params);
+size_t rsf_batch_workspace_bytes_params(const rsf_tile *tiles, int n_tiles, int iters,
+                                        const rsf_params *params);
 
 /* Evolve every tile of a batch by `iters` iterations with shared parameters
  * (the sub-volume parallelism of Sec. 4.1: tiles are independent problems,
@@ -289,7 +302,7 @@ rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out);
  * curtain (halo) sized by the Gaussian scale (Sec. 4.1, volume level
  * parallelism).  A server evolves such tiles as requests arrive: a worker
  * thread admits requests in arrival order while the sum of the admitted
- * requests' workspaces (rsf_workspace_bytes) stays within the HBM budget and
+ * requests' workspaces (rsf_workspace_bytes_params) stays within the HBM budget and
  * a resident slot is free, then advances every resident tile by up to
  * `chunk_iters` iterations per scheduling chunk.  Tiles with equal
  * parameters, image type and storage type (in particular equal sigma) share

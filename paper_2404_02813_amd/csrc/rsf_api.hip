@@ -83,7 +83,7 @@ struct BatchLayout {
 };
 
 BatchLayout plan_layout(const rsf_tile *tiles, int n, int iters, int storage,
-                        const std::vector<Split> &splits)
+                        const std::vector<Split> &splits, bool k2 = false)
 {
     BatchLayout L;
     size_t off = 0;
@@ -100,7 +100,7 @@ BatchLayout plan_layout(const rsf_tile *tiles, int n, int iters, int storage,
         T.g = rsf::host::grid_of(tiles[t].nx, tiles[t].ny, tiles[t].nz);
         T.sp = splits[t];
         T.base = off;
-        T.T = rsf::host::tile_regions(T.g, iters, storage);
+        T.T = rsf::host::tile_regions(T.g, iters, storage, k2);
         off += T.T.total;
         L.pre_xy.push_back(L.pre_xy.back() + (int)rsf::xy_blocks(T.g, T.sp));
         L.pre_z.push_back(L.pre_z.back() + (int)rsf::z_blocks(T.g, T.sp));
@@ -170,9 +170,9 @@ rsf_status check_params(rsf_context *ctx, const rsf_params &p)
     return check(ctx, rsf::host::params_error(p));
 }
 
-rsf_status check_types(rsf_context *ctx, float sigma, int image, int storage)
+rsf_status check_types(rsf_context *ctx, const rsf_params &p, int image)
 {
-    return check(ctx, rsf::host::types_error(sigma, image, storage));
+    return check(ctx, rsf::host::types_error(p, image));
 }
 
 rsf_status check_tiles(rsf_context *ctx, const rsf_tile *tiles, int n, bool need_pointers)
@@ -243,6 +243,9 @@ struct Plan {
     TileDesc *descs;             // device
     Batch xy, z, u, tile;
     int64_t blocks_xy, blocks_z, blocks_u;   // grid sizes
+    bool k2;             // K2*I and K2*I^2 for the Sec. 4.2 force with sigma2 > 0
+    int R2;
+    Taps taps2;
 };
 
 Grid3 grid_of(const rsf_tile &t) { return rsf::host::grid_of(t.nx, t.ny, t.nz); }
@@ -287,7 +290,10 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.storage = p.storage;
     P.taps = make_taps(p.sigma, P.R);
     P.c = make_coeffs(p, tol);
-    P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R));
+    P.k2 = rsf::host::needs_k2(p);
+    P.R2 = P.k2 ? radius_of(p.sigma2) : 0;
+    if (P.k2) P.taps2 = make_taps(p.sigma2, P.R2);
+    P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R), P.k2);
     P.base = base;
     rsf_status st = ensure_stage(ctx, P.L.table_bytes);
     if (st != RSF_OK) return st;
@@ -333,16 +339,29 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     return RSF_OK;
 }
 
-// Per-batch set-up: K*1 edge tables, flags, and K*I.
+// Per-batch set-up: K*1 edge tables, flags, K*I, and for the Sec. 4.2 force
+// with sigma2 > 0 also K2*I and K2*I^2 (each an xy pass into P, then a z pass).
 rsf_status prologue(rsf_context *ctx, const Plan &P, hipStream_t s)
 {
     HIP_TRY(timed(ctx, RSF_PASS_SETUP, s, [&] {
                 hipError_t e = rsf::launch_setup(P.tile, P.taps, P.R, s);
+                if (P.k2) {
+                    Coeffs sq = P.c;
+                    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+                        sq.square = k;
+                        e = rsf::launch_xy(P.R2, rsf::XY_ONE, P.image, P.storage, P.xy,
+                                           P.blocks_xy, P.taps2, sq, false, s);
+                        if (e == hipSuccess)
+                            e = rsf::launch_z_plain(P.R2, P.storage, P.z, P.blocks_z, P.taps2,
+                                                    k ? rsf::Z_TO_K2I2 : rsf::Z_TO_K2I, s);
+                    }
+                }
                 if (e == hipSuccess)
                     e = rsf::launch_xy(P.R, rsf::XY_ONE, P.image, P.storage, P.xy, P.blocks_xy,
                                        P.taps, P.c, false, s);
                 if (e == hipSuccess)
-                    e = rsf::launch_z_plain(P.R, P.storage, P.z, P.blocks_z, P.taps, s);
+                    e = rsf::launch_z_plain(P.R, P.storage, P.z, P.blocks_z, P.taps, rsf::Z_TO_KI,
+                                            s);
                 return e;
             }),
             "setup (K*1 tables, K*I)");
@@ -360,7 +379,10 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
             "z(H)");
     const bool paper = P.c.force == RSF_FORCE_PAPER;
     HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
-                return rsf::launch_xy(P.R, paper ? rsf::XY_PAPER : rsf::XY_FITS, P.image,
+                return rsf::launch_xy(P.R,
+                                      paper ? (P.k2 ? rsf::XY_PAPER2 : rsf::XY_PAPER)
+                                            : rsf::XY_FITS,
+                                      P.image,
                                       P.storage, P.xy, P.blocks_xy, P.taps, P.c, probe, s);
             }),
             "xy(fits)");
@@ -393,16 +415,17 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     if (st != RSF_OK) return st;
     st = check_params(ctx, p);
     if (st != RSF_OK) return st;
-    st = check_types(ctx, p.sigma, vdt, p.storage);
+    st = check_types(ctx, p, vdt);
     if (st != RSF_OK) return st;
     if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
     if (!(tol >= 0.0) || !std::isfinite(tol))
         return fail(ctx, RSF_ERR_INVALID_ARG, "tol must be >= 0");
     st = set_device(ctx);
     if (st != RSF_OK) return st;
-    const size_t need =
-        plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, radius_of(p.sigma)))
-            .total;
+    const size_t need = plan_layout(tiles, n, iters, p.storage,
+                                    splits_for(ctx, tiles, n, radius_of(p.sigma)),
+                                    rsf::host::needs_k2(p))
+                            .total;
     if (workspace && ws_bytes < need) return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
         return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -596,6 +619,30 @@ size_t rsf_workspace_bytes(int64_t nx, int64_t ny, int64_t nz, int iters, int st
     return rsf_batch_workspace_bytes(&t, 1, iters, storage);
 }
 
+size_t rsf_batch_workspace_bytes_params(const rsf_tile *tiles, int n, int iters,
+                                        const rsf_params *params)
+{
+    try {
+        if (!tiles || n < 1 || iters < 0 || !params) return 0;
+        if (rsf::host::params_error(*params)) return 0;
+        for (int t = 0; t < n; ++t)
+            if (tiles[t].nx < 3 || tiles[t].ny < 3 || tiles[t].nz < 3) return 0;
+        return plan_layout(tiles, n, iters, params->storage, splits_for(nullptr, tiles, n, 0),
+                           rsf::host::needs_k2(*params))
+            .total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+size_t rsf_workspace_bytes_params(int64_t nx, int64_t ny, int64_t nz, int iters,
+                                  const rsf_params *params)
+{
+    rsf_tile t{};
+    t.nx = nx; t.ny = ny; t.nz = nz;
+    return rsf_batch_workspace_bytes_params(&t, 1, iters, params);
+}
+
 rsf_status rsf_evolve(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
                       int64_t nx, int64_t ny, int64_t nz, float sigma, float lambda1,
                       float lambda2, float nu, float mu, float dt, float eps, int iters,
@@ -688,7 +735,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
         if (st != RSF_OK) return st;
         st = check_params(ctx, *params);
         if (st != RSF_OK) return st;
-        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        st = check_types(ctx, *params, volume_dtype);
         if (st != RSF_OK) return st;
         if (trial_iters < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "trial_iters must be >= 1");
         st = set_device(ctx);
@@ -744,7 +791,8 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 const int runs = trial_iters + 1;
                 const size_t need =
                     plan_layout(tt.data(), n_tiles, runs, params->storage,
-                                splits_for(ctx, tt.data(), n_tiles, R)).total;
+                                splits_for(ctx, tt.data(), n_tiles, R),
+                                rsf::host::needs_k2(*params)).total;
                 st = ensure_ws(ctx, need);
                 if (st != RSF_OK) break;
                 ctx->has_last = false;   // the trials overwrite the workspace
@@ -806,7 +854,7 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
         if (st != RSF_OK) return st;
         st = check_params(ctx, *params);
         if (st != RSF_OK) return st;
-        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        st = check_types(ctx, *params, volume_dtype);
         if (st != RSF_OK) return st;
         if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
         if (block < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "block must be >= 1");
@@ -850,7 +898,9 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
             const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
             const Grid3 g = rsf::host::grid_of(b.ext[0], b.ext[1], b.ext[2]);
             return align_up(v * elem) + align_up(v * 4) +
-                   rsf::host::tile_regions(g, iters, params->storage).total + 2 * kAlign;
+                   rsf::host::tile_regions(g, iters, params->storage, rsf::host::needs_k2(*params))
+                       .total +
+                   2 * kAlign;
         };
         std::vector<std::pair<size_t, size_t>> groups;   // [first, last)
         size_t first = 0, sum = 0, largest = 0;
@@ -987,14 +1037,15 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
         if (st != RSF_OK) return st;
         st = check_params(ctx, *params);
         if (st != RSF_OK) return st;
-        st = check_types(ctx, params->sigma, volume_dtype, params->storage);
+        st = check_types(ctx, *params, volume_dtype);
         if (st != RSF_OK) return st;
         st = set_device(ctx);
         if (st != RSF_OK) return st;
         // phi is only read: the update writes into phi_next (or the workspace)
         rsf_tile t{volume, const_cast<float *>(phi), nx, ny, nz};
         st = ensure_ws(ctx, plan_layout(&t, 1, 1, params->storage,
-                                        splits_for(ctx, &t, 1, radius_of(params->sigma)))
+                                        splits_for(ctx, &t, 1, radius_of(params->sigma)),
+                                        rsf::host::needs_k2(*params))
                                 .total);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);

@@ -81,16 +81,27 @@ inline const char *params_error(const rsf_params &p)
         return "storage must be RSF_F32, RSF_F16 or RSF_BF16";
     if (p.force != RSF_FORCE_RSF && p.force != RSF_FORCE_PAPER) return "unknown force";
     if (!fin(p.sigma2) || p.sigma2 < 0.f) return "sigma2 must be finite and >= 0";
-    if (p.force == RSF_FORCE_PAPER && p.sigma2 != 0.f)
-        return "RSF_FORCE_PAPER is built for sigma2 = 0 only";
+    if (p.force == RSF_FORCE_PAPER && radius_of(p.sigma2) > kMaxR)
+        return "sigma2 must have ceil(3 sigma2) <= 16";
     return nullptr;
 }
+
+// The Sec. 4.2 force with sigma2 > 0 needs K2*I and K2*I^2.
+inline bool needs_k2(const rsf_params &p) { return p.force == RSF_FORCE_PAPER && p.sigma2 > 0.f; }
 
 inline const char *types_error(float sigma, int image, int storage)
 {
     if (image != RSF_F32 && image != RSF_U16) return "volume dtype must be RSF_F32 or RSF_U16";
     if (!types_supported(radius_of(sigma), image, storage))
         return "this image/storage combination is built for ceil(3 sigma) in 4..12 only";
+    return nullptr;
+}
+
+inline const char *types_error(const rsf_params &p, int image)
+{
+    if (const char *w = types_error(p.sigma, image, p.storage)) return w;
+    if (needs_k2(p) && !types_supported(radius_of(p.sigma2), image, p.storage))
+        return "this image/storage combination is built for ceil(3 sigma2) in 4..12 only";
     return nullptr;
 }
 
@@ -104,17 +115,24 @@ inline Grid3 grid_of(int64_t nx, int64_t ny, int64_t nz)
 // for any valid split), the per-iteration history and the flags.  Offsets are
 // relative to the region's start; `total` is its size.
 struct TileRegions {
-    size_t P, Q, KI, phiB, cx, cy, cz, partials, hist, flags, total;
+    size_t P, Q, KI, K2I, K2I2, phiB, cx, cy, cz, partials, hist, flags, total;
+    bool k2;
 };
 
-inline TileRegions tile_regions(const Grid3 &g, int iters, int storage)
+// k2: also K2*I and K2*I^2 (the Sec. 4.2 force with sigma2 > 0).
+inline TileRegions tile_regions(const Grid3 &g, int iters, int storage, bool k2 = false)
 {
     TileRegions T{};
     const size_t v = (size_t)g.nx * g.ny * g.nz;
     size_t off = 0;
+    T.k2 = k2;
     T.P = off; off += align_up(2 * v * elem_size(storage));
     T.Q = off; off += align_up(2 * v * elem_size(storage));
     T.KI = off; off += align_up(v * elem_size(storage));
+    if (k2) {
+        T.K2I = off; off += align_up(v * elem_size(storage));
+        T.K2I2 = off; off += align_up(v * elem_size(storage));
+    }
     T.phiB = off; off += align_up(v * sizeof(float));
     T.cx = off; off += align_up((size_t)g.nx * sizeof(float));
     T.cy = off; off += align_up((size_t)g.ny * sizeof(float));
@@ -140,6 +158,8 @@ inline TileDesc tile_desc(const Grid3 &g, const Split &sp, const void *volume, f
     d.P = base + T.P;
     d.Q = base + T.Q;
     d.KI = base + T.KI;
+    d.K2I = T.k2 ? base + T.K2I : nullptr;
+    d.K2I2 = T.k2 ? base + T.K2I2 : nullptr;
     d.cx = reinterpret_cast<float *>(base + T.cx);
     d.cy = reinterpret_cast<float *>(base + T.cy);
     d.cz = reinterpret_cast<float *>(base + T.cz);

@@ -50,6 +50,7 @@ struct TileDesc {
     float *phi[2];          // phi ping-pong: [0] the caller's buffer, [1] workspace
     void *P, *Q;            // interleaved pair fields, storage type
     void *KI;               // K * I, storage type
+    void *K2I, *K2I2;       // K2 * I and K2 * I^2 (Sec. 4.2 force, sigma2 > 0), storage type
     float *cx, *cy, *cz;    // K * 1 = cx[x] cy[y] cz[z]
     double *partials;       // one sum |dphi| per update-pass block
     double *hist;           // sum |dphi| per iteration run
@@ -66,7 +67,8 @@ struct Coeffs {
     float eps, eps_over_pi, eps2;   // delta = eps_over_pi / (eps2 + phi^2)
     float eta;
     int reg;                        // 0 double well, 1 single well
-    int force;                      // 0 RSF e_i (sigma), 1 Sec. 4.2 form with sigma2 = 0
+    int force;                      // 0 RSF e_i (sigma), 1 Sec. 4.2 form (sigma2)
+    int square;                     // XY_ONE: convolve I^2 instead of I
     double tol;                     // stop a tile once sum|dphi| / voxels < tol (0: never)
 };
 
@@ -126,11 +128,14 @@ bool split_valid(const Grid3 &g, const Split &s);
 
 bool types_supported(int R, int image_dtype, int storage_dtype);
 
-// xy pass modes: XY_ONE reads the image and writes one field (P), for K*I;
-// XY_FITS reads the pair P and K*I and writes the pair Q; XY_TWO reads the
-// pair Q and writes the pair P; XY_PAPER reads the pair P, K*I and the image
-// and writes the Sec. 4.2 force (sigma2 = 0) to Q as float.
-enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2, XY_PAPER = 3 };
+// xy pass modes: XY_ONE reads the image (or its square) and writes one field
+// (P), for K*I; XY_FITS reads the pair P and K*I and writes the pair Q;
+// XY_TWO reads the pair Q and writes the pair P; XY_PAPER reads the pair P,
+// K*I and the image and writes the Sec. 4.2 force with sigma2 = 0 to Q as
+// float; XY_PAPER2 reads K2*I and K2*I^2 in place of the image (sigma2 > 0).
+enum XyMode { XY_ONE = 0, XY_TWO = 1, XY_FITS = 2, XY_PAPER = 3, XY_PAPER2 = 4 };
+// Where the plain z pass writes: K*I, K2*I or K2*I^2.
+enum ZTarget { Z_TO_KI = 0, Z_TO_K2I = 1, Z_TO_K2I2 = 2 };
 
 // One workgroup per tile: K*1 edge tables, flags cleared.
 hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s);
@@ -138,7 +143,7 @@ hipError_t launch_xy(int R, int mode, int image_dtype, int storage_dtype, const 
                      int64_t blocks, const Taps &t, const Coeffs &c, bool probe, hipStream_t s);
 // K*I: the z pass of P into KI.
 hipError_t launch_z_plain(int R, int storage_dtype, const Batch &b, int64_t blocks,
-                          const Taps &t, hipStream_t s);
+                          const Taps &t, int target, hipStream_t s);
 // Stage-1 z pass: (phi, I) -> the pair P = (Kz*(H I), Kz*H).
 hipError_t launch_z_heaviside(int R, int image_dtype, int storage_dtype, const Batch &b,
                               int64_t blocks, const Taps &t, const Coeffs &c, bool probe,
@@ -178,7 +183,8 @@ template <int R, class IT, class ST>
 hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
                        bool probe, hipStream_t s);
 template <int R, class ST>
-hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, hipStream_t s);
+hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, int target,
+                            hipStream_t s);
 template <int R, class IT, class ST>
 hipError_t launch_z_heaviside_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
                                 bool probe, hipStream_t s);

@@ -263,11 +263,11 @@ hipError_t launch_xy(int R, int mode, int it, int st, const Batch &b, int64_t bl
 }
 
 hipError_t launch_z_plain(int R, int st, const Batch &b, int64_t blocks, const Taps &t,
-                          hipStream_t s)
+                          int target, hipStream_t s)
 {
     const int it = F32;   // the plain z pass only touches the storage type
 #define C(RR, IT, ST) \
-    case RR: return launch_z_plain_r<RR, ST>(b, blocks, t, s);
+    case RR: return launch_z_plain_r<RR, ST>(b, blocks, t, target, s);
     RSF_DISPATCH(C)
 #undef C
 }

@@ -26,7 +26,8 @@ namespace {
 template <int R, int MODE, class IN, class ST, class IMG = float>
 __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
 {
-    constexpr bool FITS = MODE == XY_FITS || MODE == XY_PAPER;
+    constexpr bool PAPER_F = MODE == XY_PAPER || MODE == XY_PAPER2;
+    constexpr bool FITS = MODE == XY_FITS || PAPER_F;
     constexpr int NF = MODE == XY_ONE ? 1 : 2;
     constexpr int W = 2 * R + 1;
     constexpr int RW = 64 + 2 * R;
@@ -88,7 +89,8 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                     row[slot][0][j] = to_f(r.p[h].x);
                     row[slot][NF - 1][j] = to_f(r.p[h].y);
                 } else {
-                    row[slot][0][j] = to_f(r.s[h]);
+                    const float v = to_f(r.s[h]);
+                    row[slot][0][j] = c.square ? v * v : v;
                 }
             }
         }
@@ -119,10 +121,14 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     const int xc = min(x, g.nx - 1);
     const gptr<const ST> ki_slice = glb(static_cast<const ST *>(d.KI)) + zb;
     const gptr<const IMG> im_slice = glb(static_cast<const IMG *>(d.I)) + zb;
+    const gptr<const ST> k2i_slice = glb(static_cast<const ST *>(d.K2I)) + zb;
+    const gptr<const ST> k2q_slice = glb(static_cast<const ST *>(d.K2I2)) + zb;
     const gptr<const float> cyp = glb(d.cy);
     if (FITS) cxz = glb(d.cx)[xc] * glb(d.cz)[z];
     ST ki_next = FITS ? ki_slice[y0 * g.nx + xc] : ST{};
     IMG im_next = MODE == XY_PAPER ? im_slice[y0 * g.nx + xc] : IMG{};
+    ST k2i_next = MODE == XY_PAPER2 ? k2i_slice[y0 * g.nx + xc] : ST{};
+    ST k2q_next = MODE == XY_PAPER2 ? k2q_slice[y0 * g.nx + xc] : ST{};
     float cy_next = FITS ? cyp[y0] : 0.f;
     const gptr<float> probe_f1 = glb(d.probe_f1), probe_f2 = glb(d.probe_f2),
                       probe_fd = glb(d.probe_Fd);
@@ -137,16 +143,22 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                 const Raw cur = nxt;
                 nxt = fetch(y + R + 1);
                 float ki = 0.f, cyv = 0.f, im = 0.f;
-                ST ki_raw = ST{};
+                ST ki_raw = ST{}, k2i_raw = ST{}, k2q_raw = ST{};
                 IMG im_raw = IMG{};
                 if (FITS) {
                     ki_raw = ki_next;
                     cyv = cy_next;
                     im_raw = im_next;
+                    k2i_raw = k2i_next;
+                    k2q_raw = k2q_next;
                     if (y + 1 < y1) {
                         ki_next = ki_slice[(y + 1) * g.nx + xc];
                         cy_next = cyp[y + 1];
                         if (MODE == XY_PAPER) im_next = im_slice[(y + 1) * g.nx + xc];
+                        if (MODE == XY_PAPER2) {
+                            k2i_next = k2i_slice[(y + 1) * g.nx + xc];
+                            k2q_next = k2q_slice[(y + 1) * g.nx + xc];
+                        }
                     }
                 }
                 // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
@@ -174,6 +186,14 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
                             // F+- = (I - r+-)^2 (Sec. 4.2 expansion, sigma2 = 0)
                             const float d1 = im - f1, d2 = im - f2;
                             const float Fd = c.l1 * d1 * d1 - c.l2 * d2 * d2;
+                            of_s[v] = Fd;
+                            if (probe_fd) probe_fd[zb + v] = Fd;
+                        } else if (MODE == XY_PAPER2) {
+                            // F+- = K2*I^2 - 2 r+- K2*I + r+-^2 (Sec. 4.2 expansion)
+                            const float a = to_f(k2i_raw), q = to_f(k2q_raw);
+                            const float F1 = q - 2.f * f1 * a + f1 * f1;
+                            const float F2 = q - 2.f * f2 * a + f2 * f2;
+                            const float Fd = c.l1 * F1 - c.l2 * F2;
                             of_s[v] = Fd;
                             if (probe_fd) probe_fd[zb + v] = Fd;
                         } else {
@@ -265,14 +285,15 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
 
 // K*I: z pass of the field P into KI.
 template <int R, class ST>
-__global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t)
+__global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t, int target)
 {
     Where wh;
     if (!locate(bt, wh)) return;
     const TileDesc &d = bt.tiles[wh.t];
     const Grid3 g = d.g;
     const gptr<const ST> in = glb(static_cast<const ST *>(d.P));
-    const gptr<ST> out = glb(static_cast<ST *>(d.KI));
+    const gptr<ST> out = glb(static_cast<ST *>(
+        target == Z_TO_KI ? d.KI : (target == Z_TO_K2I ? d.K2I : d.K2I2)));
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
     const int col = zt.col;   // nx * ny < 2^31 - 1024
@@ -605,6 +626,9 @@ hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, 
     case XY_PAPER:
         hipLaunchKernelGGL((xy_kernel<R, XY_PAPER, ST, ST, IT>), grid, dim3(64), 0, s, b, t, c);
         break;
+    case XY_PAPER2:
+        hipLaunchKernelGGL((xy_kernel<R, XY_PAPER2, ST, ST, IT>), grid, dim3(64), 0, s, b, t, c);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -612,9 +636,11 @@ hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, 
 }
 
 template <int R, class ST>
-hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, hipStream_t s)
+hipError_t launch_z_plain_r(const Batch &b, int64_t blocks, const Taps &t, int target,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL((z_plain_kernel<R, ST>), dim3((unsigned)blocks), dim3(kThreads), 0, s, b, t);
+    hipLaunchKernelGGL((z_plain_kernel<R, ST>), dim3((unsigned)blocks), dim3(kThreads), 0, s, b, t,
+                       target);
     return hipGetLastError();
 }
 
@@ -670,7 +696,7 @@ hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs 
 #define RSF_INSTANTIATE(RR, IT, ST)                                                           \
     template hipError_t launch_xy_r<RR, IT, ST>(int, const Batch &, int64_t, const Taps &,    \
                                                 const Coeffs &, bool, hipStream_t);           \
-    template hipError_t launch_z_plain_r<RR, ST>(const Batch &, int64_t, const Taps &,        \
+    template hipError_t launch_z_plain_r<RR, ST>(const Batch &, int64_t, const Taps &, int,   \
                                                  hipStream_t);                                \
     template hipError_t launch_z_heaviside_r<RR, IT, ST>(const Batch &, int64_t, const Taps &, \
                                                          const Coeffs &, bool, hipStream_t);  \

@@ -328,6 +328,9 @@ bool launch_chunk(rsf_server *s, std::string &why)
         const Tile *proto;
         int R, image, storage;
         Taps taps;
+        bool k2;
+        int R2;
+        Taps taps2;
         Coeffs c;
         int iters;
         View run_xy, run_z, run_u, run_tile, new_xy, new_z, new_tile, fin_z;
@@ -394,6 +397,9 @@ bool launch_chunk(rsf_server *s, std::string &why)
         L.image = proto->req.volume_dtype;
         L.storage = proto->req.params.storage;
         L.taps = make_taps(proto->req.params.sigma, L.R);
+        L.k2 = needs_k2(proto->req.params);
+        L.R2 = L.k2 ? radius_of(proto->req.params.sigma2) : 0;
+        if (L.k2) L.taps2 = make_taps(proto->req.params.sigma2, L.R2);
         L.c = make_coeffs(proto->req.params, proto->req.tol);
         L.iters = iters;
         L.n_run = (int)run.size();
@@ -459,11 +465,25 @@ bool launch_chunk(rsf_server *s, std::string &why)
         hipStream_t st = nstreams > 1 ? s->gstream[gi % kGroupStreams] : s->stream;
         if (L.n_new > 0) {
             if (!ok(rsf::launch_setup(L.new_tile.b, L.taps, L.R, st), "set-up")) return false;
+            if (L.k2) {
+                Coeffs sq = L.c;
+                for (int k = 0; k < 2; ++k) {
+                    sq.square = k;
+                    if (!ok(rsf::launch_xy(L.R2, rsf::XY_ONE, L.image, L.storage, L.new_xy.b,
+                                           L.new_xy.blocks, L.taps2, sq, false, st),
+                            "K2*I (xy)") ||
+                        !ok(rsf::launch_z_plain(L.R2, L.storage, L.new_z.b, L.new_z.blocks,
+                                                L.taps2, k ? rsf::Z_TO_K2I2 : rsf::Z_TO_K2I, st),
+                            "K2*I (z)"))
+                        return false;
+                }
+            }
             if (!ok(rsf::launch_xy(L.R, rsf::XY_ONE, L.image, L.storage, L.new_xy.b,
                                    L.new_xy.blocks, L.taps, L.c, false, st),
                     "K*I (xy)"))
                 return false;
-            if (!ok(rsf::launch_z_plain(L.R, L.storage, L.new_z.b, L.new_z.blocks, L.taps, st),
+            if (!ok(rsf::launch_z_plain(L.R, L.storage, L.new_z.b, L.new_z.blocks, L.taps,
+                                        rsf::Z_TO_KI, st),
                     "K*I (z)"))
                 return false;
         }
@@ -472,8 +492,10 @@ bool launch_chunk(rsf_server *s, std::string &why)
             if (!ok(rsf::launch_z_heaviside(L.R, L.image, L.storage, L.run_z.b, L.run_z.blocks,
                                             L.taps, L.c, false, st),
                     "z(H)") ||
-                !ok(rsf::launch_xy(L.R, paper ? rsf::XY_PAPER : rsf::XY_FITS, L.image, L.storage,
-                                   L.run_xy.b, L.run_xy.blocks, L.taps, L.c, false, st),
+                !ok(rsf::launch_xy(L.R,
+                                   paper ? (L.k2 ? rsf::XY_PAPER2 : rsf::XY_PAPER) : rsf::XY_FITS,
+                                   L.image, L.storage, L.run_xy.b, L.run_xy.blocks, L.taps, L.c,
+                                   false, st),
                     "xy(fits)") ||
                 (!paper && !ok(rsf::launch_xy(L.R, rsf::XY_TWO, L.image, L.storage, L.run_xy.b,
                                               L.run_xy.blocks, L.taps, L.c, false, st),
@@ -726,7 +748,7 @@ rsf_status rsf_server_submit(rsf_server *s, const rsf_request *req, uint64_t *ti
         if (const char *w = dims_error(req->nx, req->ny, req->nz))
             return refuse(RSF_ERR_INVALID_ARG, w);
         if (const char *w = params_error(req->params)) return refuse(RSF_ERR_INVALID_ARG, w);
-        if (const char *w = types_error(req->params.sigma, req->volume_dtype, req->params.storage))
+        if (const char *w = types_error(req->params, req->volume_dtype))
             return refuse(RSF_ERR_INVALID_ARG, w);
         if (req->iters < 0) return refuse(RSF_ERR_INVALID_ARG, "iters must be >= 0");
         if (!(req->tol >= 0.0) || !std::isfinite(req->tol))
@@ -735,10 +757,10 @@ rsf_status rsf_server_submit(rsf_server *s, const rsf_request *req, uint64_t *ti
         t->req = *req;
         t->g = grid_of(req->nx, req->ny, req->nz);
         t->R = radius_of(req->params.sigma);
-        t->T = tile_regions(t->g, req->iters, req->params.storage);
-        // charged as rsf_workspace_bytes (the region plus a one-tile table)
-        t->ws_bytes = rsf_workspace_bytes(req->nx, req->ny, req->nz, req->iters,
-                                          req->params.storage);
+        t->T = tile_regions(t->g, req->iters, req->params.storage, needs_k2(req->params));
+        // charged as rsf_workspace_bytes_params (the region plus a one-tile table)
+        t->ws_bytes = rsf_workspace_bytes_params(req->nx, req->ny, req->nz, req->iters,
+                                                 &req->params);
         if (t->ws_bytes < t->T.total) return refuse(RSF_ERR_INTERNAL, "workspace size");
         if (t->ws_bytes > s->cfg.budget_bytes)
             return refuse(RSF_ERR_BUDGET, "request workspace exceeds the server budget");

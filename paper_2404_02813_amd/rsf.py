@@ -39,7 +39,8 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_evolve", "rsf_evolve_ex", "rsf_get_stats", "rsf_gauss3d", "rsf_probe",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
            "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
-           "rsf_set_split_targets", "rsf_evolve_volume",
+           "rsf_set_split_targets", "rsf_evolve_volume", "rsf_workspace_bytes_params",
+           "rsf_batch_workspace_bytes_params",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
@@ -157,6 +158,11 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
                                ctypes.POINTER(ctypes.c_int64), vp]
     L.rsf_autotune.restype = i
+    L.rsf_workspace_bytes_params.argtypes = [i64, i64, i64, i, ctypes.POINTER(rsf_params)]
+    L.rsf_workspace_bytes_params.restype = ctypes.c_size_t
+    L.rsf_batch_workspace_bytes_params.argtypes = [ctypes.POINTER(rsf_tile), i, i,
+                                                   ctypes.POINTER(rsf_params)]
+    L.rsf_batch_workspace_bytes_params.restype = ctypes.c_size_t
     L.rsf_evolve_volume.argtypes = [vp, vp, i, vp, i64, i64, i64, i64, i64,
                                     ctypes.POINTER(rsf_params), i, ctypes.c_size_t, vp]
     L.rsf_evolve_volume.restype = i
@@ -328,6 +334,18 @@ def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
     _check(ctx, lib().rsf_autotune(ctx, arr, len(volumes), vdt, ctypes.byref(params),
                                    int(trial_iters), chosen, _stream(stream)))
     return tuple(chosen)
+
+
+def rsf_workspace_bytes_params(nx: int, ny: int, nz: int, iters: int, params: rsf_params) -> int:
+    return int(lib().rsf_workspace_bytes_params(nx, ny, nz, iters, ctypes.byref(params)))
+
+
+def rsf_batch_workspace_bytes_params(shapes, iters: int, params: rsf_params) -> int:
+    arr = (rsf_tile * len(shapes))()
+    for k, (nz, ny, nx) in enumerate(shapes):
+        arr[k] = rsf_tile(None, None, nx, ny, nz)
+    return int(lib().rsf_batch_workspace_bytes_params(arr, len(shapes), iters,
+                                                      ctypes.byref(params)))
 
 
 def rsf_evolve_volume(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,

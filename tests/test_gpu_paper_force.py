@@ -4,7 +4,8 @@ test_oracle_pins.py), with the same bar as the RSF force:
   - one-step fields within FP32 rounding of the value;
   - after N iterations max|dphi| <= 1e-3 (8e-3 with BF16 storage) and
     >= 99.99 % agreement of phi > 0;
-and the batch and server paths bitwise equal to each tile alone.
+and the batch and server paths bitwise equal to each tile alone.  sigma2 > 0
+(K2*I and K2*I^2 precomputed with their own Gaussian) is held to the same bar.
 """
 import sys
 
@@ -172,15 +173,93 @@ def test_paper_force_batch_and_server_equal_alone(rsf):
         assert torch.equal(a, b)
 
 
-def test_paper_force_needs_sigma2_zero(rsf):
+def g2params(mod, sigma2, storage="f32", **kw):
+    p = dict(P, **kw)
+    return mod.make_params(**p, eta=1e-10, storage=storage, force=mod.RSF_FORCE_PAPER,
+                           sigma2=sigma2)
+
+
+def o2params(sigma2, **kw):
+    return oracle.params_array(**dict(P, **kw), eta=1e-10, force=oracle.FORCE_PAPER, sigma2=sigma2)
+
+
+@pytest.mark.parametrize("shape,sigma,sigma2", [((35, 37, 40), 3.0, 1.0), ((21, 19, 70), 2.0, 3.0),
+                                                ((18, 25, 31), 1.5, 5.0)])
+def test_paper_force_sigma2_probe_fields(rsf, shape, sigma, sigma2):
+    """sigma2 > 0: K2*I and K2*I^2 precomputed with their own Gaussian."""
     mod, ctx = rsf
-    say("paper force: sigma2 > 0 is refused")
-    v = dev(np.zeros((8, 8, 8)))
+    say(f"paper force sigma2={sigma2} probe shape={shape} sigma={sigma}")
+    I = inputs.vessel_phantom(shape, 6, 1.0, 3.0, seed=5)
+    phi = smooth(shape, 6)
+    kw = dict(sigma=sigma, lambda1=2.0, lambda2=1.5, nu=0.2)
+    got = {k: host(v) for k, v in ctx.probe(dev(I), dev(phi), g2params(mod, sigma2, **kw)).items()}
+    nxt, f, _ = oracle.step(I, phi, o2params(sigma2, **kw), reg=1)
+    want = dict(f)
+    want["Fd"] = 2.0 * f["e1"] - 1.5 * f["e2"]
+    want["phi_next"] = nxt
+    for k, tol in FIELD_TOL.items():
+        scale = max(1.0, float(np.max(np.abs(want[k]))))
+        err = float(np.max(np.abs(got[k] - want[k])))
+        assert err < tol * scale, (k, err, scale)
+
+
+@pytest.mark.parametrize("storage,image,sigma2,iters", [("f32", "f32", 1.5, 20), ("f16", "u16", 2.0, 60),
+                                                        ("f32", "u16", 4.0, 40)])
+def test_paper_force_sigma2_evolution(rsf, storage, image, sigma2, iters):
+    mod, ctx = rsf
+    n = 64
+    say(f"paper force sigma2={sigma2} evolve {storage}/{image} iters={iters}")
+    if image == "u16":
+        u = inputs.u16_phantom((n, n, n), 16, 1.0, 4.0, seed=47)
+        I = u.astype(np.float64) / 65535.0
+        vol = torch.from_numpy(u).cuda()
+    else:
+        I = inputs.vessel_phantom((n, n, n), 16, 1.0, 3.0, seed=48)
+        vol = dev(I)
+    phi0 = inputs.box_phi0((n, n, n))
+    phi = dev(phi0)
+    ctx.evolve_ex(vol, phi, g2params(mod, sigma2, storage=storage, sigma=4.0), iters)
+    want, _ = oracle.evolve(I, phi0, o2params(sigma2, sigma=4.0), iters)
+    dmax, agree = parity(host(phi), want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.7f}")
+    assert dmax <= phi_tol(storage) and agree >= SIGN_AGREE
+
+
+def test_paper_force_sigma2_server_and_workspace(rsf):
+    mod, ctx = rsf
+    say("paper force sigma2 > 0: workspace size, server vs alone")
+    p = g2params(mod, 1.0)
+    base = mod.rsf_workspace_bytes(40, 50, 60, 10, mod.RSF_F32)
+    assert mod.rsf_workspace_bytes_params(40, 50, 60, 10, p) >= base + 2 * 40 * 50 * 60 * 4
+    assert mod.rsf_workspace_bytes_params(40, 50, 60, 10, mod.make_params(**P)) == base
+    shapes = [(40, 50, 60), (33, 47, 61)]
+    vols = [dev(inputs.vessel_phantom(s, 6, 1.0, 3.0, seed=80 + k)) for k, s in enumerate(shapes)]
+    phis = [dev(inputs.tile_phi0(s, 9)) for s in shapes]
+    alone = []
+    for v, q in zip(vols, phis):
+        a = q.clone()
+        ctx.evolve_ex(v, a, p, 9)
+        alone.append(a)
+    outs = [q.clone() for q in phis]
+    torch.cuda.synchronize()
+    with mod.Server(budget_bytes=2 << 30, chunk_iters=4) as srv:
+        tickets = [srv.submit(v, o, p, 9) for v, o in zip(vols, outs)]
+        results = [srv.wait(t, 120.0) for t in tickets]
+    assert all(r["status"] == 0 for r in results)
+    for a, b in zip(alone, outs):
+        assert torch.equal(a, b)
+
+
+def test_paper_force_sigma2_limits(rsf):
+    mod, ctx = rsf
+    say("paper force: sigma2 outside the built radii is refused")
     phi = dev(inputs.box_phi0((8, 8, 8)))
     before = phi.clone()
-    p = mod.make_params(**P, force=mod.RSF_FORCE_PAPER, sigma2=1.0)
-    with pytest.raises(mod.RsfError) as e:
-        ctx.evolve_ex(v, phi, p, 2)
-    assert e.value.status == mod.RSF_ERR_INVALID_ARG
+    for vol, p in [(dev(np.zeros((8, 8, 8))), g2params(mod, 6.0)),                  # R2 = 18
+                   (torch.zeros((8, 8, 8), dtype=torch.uint16, device="cuda"),
+                    g2params(mod, 0.5, storage="f16"))]:                            # R2 = 2
+        with pytest.raises(mod.RsfError) as e:
+            ctx.evolve_ex(vol, phi, p, 2)
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
     torch.cuda.synchronize()
     assert torch.equal(phi, before)
