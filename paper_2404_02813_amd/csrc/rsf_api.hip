@@ -268,7 +268,12 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
     std::vector<Split> splits;
     for (int t = 0; t < n; ++t) {
         const Grid3 g = grid_of(tiles[t]);
-        Split s = rsf::default_split(g, sh[t], ctx ? ctx->targets : rsf::kDefaultTargets);
+        const rsf::Targets tg = ctx ? ctx->targets : rsf::kDefaultTargets;
+        const bool own_targets = tg.xy != rsf::kDefaultTargets.xy ||
+                                 tg.z != rsf::kDefaultTargets.z || tg.u != rsf::kDefaultTargets.u;
+        // a single volume with the built-in targets: split for the resident capacity
+        Split s = n == 1 && !own_targets && R > 0 ? rsf::capacity_split(g, R)
+                                                  : rsf::default_split(g, sh[t], tg);
         if (ctx) {
             auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
             if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) s = it->second;

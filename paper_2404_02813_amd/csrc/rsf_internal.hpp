@@ -119,6 +119,14 @@ Split make_split(const Grid3 &g, int64_t xy_waves, int64_t z_target, int64_t u_t
 // Split of a tile holding fraction `share` of its batch's voxels: that share
 // of the batch's targets.
 Split default_split(const Grid3 &g, double share = 1.0, const Targets &tg = kDefaultTargets);
+// Split of a single volume from the resident capacity of the z and update
+// passes (R: Gaussian radius): z chunks are chosen so that the launches' last
+// round of workgroups is not left nearly empty.
+Split capacity_split(const Grid3 &g, int R);
+// Workgroups the GPU keeps resident at once: z passes (256-thread groups at
+// 8 per CU) and the update pass (512-thread groups at 2 per CU), on 256 CUs.
+constexpr int64_t kResidentZ = 2048;
+constexpr int64_t kResidentU = 512;
 // Update-pass workgroups of a tile under any valid split are at most this.
 __host__ __device__ inline int64_t u_blocks_max(const Grid3 &g)
 {

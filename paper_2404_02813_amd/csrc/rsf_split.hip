@@ -2,6 +2,8 @@
 // passes, z chunks of the z passes and of the update pass.
 #include <algorithm>
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "rsf_internal.hpp"
 
@@ -44,6 +46,44 @@ Split default_split(const Grid3 &g, double share, const Targets &tg)
         const int64_t len = (g.ny + base - 1) / base;
         s.xy = (int)((g.ny + len - 1) / len);
     }
+    return s;
+}
+
+// z chunks c in 1..ceil(nz/8) for a pass whose workgroups each march a chunk
+// plus `halo` extra slices: the cost of c is ceil(groups / resident) x (chunk
+// length + halo), the launch's rounds of workgroups.  Among the c that keep at
+// least `min_fill` of the resident slots busy, take the fewest chunks whose
+// cost is within 3 % of the least (fewer halo re-reads); if none keeps the
+// slots that busy, take the most chunks.
+static int capacity_chunks(int64_t nz, int64_t cols, int64_t resident, double min_fill,
+                           int64_t halo)
+{
+    const int64_t most = (nz + 7) / 8;
+    std::vector<std::pair<int64_t, double>> ok;
+    double least = -1.0;
+    for (int64_t c = 1; c <= most; ++c) {
+        const int64_t len = (nz + c - 1) / c;
+        if ((nz + len - 1) / len != c) continue;   // not c non-empty chunks
+        const int64_t groups = cols * c;
+        if ((double)groups < min_fill * (double)resident) continue;
+        const double cost = (double)((groups + resident - 1) / resident) * (double)(len + halo);
+        ok.push_back({c, cost});
+        if (least < 0.0 || cost < least) least = cost;
+    }
+    for (const auto &cc : ok)
+        if (cc.second <= 1.03 * least) return (int)cc.first;
+    const int64_t len = (nz + most - 1) / most;
+    return (int)((nz + len - 1) / len);
+}
+
+Split capacity_split(const Grid3 &g, int R)
+{
+    Split s = default_split(g, 1.0, kDefaultTargets);
+    // a z-pass chunk primes its ring with 2R slices; an update chunk reads R
+    // extra slices of the pair ring on average and 4 of phi
+    s.z = capacity_chunks(g.nz, z_cols(g), kResidentZ, 0.5, 2 * R);
+    s.u = capacity_chunks(g.nz, (int64_t)((g.nx + kUx - 1) / kUx) * ((g.ny + kUy - 1) / kUy),
+                          kResidentU, 0.75, R + 2);
     return s;
 }
 
