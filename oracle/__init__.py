@@ -70,6 +70,8 @@ def _lib(real: str = "f64"):
     lib.oracle_step.restype = ctypes.c_int
     lib.oracle_evolve.argtypes = [dp, dp, i64, i64, i64, dp, ctypes.c_int, ctypes.c_int, dp]
     lib.oracle_evolve.restype = ctypes.c_int
+    lib.oracle_fast_sweep.argtypes = [dp, i64, i64, i64, ctypes.c_int]
+    lib.oracle_fast_sweep.restype = None
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     lib.oracle_real_type.restype = ctypes.c_char_p
@@ -225,3 +227,90 @@ def evolve_volume(I, phi0, params, iters: int, block: int, curtain: int,
     boxes = volume_boxes(phi0.shape, block, curtain)
     fields = [evolve(I[sl], phi0[sl], params, iters, reg)[0] for sl, _ in boxes]
     return merge_boxes(phi0.shape, boxes, fields)
+
+
+# ---------------------------------------------------------------------------
+# Initialisation (Sec. 4.3): determinant-of-Hessian seeds per z slice, then a
+# distance function from the seeds by fast sweeping.
+# ---------------------------------------------------------------------------
+
+FAR = 1e30   # "no seed yet" distance
+
+
+def smooth_slices(I, sigma: float, dtype=np.float64) -> np.ndarray:
+    """Each z slice convolved with the sampled, truncated, unit-sum 2D
+    Gaussian (separable: x then y), zero padding, in `dtype`."""
+    w = weights(sigma).astype(dtype)
+    R = (len(w) - 1) // 2
+    u = np.asarray(I, dtype=dtype)
+    nz, ny, nx = u.shape
+    tmp = np.zeros_like(u)
+    for k in range(-R, R + 1):             # along x: out[x] += w[k + R] * u[x + k]
+        lo, hi = max(0, -k), min(nx, nx - k)
+        tmp[:, :, lo:hi] += w[k + R] * u[:, :, lo + k:hi + k]
+    out = np.zeros_like(u)
+    for k in range(-R, R + 1):             # along y
+        lo, hi = max(0, -k), min(ny, ny - k)
+        out[:, lo:hi, :] += w[k + R] * tmp[:, lo + k:hi + k, :]
+    return out
+
+
+def slice_hessian(L):
+    """In-slice second differences of L (central, reflect ghosts about the
+    boundary voxel): Lxx, Lyy, Lxy."""
+    p = np.pad(L, ((0, 0), (1, 1), (1, 1)), mode="reflect")
+    c = p[:, 1:-1, 1:-1]
+    Lxx = p[:, 1:-1, 2:] - 2 * c + p[:, 1:-1, :-2]
+    Lyy = p[:, 2:, 1:-1] - 2 * c + p[:, :-2, 1:-1]
+    Lxy = (p[:, 2:, 2:] - p[:, :-2, 2:] - p[:, 2:, :-2] + p[:, :-2, :-2]) / 4
+    return Lxx, Lyy, Lxy
+
+
+def blob_seeds(I, sigma_b: float, threshold: float, dtype=np.float64):
+    """Seed mask: bright blobs (Lxx + Lyy < 0) whose determinant of the
+    Hessian exceeds threshold x its largest value over the volume and is a
+    local maximum in its 3x3 in-slice neighbourhood (strictly above the
+    neighbours earlier in raster order, at least the later ones).  Returns
+    (mask, doh, trace)."""
+    L = smooth_slices(I, sigma_b, dtype)
+    Lxx, Lyy, Lxy = slice_hessian(L)
+    doh = (Lxx * Lyy - Lxy * Lxy).astype(dtype)
+    tr = (Lxx + Lyy).astype(dtype)
+    return seed_rule(doh, tr, threshold), doh, tr
+
+
+def seed_rule(doh, tr, threshold: float) -> np.ndarray:
+    """The selection of blob_seeds on given determinant and trace fields."""
+    thr = doh.dtype.type(threshold) * doh.max()
+    m = (doh > thr) & (tr < 0)
+    nz, ny, nx = doh.shape
+    p = np.pad(doh, ((0, 0), (1, 1), (1, 1)), mode="constant", constant_values=-np.inf)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            nb = p[:, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+            earlier = dy < 0 or (dy == 0 and dx < 0)
+            m &= (doh > nb) if earlier else (doh >= nb)
+    return m
+
+
+def fast_sweep(u0, rounds: int = 1) -> np.ndarray:
+    """Fast sweeping (Zhao 2005) on the unit grid, in FP64, from a field
+    holding 0 at the seeds and FAR elsewhere."""
+    u = _f64(u0).copy()
+    nz, ny, nx = u.shape
+    _lib().oracle_fast_sweep(_dptr(u), nx, ny, nz, int(rounds))
+    return u
+
+
+def init_phi(I, sigma_b: float, threshold: float, offset: float = 0.0, rounds: int = 1,
+             dtype=np.float64):
+    """phi0 = offset - distance to the nearest seed (seeds on the zero level
+    for offset 0).  Returns (phi0, seed mask)."""
+    m, _, _ = blob_seeds(I, sigma_b, threshold, dtype)
+    if not m.any():
+        raise ValueError("no seed found")
+    u = np.where(m, 0.0, FAR)
+    d = fast_sweep(u, rounds)
+    return offset - d, m

@@ -470,3 +470,51 @@ int oracle_evolve(const double *I_in, double *phi_io, i64 nx, i64 ny, i64 nz,
     work_free(&s); free(I); free(a); free(b); free(K1); free(w); free(K2I); free(K2I2);
     return 0;
 }
+
+/* Fast sweeping (Zhao 2005), the distance solver of Sec. 4.3: Gauss-Seidel
+ * sweeps in the eight axis orderings of the Godunov upwind discretisation of
+ * |grad u| = 1 on the unit grid, u = 0 at the seeds (u enters as 0 there and
+ * a large value elsewhere).  `rounds` repetitions of the eight sweeps. */
+static double godunov(double a, double b, double c)
+{
+    /* sort a <= b <= c */
+    double t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+    double u = a + 1.0;
+    if (u > b) {
+        u = 0.5 * (a + b + sqrt(2.0 - (a - b) * (a - b)));
+        if (u > c) {
+            const double s = a + b + c;
+            u = (s + sqrt(s * s - 3.0 * (a * a + b * b + c * c - 1.0))) / 3.0;
+        }
+    }
+    return u;
+}
+
+void oracle_fast_sweep(double *u, i64 nx, i64 ny, i64 nz, int rounds)
+{
+    for (int r = 0; r < rounds; ++r)
+        for (int d = 0; d < 8; ++d) {
+            const int sx = (d & 1) ? -1 : 1, sy = (d & 2) ? -1 : 1, sz = (d & 4) ? -1 : 1;
+            for (i64 kk = 0; kk < nz; ++kk)
+                for (i64 jj = 0; jj < ny; ++jj)
+                    for (i64 ii = 0; ii < nx; ++ii) {
+                        const i64 i = sx > 0 ? ii : nx - 1 - ii;
+                        const i64 j = sy > 0 ? jj : ny - 1 - jj;
+                        const i64 k = sz > 0 ? kk : nz - 1 - kk;
+                        const i64 p = (k * ny + j) * nx + i;
+                        double a = 1e300, b = 1e300, c = 1e300;
+                        if (i > 0) a = u[p - 1];
+                        if (i < nx - 1 && u[p + 1] < a) a = u[p + 1];
+                        if (j > 0) b = u[p - nx];
+                        if (j < ny - 1 && u[p + nx] < b) b = u[p + nx];
+                        if (k > 0) c = u[p - nx * ny];
+                        if (k < nz - 1 && u[p + nx * ny] < c) c = u[p + nx * ny];
+                        if (a >= 1e299 && b >= 1e299 && c >= 1e299) continue;
+                        const double v = godunov(a, b, c);
+                        if (v < u[p]) u[p] = v;
+                    }
+        }
+}
