@@ -252,6 +252,45 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
                              const rsf_params *params, int iters, size_t budget_bytes,
                              void *stream);
 
+/* ------------------------------------------------------------------------
+ * Initialisation (Sec. 4.3): seed points from blob detection by the
+ * determinant of the Hessian in each z slice, then phi0 from the distance to
+ * the nearest seed by fast sweeping.
+ * ---------------------------------------------------------------------- */
+
+/* Seed mask (device, nx*ny*nz bytes, 1 at seeds).  Each z slice is smoothed
+ * by the sampled, unit-sum 2D Gaussian of scale sigma_b (zero padding); the
+ * in-slice Hessian of the result comes from central second differences
+ * (reflection about the boundary voxel).  A voxel is a seed when its
+ * determinant exceeds `threshold` (in [0, 1)) times the largest determinant
+ * of the volume, the trace is negative (a bright blob) and the determinant
+ * is a maximum of the 3x3 in-slice neighbourhood (strictly above the
+ * neighbours earlier in raster order, at least the later ones).  *n_seeds
+ * (host, may be NULL) receives the count; synchronises `stream`.  volume:
+ * RSF_F32 or RSF_U16.  Allocates scratch for the call. */
+rsf_status rsf_seeds(rsf_context *ctx, const void *volume, int volume_dtype, int64_t nx,
+                     int64_t ny, int64_t nz, float sigma_b, float threshold, unsigned char *mask,
+                     int64_t *n_seeds, void *stream);
+
+/* Fast sweeping (Zhao 2005) in place: u (device floats) holds 0 at the
+ * seeds and a large value (1e30) elsewhere; `rounds` repetitions of the
+ * eight Gauss-Seidel sweep orderings of the Godunov upwind discretisation of
+ * |grad u| = 1 on the unit grid.  Each sweep runs hyperplane by hyperplane,
+ * which gives the same updates as the sequential sweep.  One round reaches
+ * the discrete solution for a single seed; several seeds can need a second
+ * (first-round differences of order 1e-4). */
+rsf_status rsf_fast_sweep(rsf_context *ctx, float *u, int64_t nx, int64_t ny, int64_t nz,
+                          int rounds, void *stream);
+
+/* phi0 = offset - (distance to the nearest seed): seeds as rsf_seeds, the
+ * distance as rsf_fast_sweep.  With offset 0 the seeds lie on the zero level
+ * and the vessels around them grow into phi > 0 (the region H weights).
+ * RSF_ERR_INVALID_ARG if no seed is found (phi untouched).  Synchronises
+ * `stream`; allocates scratch for the call. */
+rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                        int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
+                        float offset, int rounds, int64_t *n_seeds, void *stream);
+
 /* One zero-padded Gaussian convolution out = K * in (Sec. 3 kernel), the
  * separable passes the evolution uses.  in, out: device floats, distinct;
  * every dimension >= 3. */

@@ -998,6 +998,175 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of one call, freed on every exit.
+struct Scratch {
+    std::vector<void *> p;
+    ~Scratch()
+    {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <class T>
+    hipError_t get(T **out, size_t bytes)
+    {
+        void *q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+        if (e == hipSuccess) p.push_back(q);
+        *out = static_cast<T *>(q);
+        return e;
+    }
+};
+
+rsf_status check_seed_args(rsf_context *ctx, const void *volume, int vdt, int64_t nx, int64_t ny,
+                           int64_t nz, float sigma_b, float threshold)
+{
+    if (!volume) return fail(ctx, RSF_ERR_INVALID_ARG, "null volume");
+    rsf_status st = check_dims(ctx, nx, ny, nz);
+    if (st != RSF_OK) return st;
+    if (nx < 2 || ny < 2) return fail(ctx, RSF_ERR_INVALID_ARG, "seeds need nx, ny >= 2");
+    if (ny * nz > (int64_t(1) << 31)) return fail(ctx, RSF_ERR_INVALID_ARG, "ny * nz above 2^31");
+    if (vdt != RSF_F32 && vdt != RSF_U16)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "volume dtype must be RSF_F32 or RSF_U16");
+    if (!std::isfinite(sigma_b) || !(sigma_b > 0.f) || radius_of(sigma_b) > rsf::kMaxR)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "sigma_b must be > 0 with ceil(3 sigma_b) <= 16");
+    if (!std::isfinite(threshold) || threshold < 0.f || threshold >= 1.f)
+        return fail(ctx, RSF_ERR_INVALID_ARG, "threshold must be in [0, 1)");
+    return RSF_OK;
+}
+
+// Seeds into mask and u (0 at seeds, far elsewhere); the count if asked.
+rsf_status seeds_impl(rsf_context *ctx, Scratch &sc, const void *volume, int vdt, int64_t nx,
+                      int64_t ny, int64_t nz, float sigma_b, float threshold, unsigned char *mask,
+                      float *u, int64_t *n_seeds, hipStream_t s)
+{
+    const int64_t n = nx * ny * nz;
+    const int R = radius_of(sigma_b);
+    const Taps t = make_taps(sigma_b, R);
+    float *A = nullptr, *B = nullptr, *tr = nullptr, *part = nullptr, *mx = nullptr;
+    unsigned *cnt = nullptr;
+    HIP_TRY(sc.get(&A, (size_t)n * 4), "hipMalloc(seed scratch)");
+    HIP_TRY(sc.get(&B, (size_t)n * 4), "hipMalloc(seed scratch)");
+    HIP_TRY(sc.get(&tr, (size_t)n * 4), "hipMalloc(seed scratch)");
+    HIP_TRY(sc.get(&part, 65536 * 4), "hipMalloc(seed scratch)");
+    HIP_TRY(sc.get(&mx, 4), "hipMalloc(seed scratch)");
+    HIP_TRY(sc.get(&cnt, 65536 * 4), "hipMalloc(seed scratch)");
+    int blocks = 0;
+    // L = 2D Gaussian of each slice (A: x pass, B: y pass); doh into A
+    HIP_TRY(rsf::launch_smooth_x(volume, vdt, A, nx, ny, nz, t, R, s), "smooth x");
+    HIP_TRY(rsf::launch_smooth_y(A, B, nx, ny, nz, t, R, s), "smooth y");
+    HIP_TRY(rsf::launch_hessian(B, A, tr, part, nx, ny, nz, &blocks, s), "hessian");
+    HIP_TRY(rsf::launch_max(part, blocks, mx, s), "max");
+    HIP_TRY(rsf::launch_seeds(A, tr, mx, threshold, mask, u, cnt, nx, ny, nz, s), "seeds");
+    if (n_seeds) {
+        std::vector<unsigned> h((size_t)blocks);
+        HIP_TRY(hipMemcpyAsync(h.data(), cnt, (size_t)blocks * 4, hipMemcpyDeviceToHost, s),
+                "copy counts");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        int64_t total = 0;
+        for (unsigned c : h) total += c;
+        *n_seeds = total;
+    }
+    return RSF_OK;
+}
+
+rsf_status sweep_impl(rsf_context *ctx, float *u, int64_t nx, int64_t ny, int64_t nz, int rounds,
+                      hipStream_t s)
+{
+    for (int r = 0; r < rounds; ++r)
+        for (int dir = 0; dir < 8; ++dir)
+            for (int64_t h = 0; h <= nx + ny + nz - 3; ++h)
+                HIP_TRY(rsf::launch_sweep_plane(u, nx, ny, nz, dir, h, s), "sweep");
+    return RSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rsf_status rsf_seeds(rsf_context *ctx, const void *volume, int volume_dtype, int64_t nx,
+                     int64_t ny, int64_t nz, float sigma_b, float threshold, unsigned char *mask,
+                     int64_t *n_seeds, void *stream)
+{
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        ctx->err.clear();
+        rsf_status st = check_seed_args(ctx, volume, volume_dtype, nx, ny, nz, sigma_b, threshold);
+        if (st != RSF_OK) return st;
+        if (!mask) return fail(ctx, RSF_ERR_INVALID_ARG, "null mask");
+        st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Scratch sc;
+        float *u = nullptr;
+        HIP_TRY(sc.get(&u, (size_t)(nx * ny * nz) * 4), "hipMalloc(seed scratch)");
+        st = seeds_impl(ctx, sc, volume, volume_dtype, nx, ny, nz, sigma_b, threshold, mask, u,
+                        n_seeds, s);
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return st;
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+rsf_status rsf_fast_sweep(rsf_context *ctx, float *u, int64_t nx, int64_t ny, int64_t nz,
+                          int rounds, void *stream)
+{
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (!u) return fail(ctx, RSF_ERR_INVALID_ARG, "null field");
+        rsf_status st = check_dims(ctx, nx, ny, nz);
+        if (st != RSF_OK) return st;
+        if (rounds < 1 || rounds > 64) return fail(ctx, RSF_ERR_INVALID_ARG, "rounds must be in 1..64");
+        if (ny * nz > (int64_t(1) << 31)) return fail(ctx, RSF_ERR_INVALID_ARG, "ny * nz above 2^31");
+        st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        return sweep_impl(ctx, u, nx, ny, nz, rounds, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                        int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
+                        float offset, int rounds, int64_t *n_seeds, void *stream)
+{
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        ctx->err.clear();
+        rsf_status st = check_seed_args(ctx, volume, volume_dtype, nx, ny, nz, sigma_b, threshold);
+        if (st != RSF_OK) return st;
+        if (!phi) return fail(ctx, RSF_ERR_INVALID_ARG, "null phi");
+        if (!std::isfinite(offset)) return fail(ctx, RSF_ERR_INVALID_ARG, "offset must be finite");
+        if (rounds < 1 || rounds > 64) return fail(ctx, RSF_ERR_INVALID_ARG, "rounds must be in 1..64");
+        st = set_device(ctx);
+        if (st != RSF_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t n = nx * ny * nz;
+        Scratch sc;
+        unsigned char *mask = nullptr;
+        float *u = nullptr;
+        HIP_TRY(sc.get(&mask, (size_t)n), "hipMalloc(seed scratch)");
+        HIP_TRY(sc.get(&u, (size_t)n * 4), "hipMalloc(seed scratch)");
+        int64_t count = 0;
+        st = seeds_impl(ctx, sc, volume, volume_dtype, nx, ny, nz, sigma_b, threshold, mask, u,
+                        &count, s);
+        if (st != RSF_OK) return st;
+        if (n_seeds) *n_seeds = count;
+        if (count == 0) return fail(ctx, RSF_ERR_INVALID_ARG, "no seed found (lower threshold)");
+        st = sweep_impl(ctx, u, nx, ny, nz, rounds, s);
+        if (st != RSF_OK) return st;
+        HIP_TRY(rsf::launch_offset(u, phi, n, offset, s), "offset");
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return RSF_OK;
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
 rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx, int64_t ny,
                        int64_t nz, float sigma, void *stream)
 {

@@ -186,6 +186,31 @@ hipError_t launch_merge(float *acc, const float *tile, int64_t nx, int64_t ny, c
                         int curtain, hipStream_t s);
 hipError_t launch_fill(float *dst, int64_t n, float v, hipStream_t s);
 
+// Initialisation (Sec. 4.3).  Slices smoothed by the 2D Gaussian (x pass from
+// the image, then y pass), the determinant and trace of the in-slice Hessian
+// with per-workgroup maxima of the determinant, the seed mask, and one fast
+// sweeping hyperplane.
+constexpr float kFar = 1e30f;        // distance of a voxel no seed has reached
+hipError_t launch_smooth_x(const void *img, int image_dtype, float *out, int64_t nx, int64_t ny,
+                           int64_t nz, const Taps &t, int R, hipStream_t s);
+hipError_t launch_smooth_y(const float *in, float *out, int64_t nx, int64_t ny, int64_t nz,
+                           const Taps &t, int R, hipStream_t s);
+// doh, trace from L; partial maxima of doh into part[blocks]; returns blocks
+hipError_t launch_hessian(const float *L, float *doh, float *tr, float *part, int64_t nx,
+                          int64_t ny, int64_t nz, int *blocks, hipStream_t s);
+// max of part[0..n) into out[0] (one workgroup, fixed order)
+hipError_t launch_max(const float *part, int n, float *out, hipStream_t s);
+// mask and u (0 at seeds, kFar elsewhere); per-workgroup seed counts into cnt
+hipError_t launch_seeds(const float *doh, const float *tr, const float *maxv, float threshold,
+                        unsigned char *mask, float *u, unsigned *cnt, int64_t nx, int64_t ny,
+                        int64_t nz, hipStream_t s);
+// one hyperplane i' + j' + k' = h of the sweep with axis orders dir (bit 0:
+// x descending, bit 1: y, bit 2: z)
+hipError_t launch_sweep_plane(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t h,
+                              hipStream_t s);
+// phi = offset - u
+hipError_t launch_offset(const float *u, float *phi, int64_t n, float offset, hipStream_t s);
+
 // Per-radius, per-type launchers behind the dispatchers (rsf_kernels.hpp).
 template <int R, class IT, class ST>
 hipError_t launch_xy_r(int mode, const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,

@@ -155,6 +155,199 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(float *dst, int64_t n, f
         d[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Initialisation (Sec. 4.3): determinant-of-Hessian seeds, fast sweeping
+// ---------------------------------------------------------------------------
+
+template <class IT>
+__global__ __launch_bounds__(kThreads) void smooth_x_kernel(const IT *img, float *out, int64_t nx,
+                                                            int64_t n, Taps t, int R)
+{
+    const gptr<const IT> in = glb(img);
+    const gptr<float> o = glb(out);
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int64_t x = i % nx, row = i - x;
+        float acc = 0.f;
+        for (int k = -R; k <= R; ++k) {
+            const int64_t xx = x + k;
+            if (xx >= 0 && xx < nx) acc = fmaf(t.w[k + R], to_f(in[row + xx]), acc);
+        }
+        o[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void smooth_y_kernel(const float *src, float *out,
+                                                            int64_t nx, int64_t ny, int64_t n,
+                                                            Taps t, int R)
+{
+    const gptr<const float> in = glb(src);
+    const gptr<float> o = glb(out);
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int64_t yz = i / nx;
+        const int64_t y = yz % ny, base = i - y * nx;   // (z, 0, x)
+        float acc = 0.f;
+        for (int k = -R; k <= R; ++k) {
+            const int64_t yy = y + k;
+            if (yy >= 0 && yy < ny) acc = fmaf(t.w[k + R], in[base + yy * nx], acc);
+        }
+        o[i] = acc;
+    }
+}
+
+__device__ __forceinline__ int64_t refl(int64_t i, int64_t n)
+{
+    return i < 0 ? -i : (i > n - 1 ? 2 * (n - 1) - i : i);
+}
+
+__global__ __launch_bounds__(kThreads) void hessian_kernel(const float *Lp, float *doh, float *tr,
+                                                           float *part, int64_t nx, int64_t ny,
+                                                           int64_t n)
+{
+    const gptr<const float> L = glb(Lp);
+    __shared__ float sm[kThreads];
+    float best = -kFar;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int64_t x = i % nx, yz = i / nx;
+        const int64_t y = yz % ny, base = i - x - y * nx;
+        auto at = [&](int64_t xx, int64_t yy) { return L[base + refl(yy, ny) * nx + refl(xx, nx)]; };
+        const float c = at(x, y);
+        const float lxx = at(x + 1, y) - 2.f * c + at(x - 1, y);
+        const float lyy = at(x, y + 1) - 2.f * c + at(x, y - 1);
+        const float lxy = (at(x + 1, y + 1) - at(x + 1, y - 1) - at(x - 1, y + 1) +
+                           at(x - 1, y - 1)) * 0.25f;
+        const float d = lxx * lyy - lxy * lxy;
+        glb(doh)[i] = d;
+        glb(tr)[i] = lxx + lyy;
+        best = fmaxf(best, d);
+    }
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) glb(part)[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kThreads) void max_kernel(const float *part, int n, float *out)
+{
+    __shared__ float sm[kThreads];
+    float best = -kFar;
+    for (int i = threadIdx.x; i < n; i += kThreads) best = fmaxf(best, glb(part)[i]);
+    sm[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) glb(out)[0] = sm[0];
+}
+
+// A seed is a bright blob (trace < 0) whose determinant exceeds threshold x
+// the volume's largest and is a local maximum of its 3x3 in-slice
+// neighbourhood: strictly above the neighbours earlier in raster order, at
+// least the later ones (so a plateau gives one seed).
+__global__ __launch_bounds__(kThreads) void seeds_kernel(const float *dohp, const float *trp,
+                                                         const float *maxv, float threshold,
+                                                         unsigned char *mask, float *u,
+                                                         unsigned *cnt, int64_t nx, int64_t ny,
+                                                         int64_t n)
+{
+    const gptr<const float> doh = glb(dohp);
+    __shared__ unsigned sc[kThreads];
+    unsigned mine = 0;
+    const float thr = threshold * glb(maxv)[0];
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const int64_t x = i % nx, yz = i / nx;
+        const int64_t y = yz % ny, base = i - x - y * nx;
+        const float d = doh[i];
+        bool seed = d > thr && glb(trp)[i] < 0.f;
+        for (int dy = -1; dy <= 1 && seed; ++dy)
+            for (int dx = -1; dx <= 1 && seed; ++dx) {
+                if (dx == 0 && dy == 0) continue;
+                const int64_t xx = x + dx, yy = y + dy;
+                if (xx < 0 || xx >= nx || yy < 0 || yy >= ny) continue;
+                const float nb = doh[base + yy * nx + xx];
+                const bool earlier = dy < 0 || (dy == 0 && dx < 0);
+                seed = earlier ? d > nb : d >= nb;
+            }
+        glb(mask)[i] = seed ? 1 : 0;
+        glb(u)[i] = seed ? 0.f : kFar;
+        mine += seed ? 1u : 0u;
+    }
+    sc[threadIdx.x] = mine;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) glb(cnt)[blockIdx.x] = sc[0];
+}
+
+// Godunov update of |grad u| = 1 on the unit grid from the smallest
+// neighbour value along each axis (a, b, c; kFar when absent).  The roots
+// are written in the differences d1 = b - a, d2 = c - a, which are O(1)
+// where they are used: the textbook discriminant (a+b+c)^2 - 3(a^2+b^2+c^2-1)
+// cancels to O(1) from O(u^2) terms and loses most FP32 digits at large u.
+__device__ __forceinline__ float godunov(float a, float b, float c)
+{
+    float t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+    if (a + 1.f <= b) return a + 1.f;
+    const float d1 = b - a;
+    const float r2 = 0.5f * (d1 + sqrtf(2.f - d1 * d1));
+    if (a + r2 <= c) return a + r2;
+    const float d2 = c - a, d3 = d2 - d1;
+    return a + (d1 + d2 + sqrtf(3.f - (d1 * d1 + d2 * d2 + d3 * d3))) * (1.f / 3.f);
+}
+
+// One hyperplane of a sweep: the points with i' + j' + k' = h, where i' = i
+// or nx-1-i by the sweep's x order (likewise j', k').  Every point of a
+// hyperplane depends only on earlier hyperplanes in this sweep's order, so
+// hyperplane by hyperplane gives the same updates as the sequential sweep.
+// Thread (jj, kk) of the grid covers j' = jlo(k') + jj, k' = klo + kk.
+__global__ __launch_bounds__(kThreads) void sweep_plane_kernel(float *up, int64_t nx, int64_t ny,
+                                                               int64_t nz, int dir, int64_t h,
+                                                               int64_t klo, int64_t kcount)
+{
+    const int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    const int64_t jspan = ny;
+    if (t >= jspan * kcount) return;
+    const int64_t kp = klo + t / jspan;
+    const int64_t jp = t % jspan;
+    const int64_t ip = h - jp - kp;
+    if (ip < 0 || ip >= nx) return;
+    const int64_t i = (dir & 1) ? nx - 1 - ip : ip;
+    const int64_t j = (dir & 2) ? ny - 1 - jp : jp;
+    const int64_t k = (dir & 4) ? nz - 1 - kp : kp;
+    const gptr<float> u = glb(up);
+    const int64_t p = (k * ny + j) * nx + i;
+    float a = kFar, b = kFar, c = kFar;
+    if (i > 0) a = u[p - 1];
+    if (i < nx - 1) a = fminf(a, u[p + 1]);
+    if (j > 0) b = u[p - nx];
+    if (j < ny - 1) b = fminf(b, u[p + nx]);
+    if (k > 0) c = u[p - nx * ny];
+    if (k < nz - 1) c = fminf(c, u[p + nx * ny]);
+    if (a >= kFar && b >= kFar && c >= kFar) return;
+    const float v = godunov(a, b, c);
+    if (v < u[p]) u[p] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void offset_kernel(const float *u, float *phi, int64_t n,
+                                                          float offset)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        glb(phi)[i] = offset - glb(u)[i];
+}
+
 unsigned stride_grid(int64_t n)
 {
     const int64_t g = (n + kThreads - 1) / kThreads;
@@ -192,6 +385,78 @@ hipError_t launch_merge(float *acc, const float *tile, int64_t nx, int64_t ny, c
     return hipGetLastError();
 }
 
+// dtype codes as in rsf.h
+constexpr int F32 = 0, F16 = 1, BF16 = 2, U16 = 3;
+
+hipError_t launch_smooth_x(const void *img, int image_dtype, float *out, int64_t nx, int64_t ny,
+                           int64_t nz, const Taps &t, int R, hipStream_t s)
+{
+    const int64_t n = nx * ny * nz;
+    if (image_dtype == U16)
+        hipLaunchKernelGGL(smooth_x_kernel<uint16_t>, dim3(stride_grid(n)), dim3(kThreads), 0, s,
+                           static_cast<const uint16_t *>(img), out, nx, n, t, R);
+    else
+        hipLaunchKernelGGL(smooth_x_kernel<float>, dim3(stride_grid(n)), dim3(kThreads), 0, s,
+                           static_cast<const float *>(img), out, nx, n, t, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_y(const float *in, float *out, int64_t nx, int64_t ny, int64_t nz,
+                           const Taps &t, int R, hipStream_t s)
+{
+    const int64_t n = nx * ny * nz;
+    hipLaunchKernelGGL(smooth_y_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, in, out, nx, ny,
+                       n, t, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_hessian(const float *L, float *doh, float *tr, float *part, int64_t nx,
+                          int64_t ny, int64_t nz, int *blocks, hipStream_t s)
+{
+    const int64_t n = nx * ny * nz;
+    const unsigned g = stride_grid(n);
+    *blocks = (int)g;
+    hipLaunchKernelGGL(hessian_kernel, dim3(g), dim3(kThreads), 0, s, L, doh, tr, part, nx, ny, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_max(const float *part, int n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(kThreads), 0, s, part, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_seeds(const float *doh, const float *tr, const float *maxv, float threshold,
+                        unsigned char *mask, float *u, unsigned *cnt, int64_t nx, int64_t ny,
+                        int64_t nz, hipStream_t s)
+{
+    const int64_t n = nx * ny * nz;
+    hipLaunchKernelGGL(seeds_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, doh, tr, maxv,
+                       threshold, mask, u, cnt, nx, ny, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_plane(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t h,
+                              hipStream_t s)
+{
+    // k' runs over the values for which some (i', j') completes the plane
+    const int64_t klo = std::max<int64_t>(0, h - (nx - 1) - (ny - 1));
+    const int64_t khi = std::min<int64_t>(nz - 1, h);
+    if (khi < klo) return hipSuccess;
+    const int64_t kcount = khi - klo + 1;
+    const int64_t n = ny * kcount;
+    const int64_t g = (n + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(sweep_plane_kernel, dim3((unsigned)g), dim3(kThreads), 0, s, u, nx, ny, nz,
+                       dir, h, klo, kcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_offset(const float *u, float *phi, int64_t n, float offset, hipStream_t s)
+{
+    hipLaunchKernelGGL(offset_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, u, phi, n, offset);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float *dst, int64_t n, float v, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_kernel, dim3(stride_grid(n)), dim3(kThreads), 0, s, dst, n, v);
@@ -216,8 +481,6 @@ hipError_t launch_finish(const Batch &b, int64_t blocks, hipStream_t s)
     return hipGetLastError();
 }
 
-// dtype codes as in rsf.h
-constexpr int F32 = 0, F16 = 1, BF16 = 2, U16 = 3;
 
 bool types_supported(int R, int it, int st)
 {

@@ -40,7 +40,7 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
            "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
            "rsf_set_split_targets", "rsf_evolve_volume", "rsf_workspace_bytes_params",
-           "rsf_batch_workspace_bytes_params",
+           "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
@@ -158,6 +158,13 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
                                ctypes.POINTER(ctypes.c_int64), vp]
     L.rsf_autotune.restype = i
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.rsf_seeds.argtypes = [vp, vp, i, i64, i64, i64, f, f, vp, i64p, vp]
+    L.rsf_seeds.restype = i
+    L.rsf_fast_sweep.argtypes = [vp, vp, i64, i64, i64, i, vp]
+    L.rsf_fast_sweep.restype = i
+    L.rsf_init_phi.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, i, i64p, vp]
+    L.rsf_init_phi.restype = i
     L.rsf_workspace_bytes_params.argtypes = [i64, i64, i64, i, ctypes.POINTER(rsf_params)]
     L.rsf_workspace_bytes_params.restype = ctypes.c_size_t
     L.rsf_batch_workspace_bytes_params.argtypes = [ctypes.POINTER(rsf_tile), i, i,
@@ -348,6 +355,43 @@ def rsf_batch_workspace_bytes_params(shapes, iters: int, params: rsf_params) -> 
                                                       ctypes.byref(params)))
 
 
+def rsf_seeds(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
+              mask: torch.Tensor | None = None, stream=None):
+    """Seed mask (uint8 tensor) and the seed count."""
+    _field(volume, "volume", "image")
+    nz, ny, nx = volume.shape
+    if mask is None:
+        mask = torch.empty(volume.shape, dtype=torch.uint8, device=volume.device)
+    if mask.dtype != torch.uint8 or mask.shape != volume.shape or not mask.is_contiguous():
+        raise ValueError("mask must be a contiguous uint8 tensor of the volume's shape")
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().rsf_seeds(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype], nx, ny, nz,
+                                float(sigma_b), float(threshold), mask.data_ptr(), ctypes.byref(n),
+                                _stream(stream)))
+    return mask, n.value
+
+
+def rsf_fast_sweep(ctx, u: torch.Tensor, rounds: int = 2, stream=None) -> None:
+    _field(u, "u")
+    nz, ny, nx = u.shape
+    _check(ctx, lib().rsf_fast_sweep(ctx, u.data_ptr(), nx, ny, nz, int(rounds), _stream(stream)))
+
+
+def rsf_init_phi(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma_b: float, threshold: float,
+                 offset: float = 0.0, rounds: int = 2, stream=None) -> int:
+    """phi = offset - distance to the nearest seed; returns the seed count."""
+    _field(volume, "volume", "image")
+    _field(phi, "phi")
+    if volume.shape != phi.shape:
+        raise ValueError("volume and phi must have the same shape")
+    nz, ny, nx = phi.shape
+    n = ctypes.c_int64(0)
+    _check(ctx, lib().rsf_init_phi(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                   phi.data_ptr(), nx, ny, nz, float(sigma_b), float(threshold),
+                                   float(offset), int(rounds), ctypes.byref(n), _stream(stream)))
+    return n.value
+
+
 def rsf_evolve_volume(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
                       iters: int, block: int, curtain: int = 0, budget_bytes: int = 0,
                       stream=None) -> None:
@@ -476,6 +520,15 @@ class Context:
                       stream=None):
         rsf_evolve_volume(self.handle, volume, phi, params, iters, block, curtain, budget_bytes,
                           stream)
+
+    def seeds(self, volume, sigma_b, threshold, mask=None, stream=None):
+        return rsf_seeds(self.handle, volume, sigma_b, threshold, mask, stream)
+
+    def fast_sweep(self, u, rounds=2, stream=None):
+        rsf_fast_sweep(self.handle, u, rounds, stream)
+
+    def init_phi(self, volume, phi, sigma_b, threshold, offset=0.0, rounds=2, stream=None):
+        return rsf_init_phi(self.handle, volume, phi, sigma_b, threshold, offset, rounds, stream)
 
     def set_split_targets(self, xy_waves=0, z_blocks=0, u_blocks=0):
         rsf_set_split_targets(self.handle, xy_waves, z_blocks, u_blocks)
