@@ -80,6 +80,15 @@ __device__ __forceinline__ void st_pair(gptr<Pair<T>> p, int64_t i, float a, flo
     ((gptr<Vec2<T>>)p)[i] = v;
 }
 
+// Value of lane `src` (wave-uniform) of v.  Lanes past a volume edge store
+// the last in-volume lane's value to that lane's own element, so that a store
+// needs no per-lane guard: a store under a per-lane branch makes the compiler
+// wait for every load in flight at the branch's end.
+__device__ __forceinline__ float lane_value(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Make `v` opaque to the optimiser: it must be computed here, so a sum that
 // feeds a register ring is not sunk to its distant use (which would keep all
 // of its inputs live instead of one value).

@@ -31,7 +31,10 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     constexpr int NF = MODE == XY_ONE ? 1 : 2;
     constexpr int W = 2 * R + 1;
     constexpr int RW = 64 + 2 * R;
-    __shared__ float row[2][NF][RW];
+    static_assert(RW <= 128, "a staged row is two loads per lane");
+    // rows are written whole (128 entries, the tail past RW is never read)
+    // so that staging has no branch
+    __shared__ float row[2][NF][128];
 
     Where wh;
     if (!locate(bt, wh)) return;
@@ -51,9 +54,11 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     const int x0 = xs * 64, x = x0 + lane;
     const int64_t zb = (int64_t)z * g.sxy;
 
-    // A row's loads are issued one step before the row is staged, so the
-    // global latency overlaps the previous row's arithmetic.
-    // raw elements of one row (lanes j and j + 64), converted when staged
+    // Raw elements of one row (lanes j and j + 64), converted when staged.
+    // The loads are unconditional, with the row and column clamped into the
+    // slice; the zero padding is applied when the row is staged.  No load
+    // sits under a branch, so waiting for one row leaves later rows in
+    // flight.
     struct Raw {
         Vec2<IN> p[2];
         IN s[2];
@@ -65,36 +70,37 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         // uniform row bases, 32-bit lane offsets
         const int yy = min(max(y, 0), g.ny - 1);
         const int64_t rowo = zb + (int64_t)yy * g.nx;
-        const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            r.p[h] = Vec2<IN>{};
-            r.s[h] = IN{};
-            const int j = lane + 64 * h;
-            const int gx = x0 - R + j;
-            if (yok && j < RW && gx >= 0 && gx < g.nx) {
-                if (NF == 2) r.p[h] = ld_pair_raw<IN>(in2 + rowo, gx);
-                else r.s[h] = (in1 + rowo)[gx];
-            }
+            // lanes past the staged width load the last staged column: same
+            // cache line, no extra traffic
+            const int gx = min(max(x0 - R + min(lane + 64 * h, RW - 1), 0), g.nx - 1);
+            if (NF == 2) r.p[h] = ld_pair_raw<IN>(in2 + rowo, gx);
+            else r.s[h] = (in1 + rowo)[gx];
         }
         return r;
     };
-    // stage a fetched row into LDS slot `slot`, x-convolve it, return the lane's value
-    auto xrow = [&](const Raw &r, int slot) -> float2 {
+    // stage row y (fetched) into LDS slot `slot`, x-convolve it, return the
+    // lane's value
+    auto xrow = [&](const Raw &r, int y, int slot) -> float2 {
+        const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = lane + 64 * h;
-            if (j < RW) {
-                if (NF == 2) {
-                    row[slot][0][j] = to_f(r.p[h].x);
-                    row[slot][NF - 1][j] = to_f(r.p[h].y);
-                } else {
-                    const float v = to_f(r.s[h]);
-                    row[slot][0][j] = c.square ? v * v : v;
-                }
+            const int gx = x0 - R + j;
+            const bool ok = yok && gx >= 0 && gx < g.nx;
+            if (NF == 2) {
+                row[slot][0][j] = ok ? to_f(r.p[h].x) : 0.f;
+                row[slot][NF - 1][j] = ok ? to_f(r.p[h].y) : 0.f;
+            } else {
+                const float v = ok ? to_f(r.s[h]) : 0.f;
+                row[slot][0][j] = c.square ? v * v : v;
             }
         }
-        __syncthreads();
+        // the workgroup is one wave: order its LDS writes before the reads
+        // (a workgroup barrier's fence would also wait for the global stores
+        // and loads in flight)
+        __syncwarp();
         float ca = 0.f, cb = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
@@ -106,109 +112,132 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         return make_float2(ca, cb);
     };
 
-    float ra[W], rb[W];
-    Raw nxt = fetch(y0 - R);
-#pragma unroll
-    for (int j = 0; j < 2 * R; ++j) {
-        const Raw cur = nxt;
-        nxt = fetch(y0 - R + j + 1);
-        const float2 v = xrow(cur, j & 1);
-        ra[j] = v.x;
-        rb[j] = v.y;
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    float cxz = 0.f;
+    // Prefetch depth as in the update pass: two stages (a row and the
+    // pointwise inputs of one step) alternate by step parity where the
+    // registers allow, so the march is unrolled by an even M >= 2R + 1.
+    constexpr int PF = R <= 10 ? 2 : 1;
+    constexpr int M = PF == 2 ? W + 1 : W;
     const int xc = min(x, g.nx - 1);
+    const int last = min(63, g.nx - 1 - x0);   // last in-slice lane of the strip
     const gptr<const ST> ki_slice = glb(static_cast<const ST *>(d.KI)) + zb;
     const gptr<const IMG> im_slice = glb(static_cast<const IMG *>(d.I)) + zb;
     const gptr<const ST> k2i_slice = glb(static_cast<const ST *>(d.K2I)) + zb;
     const gptr<const ST> k2q_slice = glb(static_cast<const ST *>(d.K2I2)) + zb;
     const gptr<const float> cyp = glb(d.cy);
-    if (FITS) cxz = glb(d.cx)[xc] * glb(d.cz)[z];
-    ST ki_next = FITS ? ki_slice[y0 * g.nx + xc] : ST{};
-    IMG im_next = MODE == XY_PAPER ? im_slice[y0 * g.nx + xc] : IMG{};
-    ST k2i_next = MODE == XY_PAPER2 ? k2i_slice[y0 * g.nx + xc] : ST{};
-    ST k2q_next = MODE == XY_PAPER2 ? k2q_slice[y0 * g.nx + xc] : ST{};
-    float cy_next = FITS ? cyp[y0] : 0.f;
+    const float cxz = FITS ? glb(d.cx)[xc] * glb(d.cz)[z] : 0.f;
+    // the loads of step y: row y + R and the fits' pointwise inputs of row y
+    struct Stage {
+        Raw row;
+        ST ki, k2i, k2q;
+        IMG im;
+        float cy;
+    };
+    auto stage = [&](int y) {
+        Stage st;
+        st.row = fetch(y + R);
+        if (FITS) {
+            const int yy = min(y, g.ny - 1);
+            const int o = yy * g.nx + xc;
+            st.ki = ki_slice[o];
+            st.cy = cyp[yy];
+            if (MODE == XY_PAPER) st.im = im_slice[o];
+            if (MODE == XY_PAPER2) {
+                st.k2i = k2i_slice[o];
+                st.k2q = k2q_slice[o];
+            }
+        }
+        return st;
+    };
+
+    float ra[M], rb[M];
+    Stage sa, sb;
+    {
+        Raw nxt = fetch(y0 - R);
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) {
+            const Raw cur = nxt;
+            if (j + 1 < 2 * R) {
+                nxt = fetch(y0 - R + j + 1);
+            } else {
+                sa = stage(y0);
+                if (PF == 2) sb = stage(y0 + 1);
+            }
+            const float2 v = xrow(cur, y0 - R + j, j & 1);
+            ra[j] = v.x;
+            rb[j] = v.y;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
     const gptr<float> probe_f1 = glb(d.probe_f1), probe_f2 = glb(d.probe_f2),
                       probe_fd = glb(d.probe_Fd);
     const gptr<ST> o1_s = glb(static_cast<ST *>(out_)) + zb;
     const gptr<Pair<ST>> o2_s = glb(static_cast<Pair<ST> *>(out_)) + zb;
     const gptr<float> of_s = glb(static_cast<float *>(out_)) + zb;
-    for (int yb = y0; yb < y1; yb += W) {
+    // step y (s = its index in the unrolled block) consumes stage `cur` and
+    // refills it with the loads of step y + PF
+    auto step = [&](Stage &cur, const int s, const int y) {
+        const Raw rw = cur.row;
+        const ST ki_raw = cur.ki, k2i_raw = cur.k2i, k2q_raw = cur.k2q;
+        const IMG im_raw = cur.im;
+        const float cyv = cur.cy;
+        // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
+        const float2 xv = xrow(rw, y + R, (y - y0) & 1);
+        cur = stage(y + PF);
+        ra[(s + 2 * R) % M] = xv.x;
+        rb[(s + 2 * R) % M] = xv.y;
+        float acc_a = 0.f, acc_b = 0.f;
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
+        for (int k = 0; k < W; ++k) {
+            acc_a = fmaf(t.w[k], ra[(s + k) % M], acc_a);
+            if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % M], acc_b);
+        }
+        // every lane stores: one past the slice edge (x >= nx) writes the
+        // value of the last in-slice lane to that lane's element (same bits)
+        const int v = y * g.nx + xc;     // offset within the slice
+        auto edge = [&](float val) { return x < g.nx ? val : lane_value(val, last); };
+        if (FITS) {
+            const float ki = to_f(ki_raw);
+            // region fits (Sec. 3 local_intensity)
+            const float K1 = cxz * cyv;
+            const float A2 = ki - acc_a;
+            const float B2 = K1 - acc_b;
+            const float f1 = acc_a * rcp(acc_b);
+            const float f2 = A2 * rcp(B2);
+            if (MODE == XY_PAPER) {
+                // F+- = (I - r+-)^2 (Sec. 4.2 expansion, sigma2 = 0)
+                const float im = to_f(im_raw);
+                const float d1 = im - f1, d2 = im - f2;
+                const float Fd = edge(c.l1 * d1 * d1 - c.l2 * d2 * d2);
+                of_s[v] = Fd;
+                if (probe_fd) probe_fd[zb + v] = Fd;
+            } else if (MODE == XY_PAPER2) {
+                // F+- = K2*I^2 - 2 r+- K2*I + r+-^2 (Sec. 4.2 expansion)
+                const float a = to_f(k2i_raw), q = to_f(k2q_raw);
+                const float F1 = q - 2.f * f1 * a + f1 * f1;
+                const float F2 = q - 2.f * f2 * a + f2 * f2;
+                const float Fd = edge(c.l1 * F1 - c.l2 * F2);
+                of_s[v] = Fd;
+                if (probe_fd) probe_fd[zb + v] = Fd;
+            } else {
+                // force-convolution inputs g1, g2
+                st_pair<ST>(o2_s, v, edge(c.l1 * f1 - c.l2 * f2),
+                            edge(c.l1 * f1 * f1 - c.l2 * f2 * f2));
+            }
+            if (probe_f1) probe_f1[zb + v] = edge(f1);
+            if (probe_f2) probe_f2[zb + v] = edge(f2);
+        } else if (NF == 2) {
+            st_pair<ST>(o2_s, v, edge(acc_a), edge(acc_b));
+        } else {
+            o1_s[v] = from_f<ST>(edge(acc_a));
+        }
+    };
+    for (int yb = y0; yb < y1; yb += M) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
             const int y = yb + s;
             if (y < y1) {
-                const Raw cur = nxt;
-                nxt = fetch(y + R + 1);
-                float ki = 0.f, cyv = 0.f, im = 0.f;
-                ST ki_raw = ST{}, k2i_raw = ST{}, k2q_raw = ST{};
-                IMG im_raw = IMG{};
-                if (FITS) {
-                    ki_raw = ki_next;
-                    cyv = cy_next;
-                    im_raw = im_next;
-                    k2i_raw = k2i_next;
-                    k2q_raw = k2q_next;
-                    if (y + 1 < y1) {
-                        ki_next = ki_slice[(y + 1) * g.nx + xc];
-                        cy_next = cyp[y + 1];
-                        if (MODE == XY_PAPER) im_next = im_slice[(y + 1) * g.nx + xc];
-                        if (MODE == XY_PAPER2) {
-                            k2i_next = k2i_slice[(y + 1) * g.nx + xc];
-                            k2q_next = k2q_slice[(y + 1) * g.nx + xc];
-                        }
-                    }
-                }
-                // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
-                const float2 v = xrow(cur, (y - y0) & 1);
-                ra[(s + 2 * R) % W] = v.x;
-                rb[(s + 2 * R) % W] = v.y;
-                float acc_a = 0.f, acc_b = 0.f;
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    acc_a = fmaf(t.w[k], ra[(s + k) % W], acc_a);
-                    if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % W], acc_b);
-                }
-                if (x < g.nx) {
-                    const int v = y * g.nx + x;      // offset within the slice
-                    if (FITS) {
-                        ki = to_f(ki_raw);
-                        im = to_f(im_raw);
-                        // region fits (Sec. 3 local_intensity)
-                        const float K1 = cxz * cyv;
-                        const float A2 = ki - acc_a;
-                        const float B2 = K1 - acc_b;
-                        const float f1 = acc_a * rcp(acc_b);
-                        const float f2 = A2 * rcp(B2);
-                        if (MODE == XY_PAPER) {
-                            // F+- = (I - r+-)^2 (Sec. 4.2 expansion, sigma2 = 0)
-                            const float d1 = im - f1, d2 = im - f2;
-                            const float Fd = c.l1 * d1 * d1 - c.l2 * d2 * d2;
-                            of_s[v] = Fd;
-                            if (probe_fd) probe_fd[zb + v] = Fd;
-                        } else if (MODE == XY_PAPER2) {
-                            // F+- = K2*I^2 - 2 r+- K2*I + r+-^2 (Sec. 4.2 expansion)
-                            const float a = to_f(k2i_raw), q = to_f(k2q_raw);
-                            const float F1 = q - 2.f * f1 * a + f1 * f1;
-                            const float F2 = q - 2.f * f2 * a + f2 * f2;
-                            const float Fd = c.l1 * F1 - c.l2 * F2;
-                            of_s[v] = Fd;
-                            if (probe_fd) probe_fd[zb + v] = Fd;
-                        } else {
-                            // force-convolution inputs g1, g2
-                            st_pair<ST>(o2_s, v, c.l1 * f1 - c.l2 * f2,
-                                        c.l1 * f1 * f1 - c.l2 * f2 * f2);
-                        }
-                        if (probe_f1) probe_f1[zb + v] = f1;
-                        if (probe_f2) probe_f2[zb + v] = f2;
-                    } else if (NF == 2) {
-                        st_pair<ST>(o2_s, v, acc_a, acc_b);
-                    } else {
-                        o1_s[v] = from_f<ST>(acc_a);
-                    }
-                }
+                if (PF == 2 && (s & 1)) step(sb, s, y);
+                else step(sa, s, y);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -425,13 +454,16 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             float v[NLD];
         };
         // Slices used for outputs lie in [-2, nz + 1]; the march also touches
-        // up to nz + 3 (prefetch and n, V past the chunk end, never used), so
+        // up to nz + 4 (prefetch and n, V past the chunk end, never used), so
         // clamp before reflecting to keep every address inside the volume.
+        // Lanes past the tile (!lok) load a reflected in-volume point too and
+        // drop it: every prefetch is an unconditional load, so no branch
+        // forces a wait on the loads in flight.
         auto fetch_phi = [&](int j) {
             PhiRaw r;
             const gptr<const float> base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
 #pragma unroll
-            for (int k = 0; k < NLD; ++k) r.v[k] = lok[k] ? base[loff[k]] : 0.f;
+            for (int k = 0; k < NLD; ++k) r.v[k] = base[loff[k]];
             return r;
         };
         auto phi_slot = [&](int j) { return sphi[(j + 2 * NPHI) % NPHI]; };
@@ -494,8 +526,15 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         q_phase(z0, nz0, vz0);
         q_phase(z0 + 1, nzp, vzp);
 
+        // Prefetch depth: two stages of loads in flight where the registers
+        // allow (the conv ring grows with R).  The two stage buffers
+        // alternate by step parity, never copied (a copy of registers whose
+        // loads are in flight would wait for them), so the march is unrolled
+        // by an even count M and the conv ring has M >= 2R + 1 slots.
         constexpr int W = 2 * R + 1;
-        float ra[W], rb[W];
+        constexpr int PF = R <= 10 ? 2 : 1;
+        constexpr int M = PF == 2 ? W + 1 : W;
+        float ra[M], rb[M];
         if constexpr (!PAPER) {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) {
@@ -506,83 +545,102 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             }
         }
         __builtin_amdgcn_sched_barrier(0);
-        // one-step-ahead prefetch of the next phi slice, conv inputs and image
-        // (PAPER: the force field instead)
+        // A stage holds the loads of one step: the phi slice, the conv
+        // inputs, the image (PAPER: the force field instead) and the z edge
+        // factor.  The loads are unconditional with indices clamped into the
+        // volume (a clamped conv input is replaced by the zero padding when
+        // it enters the ring), so no load sits under a branch and the wait
+        // for the oldest stage leaves the newer one in flight.
+        const int zmax = g.nz - 1;
         const gptr<const float> fdp = glb(static_cast<const float *>(d.Q));
-        PhiRaw phi_nxt = fetch_phi(z0 + 3);
-        Vec2<ST> t_nxt{};
-        if constexpr (!PAPER) t_nxt = z0 + R < g.nz ? pair_at(z0 + R) : Vec2<ST>{};
-        // raw image (PAPER: the float force), converted where used
         using IRaw = typename std::conditional<PAPER, float, IT>::type;
         const gptr<const IRaw> ip = PAPER ? (gptr<const IRaw>)fdp : (gptr<const IRaw>)img;
         auto iraw = [&](int z) { return (ip + (int64_t)z * g.sxy)[col]; };
-        IRaw I_nxt = z0 < zt.z1 ? iraw(z0) : IRaw{};
-        for (int zb = z0; zb < zt.z1; zb += W) {
+        struct Stage {
+            PhiRaw phi;    // phi slice z + 3
+            Vec2<ST> t;    // conv inputs of slice z + R
+            IRaw I;        // image (PAPER: F_d) of slice z
+            float cz;      // z edge factor of slice z
+        };
+        auto stage = [&](int z) {
+            Stage st;
+            st.phi = fetch_phi(z + 3);
+            if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
+            st.I = iraw(min(z, zmax));
+            st.cz = PAPER ? 0.f : czp[min(z, zmax)];
+            return st;
+        };
+        Stage sa = stage(z0), sb{};
+        if constexpr (PF == 2) sb = stage(z0 + 1);
+        // step z (s = its index in the unrolled block) consumes stage `cur`
+        // and refills it with the loads of step z + PF
+        auto step = [&](Stage &cur, const int s, const int z) {
+            store_phi(cur.phi, z + 3);
+            if constexpr (!PAPER) {
+                const bool in = z + R < g.nz;   // zero padding past the volume
+                ra[(s + 2 * R) % M] = in ? to_f(cur.t.x) : 0.f;
+                rb[(s + 2 * R) % M] = in ? to_f(cur.t.y) : 0.f;
+            }
+            const IRaw I_cur = cur.I;   // PAPER: F_d of slice z
+            const float cz_cur = cur.cz;
+            cur = stage(z + PF);
+            __syncthreads();
+            float nzpp, vzpp;
+            q_phase(z + 2, nzpp, vzpp);
+            float KG1 = 0.f, KG2 = 0.f;
+            if constexpr (!PAPER) {
 #pragma unroll
-            for (int s = 0; s < W; ++s) {
+                for (int k = 0; k < W; ++k) {
+                    KG1 = fmaf(t.w[k], ra[(s + k) % M], KG1);
+                    KG2 = fmaf(t.w[k], rb[(s + k) % M], KG2);
+                }
+            }
+            if (zt.active) {
+                const int64_t zo = (int64_t)z * g.sxy;
+                const float *p0 = phi_slot(z), *pm = phi_slot(z - 1), *pp = phi_slot(z + 1);
+                const int c = (ty + 2) * PX + tx + 2;
+                const float cphi = p0[c];
+                const float lap = p0[c + 1] + p0[c - 1] + p0[c + PX] + p0[c - PX] + pp[c] + pm[c] -
+                                  6.f * cphi;
+                const float *q = &sq[(z + 2 * NQ) % NQ][0][0];
+                const int o = own_q;
+                const float kappa = 0.5f * (q[o + 1] - q[o - 1]) +
+                                    0.5f * (q[2 * QS + o + QX] - q[2 * QS + o - QX]) +
+                                    0.5f * (nzp - nzm);
+                const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
+                                   0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
+                                   0.5f * (vzp - vzm);
+                const float Iv = to_f(I_cur);
+                float Fd;
+                if constexpr (PAPER) {
+                    Fd = Iv;
+                } else {
+                    const float K1 = cxy * cz_cur;
+                    Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
+                }
+                const float Rt = lap + divV;
+                const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
+                const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
+                const float nxt = cphi + ua.dt * E;
+                (phi_out + zo)[col] = nxt;
+                acc += fabs((double)nxt - (double)cphi);
+                if (PROBE) {
+                    if (d.probe_Fd) (glb(d.probe_Fd) + zo)[col] = Fd;
+                    if (d.probe_kappa) (glb(d.probe_kappa) + zo)[col] = kappa;
+                    if (d.probe_lap) (glb(d.probe_lap) + zo)[col] = lap;
+                    if (d.probe_R) (glb(d.probe_R) + zo)[col] = Rt;
+                    if (d.probe_E) (glb(d.probe_E) + zo)[col] = E;
+                }
+            }
+            nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
+        };
+        for (int zb = z0; zb < zt.z1; zb += M) {
+#pragma unroll
+            for (int s = 0; s < M; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
-                    store_phi(phi_nxt, z + 3);
-                    if constexpr (!PAPER) {
-                        ra[(s + 2 * R) % W] = to_f(t_nxt.x);
-                        rb[(s + 2 * R) % W] = to_f(t_nxt.y);
-                    }
-                    const IRaw I_cur = I_nxt;   // PAPER: F_d of slice z
-                    phi_nxt = fetch_phi(z + 4);
-                    if constexpr (!PAPER) {
-                        const int zn = z + R + 1;
-                        t_nxt = zn < g.nz ? pair_at(zn) : Vec2<ST>{};
-                    }
-                    if (z + 1 < zt.z1) I_nxt = iraw(z + 1);
-                    __syncthreads();
-                    float nzpp, vzpp;
-                    q_phase(z + 2, nzpp, vzpp);
-                    float KG1 = 0.f, KG2 = 0.f;
-                    if constexpr (!PAPER) {
-#pragma unroll
-                        for (int k = 0; k < W; ++k) {
-                            KG1 = fmaf(t.w[k], ra[(s + k) % W], KG1);
-                            KG2 = fmaf(t.w[k], rb[(s + k) % W], KG2);
-                        }
-                    }
-                    if (zt.active) {
-                        const int64_t zo = (int64_t)z * g.sxy;
-                        const float *p0 = phi_slot(z), *pm = phi_slot(z - 1), *pp = phi_slot(z + 1);
-                        const int c = (ty + 2) * PX + tx + 2;
-                        const float cphi = p0[c];
-                        const float lap = p0[c + 1] + p0[c - 1] + p0[c + PX] + p0[c - PX] +
-                                          pp[c] + pm[c] - 6.f * cphi;
-                        const float *q = &sq[(z + 2 * NQ) % NQ][0][0];
-                        const int o = own_q;
-                        const float kappa = 0.5f * (q[o + 1] - q[o - 1]) +
-                                            0.5f * (q[2 * QS + o + QX] - q[2 * QS + o - QX]) +
-                                            0.5f * (nzp - nzm);
-                        const float divV = 0.5f * (q[QS + o + 1] - q[QS + o - 1]) +
-                                           0.5f * (q[3 * QS + o + QX] - q[3 * QS + o - QX]) +
-                                           0.5f * (vzp - vzm);
-                        const float Iv = to_f(I_cur);
-                        float Fd;
-                        if constexpr (PAPER) {
-                            Fd = Iv;
-                        } else {
-                            const float K1 = cxy * czp[z];
-                            Fd = (ua.l1 - ua.l2) * Iv * Iv * K1 - 2.f * Iv * KG1 + KG2;
-                        }
-                        const float Rt = lap + divV;
-                        const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
-                        const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
-                        const float nxt = cphi + ua.dt * E;
-                        (phi_out + zo)[col] = nxt;
-                        acc += fabs((double)nxt - (double)cphi);
-                        if (PROBE) {
-                            if (d.probe_Fd) (glb(d.probe_Fd) + zo)[col] = Fd;
-                            if (d.probe_kappa) (glb(d.probe_kappa) + zo)[col] = kappa;
-                            if (d.probe_lap) (glb(d.probe_lap) + zo)[col] = lap;
-                            if (d.probe_R) (glb(d.probe_R) + zo)[col] = Rt;
-                            if (d.probe_E) (glb(d.probe_E) + zo)[col] = E;
-                        }
-                    }
-                    nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
+                    if (PF == 2 && (s & 1)) step(sb, s, z);
+                    else step(sa, s, z);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
