@@ -275,8 +275,9 @@ rsf_status rsf_seeds(rsf_context *ctx, const void *volume, int volume_dtype, int
 /* Fast sweeping (Zhao 2005) in place: u (device floats) holds 0 at the
  * seeds and a large value (1e30) elsewhere; `rounds` repetitions of the
  * eight Gauss-Seidel sweep orderings of the Godunov upwind discretisation of
- * |grad u| = 1 on the unit grid.  Each sweep runs hyperplane by hyperplane,
- * which gives the same updates as the sequential sweep.  One round reaches
+ * |grad u| = 1 on the unit grid.  Each sweep runs over hyperplanes of
+ * 32x8x8 blocks (each block swept in LDS along its own hyperplanes), which
+ * gives the same updates as the sequential sweep.  One round reaches
  * the discrete solution for a single seed; several seeds can need a second
  * (first-round differences of order 1e-4). */
 rsf_status rsf_fast_sweep(rsf_context *ctx, float *u, int64_t nx, int64_t ny, int64_t nz,
@@ -320,7 +321,13 @@ typedef enum {
     RSF_PASS_XY_FORCE = 3,     /* xy Gaussian of (g1, g2)                     */
     RSF_PASS_Z_UPDATE = 4,     /* z Gaussian + force, curvature, update       */
     RSF_PASS_REDUCE = 5,       /* FP64 sum |dphi|                             */
-    RSF_PASS_COUNT = 6
+    /* initialisation (Sec. 4.3) */
+    RSF_PASS_INIT_SMOOTH = 6,  /* x or y pass of the slice Gaussian           */
+    RSF_PASS_INIT_HESSIAN = 7, /* determinant and trace, and their maximum    */
+    RSF_PASS_INIT_SELECT = 8,  /* seed selection, initial distance field      */
+    RSF_PASS_INIT_SWEEP = 9,   /* one hyperplane of blocks of a fast sweep    */
+    RSF_PASS_INIT_OFFSET = 10, /* phi0 = offset - distance                    */
+    RSF_PASS_COUNT = 11
 } rsf_pass;
 
 typedef struct {

@@ -1055,11 +1055,23 @@ rsf_status seeds_impl(rsf_context *ctx, Scratch &sc, const void *volume, int vdt
     HIP_TRY(sc.get(&cnt, 65536 * 4), "hipMalloc(seed scratch)");
     int blocks = 0;
     // L = 2D Gaussian of each slice (A: x pass, B: y pass); doh into A
-    HIP_TRY(rsf::launch_smooth_x(volume, vdt, A, nx, ny, nz, t, R, s), "smooth x");
-    HIP_TRY(rsf::launch_smooth_y(A, B, nx, ny, nz, t, R, s), "smooth y");
-    HIP_TRY(rsf::launch_hessian(B, A, tr, part, nx, ny, nz, &blocks, s), "hessian");
-    HIP_TRY(rsf::launch_max(part, blocks, mx, s), "max");
-    HIP_TRY(rsf::launch_seeds(A, tr, mx, threshold, mask, u, cnt, nx, ny, nz, s), "seeds");
+    HIP_TRY(timed(ctx, RSF_PASS_INIT_SMOOTH, s,
+                  [&] { return rsf::launch_smooth_x(volume, vdt, A, nx, ny, nz, t, R, s); }),
+            "smooth x");
+    HIP_TRY(timed(ctx, RSF_PASS_INIT_SMOOTH, s,
+                  [&] { return rsf::launch_smooth_y(A, B, nx, ny, nz, t, R, s); }),
+            "smooth y");
+    HIP_TRY(timed(ctx, RSF_PASS_INIT_HESSIAN, s,
+                  [&] {
+                      const hipError_t e = rsf::launch_hessian(B, A, tr, part, nx, ny, nz, &blocks, s);
+                      return e != hipSuccess ? e : rsf::launch_max(part, blocks, mx, s);
+                  }),
+            "hessian");
+    HIP_TRY(timed(ctx, RSF_PASS_INIT_SELECT, s,
+                  [&] {
+                      return rsf::launch_seeds(A, tr, mx, threshold, mask, u, cnt, nx, ny, nz, s);
+                  }),
+            "seeds");
     if (n_seeds) {
         std::vector<unsigned> h((size_t)blocks);
         HIP_TRY(hipMemcpyAsync(h.data(), cnt, (size_t)blocks * 4, hipMemcpyDeviceToHost, s),
@@ -1075,10 +1087,13 @@ rsf_status seeds_impl(rsf_context *ctx, Scratch &sc, const void *volume, int vdt
 rsf_status sweep_impl(rsf_context *ctx, float *u, int64_t nx, int64_t ny, int64_t nz, int rounds,
                       hipStream_t s)
 {
+    const int64_t planes = rsf::sweep_block_planes(nx, ny, nz);
     for (int r = 0; r < rounds; ++r)
         for (int dir = 0; dir < 8; ++dir)
-            for (int64_t h = 0; h <= nx + ny + nz - 3; ++h)
-                HIP_TRY(rsf::launch_sweep_plane(u, nx, ny, nz, dir, h, s), "sweep");
+            for (int64_t h = 0; h < planes; ++h)
+                HIP_TRY(timed(ctx, RSF_PASS_INIT_SWEEP, s,
+                              [&] { return rsf::launch_sweep_blocks(u, nx, ny, nz, dir, h, s); }),
+                        "sweep");
     return RSF_OK;
 }
 
@@ -1159,7 +1174,9 @@ rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, 
         if (count == 0) return fail(ctx, RSF_ERR_INVALID_ARG, "no seed found (lower threshold)");
         st = sweep_impl(ctx, u, nx, ny, nz, rounds, s);
         if (st != RSF_OK) return st;
-        HIP_TRY(rsf::launch_offset(u, phi, n, offset, s), "offset");
+        HIP_TRY(timed(ctx, RSF_PASS_INIT_OFFSET, s,
+                      [&] { return rsf::launch_offset(u, phi, n, offset, s); }),
+                "offset");
         HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
         return RSF_OK;
     } catch (...) {

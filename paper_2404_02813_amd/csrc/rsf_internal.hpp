@@ -204,10 +204,12 @@ hipError_t launch_max(const float *part, int n, float *out, hipStream_t s);
 hipError_t launch_seeds(const float *doh, const float *tr, const float *maxv, float threshold,
                         unsigned char *mask, float *u, unsigned *cnt, int64_t nx, int64_t ny,
                         int64_t nz, hipStream_t s);
-// one hyperplane i' + j' + k' = h of the sweep with axis orders dir (bit 0:
-// x descending, bit 1: y, bit 2: z)
-hipError_t launch_sweep_plane(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t h,
-                              hipStream_t s);
+// Fast sweeping by hyperplanes of blocks: a sweep with axis orders dir (bit
+// 0: x descending, bit 1: y, bit 2: z) is sweep_block_planes() launches of
+// launch_sweep_blocks with H = 0, 1, ...
+int64_t sweep_block_planes(int64_t nx, int64_t ny, int64_t nz);
+hipError_t launch_sweep_blocks(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t H,
+                               hipStream_t s);
 // phi = offset - u
 hipError_t launch_offset(const float *u, float *phi, int64_t n, float offset, hipStream_t s);
 

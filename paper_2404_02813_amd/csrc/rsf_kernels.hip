@@ -307,37 +307,83 @@ __device__ __forceinline__ float godunov(float a, float b, float c)
     return a + (d1 + d2 + sqrtf(3.f - (d1 * d1 + d2 * d2 + d3 * d3))) * (1.f / 3.f);
 }
 
-// One hyperplane of a sweep: the points with i' + j' + k' = h, where i' = i
-// or nx-1-i by the sweep's x order (likewise j', k').  Every point of a
-// hyperplane depends only on earlier hyperplanes in this sweep's order, so
-// hyperplane by hyperplane gives the same updates as the sequential sweep.
-// Thread (jj, kk) of the grid covers j' = jlo(k') + jj, k' = klo + kk.
-__global__ __launch_bounds__(kThreads) void sweep_plane_kernel(float *up, int64_t nx, int64_t ny,
-                                                               int64_t nz, int dir, int64_t h,
-                                                               int64_t klo, int64_t kcount)
+// One hyperplane of blocks of a sweep.  In the sweep's orientation
+// (i' = i or nx-1-i by its x order, likewise j', k') the volume is cut into
+// blocks of kSbx x kSby x kSbz; the blocks with bi' + bj' + bk' = H are
+// independent: a block's upwind neighbours (i'-1, j'-1, k'-1 across a face)
+// lie in blocks of hyperplane H-1, already swept, and its downwind ones in
+// hyperplane H+1, not yet.  One wave loads its block with a one-voxel face
+// halo into LDS (absent points as kFar), marches the block's own inner
+// hyperplanes in order (lane = one (j', k') line) and writes the block back.
+// Every point is thus updated after its upwind neighbours and before its
+// downwind ones, which gives exactly the sequential Gauss-Seidel sweep.
+// Workgroup g covers bj' = g % nby, bk' = kblo + g / nby.
+constexpr int kSbx = 32, kSby = 8, kSbz = 8;
+static_assert(kSby * kSbz == 64, "one lane per (j', k') line of a block");
+__global__ __launch_bounds__(64) void sweep_block_kernel(float *up, int64_t nx, int64_t ny,
+                                                         int64_t nz, int dir, int64_t H,
+                                                         int64_t nbx, int64_t nby, int64_t kblo)
 {
-    const int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-    const int64_t jspan = ny;
-    if (t >= jspan * kcount) return;
-    const int64_t kp = klo + t / jspan;
-    const int64_t jp = t % jspan;
-    const int64_t ip = h - jp - kp;
-    if (ip < 0 || ip >= nx) return;
-    const int64_t i = (dir & 1) ? nx - 1 - ip : ip;
-    const int64_t j = (dir & 2) ? ny - 1 - jp : jp;
-    const int64_t k = (dir & 4) ? nz - 1 - kp : kp;
+    constexpr int TX = kSbx + 2, TY = kSby + 2, TZ = kSbz + 2;
+    __shared__ float tile[TZ][TY][TX];
+    const int64_t gb = blockIdx.x;
+    const int64_t bj = gb % nby, bk = kblo + gb / nby;
+    const int64_t bi = H - bj - bk;
+    if (bi < 0 || bi >= nbx) return;   // the whole workgroup
     const gptr<float> u = glb(up);
-    const int64_t p = (k * ny + j) * nx + i;
-    float a = kFar, b = kFar, c = kFar;
-    if (i > 0) a = u[p - 1];
-    if (i < nx - 1) a = fminf(a, u[p + 1]);
-    if (j > 0) b = u[p - nx];
-    if (j < ny - 1) b = fminf(b, u[p + nx]);
-    if (k > 0) c = u[p - nx * ny];
-    if (k < nz - 1) c = fminf(c, u[p + nx * ny]);
-    if (a >= kFar && b >= kFar && c >= kFar) return;
-    const float v = godunov(a, b, c);
-    if (v < u[p]) u[p] = v;
+    const int lane = threadIdx.x;
+    const int64_t i0 = bi * kSbx, j0 = bj * kSby, k0 = bk * kSbz;   // oriented origin
+    // global index of oriented point (ip, jp, kp), all inside the volume
+    auto gidx = [&](int64_t ip, int64_t jp, int64_t kp) {
+        const int64_t i = (dir & 1) ? nx - 1 - ip : ip;
+        const int64_t j = (dir & 2) ? ny - 1 - jp : jp;
+        const int64_t k = (dir & 4) ? nz - 1 - kp : kp;
+        return (k * ny + j) * nx + i;
+    };
+    // all loads issued before any is used (clamped into the volume, so none
+    // sits under a branch), then staged with the absent points set to kFar
+    constexpr int NL = (TX * TY * TZ + 63) / 64;
+    float v[NL];
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int c = min(lane + 64 * r, TX * TY * TZ - 1);
+        const int lx = c % TX, ly = (c / TX) % TY, lz = c / (TX * TY);
+        const int64_t ip = min(max(i0 - 1 + lx, (int64_t)0), nx - 1);
+        const int64_t jp = min(max(j0 - 1 + ly, (int64_t)0), ny - 1);
+        const int64_t kp = min(max(k0 - 1 + lz, (int64_t)0), nz - 1);
+        v[r] = u[gidx(ip, jp, kp)];
+    }
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+        const int c = lane + 64 * r;
+        if (c < TX * TY * TZ) {
+            const int lx = c % TX, ly = (c / TX) % TY, lz = c / (TX * TY);
+            const int64_t ip = i0 - 1 + lx, jp = j0 - 1 + ly, kp = k0 - 1 + lz;
+            const bool in = ip >= 0 && ip < nx && jp >= 0 && jp < ny && kp >= 0 && kp < nz;
+            (&tile[0][0][0])[c] = in ? v[r] : kFar;
+        }
+    }
+    __syncwarp();
+    const int ly = 1 + lane % kSby, lz = 1 + lane / kSby;
+    const bool line_in = j0 + ly - 1 < ny && k0 + lz - 1 < nz;
+    for (int s = 0; s < kSbx + kSby + kSbz - 2; ++s) {
+        const int lx = 1 + s - (ly - 1) - (lz - 1);
+        if (line_in && lx >= 1 && lx <= kSbx && i0 + lx - 1 < nx) {
+            const float a = fminf(tile[lz][ly][lx - 1], tile[lz][ly][lx + 1]);
+            const float b = fminf(tile[lz][ly - 1][lx], tile[lz][ly + 1][lx]);
+            const float c = fminf(tile[lz - 1][ly][lx], tile[lz + 1][ly][lx]);
+            if (!(a >= kFar && b >= kFar && c >= kFar)) {
+                const float v = godunov(a, b, c);
+                if (v < tile[lz][ly][lx]) tile[lz][ly][lx] = v;
+            }
+        }
+        __syncwarp();
+    }
+    for (int c = lane; c < kSbx * kSby * kSbz; c += 64) {
+        const int lx = c % kSbx, ly2 = (c / kSbx) % kSby, lz2 = c / (kSbx * kSby);
+        const int64_t ip = i0 + lx, jp = j0 + ly2, kp = k0 + lz2;
+        if (ip < nx && jp < ny && kp < nz) u[gidx(ip, jp, kp)] = tile[lz2 + 1][ly2 + 1][lx + 1];
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void offset_kernel(const float *u, float *phi, int64_t n,
@@ -436,18 +482,23 @@ hipError_t launch_seeds(const float *doh, const float *tr, const float *maxv, fl
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_plane(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t h,
-                              hipStream_t s)
+int64_t sweep_block_planes(int64_t nx, int64_t ny, int64_t nz)
 {
-    // k' runs over the values for which some (i', j') completes the plane
-    const int64_t klo = std::max<int64_t>(0, h - (nx - 1) - (ny - 1));
-    const int64_t khi = std::min<int64_t>(nz - 1, h);
+    return (nx + kSbx - 1) / kSbx + (ny + kSby - 1) / kSby + (nz + kSbz - 1) / kSbz - 2;
+}
+
+hipError_t launch_sweep_blocks(float *u, int64_t nx, int64_t ny, int64_t nz, int dir, int64_t H,
+                               hipStream_t s)
+{
+    const int64_t nbx = (nx + kSbx - 1) / kSbx, nby = (ny + kSby - 1) / kSby,
+                  nbz = (nz + kSbz - 1) / kSbz;
+    // bk' runs over the values for which some (bi', bj') completes the plane
+    const int64_t klo = std::max<int64_t>(0, H - (nbx - 1) - (nby - 1));
+    const int64_t khi = std::min<int64_t>(nbz - 1, H);
     if (khi < klo) return hipSuccess;
-    const int64_t kcount = khi - klo + 1;
-    const int64_t n = ny * kcount;
-    const int64_t g = (n + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(sweep_plane_kernel, dim3((unsigned)g), dim3(kThreads), 0, s, u, nx, ny, nz,
-                       dir, h, klo, kcount);
+    const int64_t g = nby * (khi - klo + 1);
+    hipLaunchKernelGGL(sweep_block_kernel, dim3((unsigned)g), dim3(64), 0, s, u, nx, ny, nz, dir,
+                       H, nbx, nby, klo);
     return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
 
-PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce")
+PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce",
+              "init_smooth", "init_hessian", "init_select", "init_sweep", "init_offset")
 
 
 class RsfError(RuntimeError):
@@ -73,7 +74,8 @@ class rsf_tile(ctypes.Structure):
 
 
 class rsf_profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int * 6), ("ms", ctypes.c_double * 6)]
+    _fields_ = [("launches", ctypes.c_int * len(PASS_NAMES)),
+                ("ms", ctypes.c_double * len(PASS_NAMES))]
 
 
 RSF_ORDER_ARRIVAL = 0
