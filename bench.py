@@ -65,8 +65,9 @@ def workloads():
         big.name + "_u16_f16_paper": (big, "u16", "f16", "paper"),
     }
 
-KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hip",
-                  "paper_2404_02813_amd/csrc/rsf_kernels.hpp",
+# the sources that define the four pass kernels (their launch dispatch and
+# the set-up, reduction and initialisation kernels live elsewhere)
+KERNEL_SOURCES = ["paper_2404_02813_amd/csrc/rsf_kernels.hpp",
                   "paper_2404_02813_amd/csrc/rsf_device.hpp",
                   "paper_2404_02813_amd/csrc/rsf_internal.hpp"]
 
