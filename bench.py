@@ -316,7 +316,7 @@ def run_tiles(args, w) -> int:
         "autotune_s": round(t_tune, 2),
         "autotune_targets": list(chosen),
         "batch_equals_loop_bitwise": bool(same),
-        "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
+        "passes_ms_per_launch": {k: round(v[1] / v[0], 4) for k, v in prof.items() if v[0]},
         "copy_gbs": round(copy_gbs, 1),
         "finite": ok,
         "input_gen_s": round(t_gen, 1),
@@ -347,16 +347,20 @@ def run_volume(args, w, block: int) -> int:
     phi0 = torch.from_numpy(phi0_host).cuda()
     params = rsf.make_params(**w.params())
     ctx = rsf.Context(0)
+    R = int(np.ceil(3 * w.sigma - 1e-9))
     for _ in range(W):
         ph = phi0.clone()
         ctx.evolve_volume(vol, ph, params, w.iters, block)
     phis = [phi0.clone() for _ in range(K)]
     torch.cuda.synchronize()
+    ctx.profile(True)
     t0 = time.perf_counter()
     for ph in phis:
         ctx.evolve_volume(vol, ph, params, w.iters, block)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    prof = ctx.profile_read()
     plain = phi0.clone()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -365,7 +369,11 @@ def run_volume(args, w, block: int) -> int:
     t_plain = time.perf_counter() - t1
     d = (phis[-1] - plain).abs()
     agree = float(((phis[-1] > 0) == (plain > 0)).float().mean().item())
-    R = int(np.ceil(3 * w.sigma - 1e-9))
+    # voxels one launch covers: every sub-volume with its curtains (the
+    # boxes are a tensor product of per-axis extents)
+    boxed = 1
+    for n in w.shape:
+        boxed *= sum(curtained_extents(n, block, R))
     out = {
         "metric": METRIC,
         "value": round(w.voxels * w.iters * K / elapsed / 1e9, 3),
@@ -377,13 +385,32 @@ def run_volume(args, w, block: int) -> int:
         "config": {"workload": args.workload, "shape_zyx": list(w.shape), "sigma": w.sigma,
                    "iters": w.iters, "block": block, "curtain": R,
                    "parallelism": "single_gpu"},
+        "roofline": roofline(prof, pass_bytes(4, 4, False), boxed, args.workload),
+        "voxels_with_curtains": boxed,
+        "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()
+                                 if v[0]},
         "plain_value": round(w.voxels * w.iters / t_plain / 1e9, 3),
         "max_abs_diff_vs_plain": round(float(d.max().item()), 6),
         "sign_agreement_vs_plain": round(agree, 7),
     }
     ctx.close()
+    del phis, vol, phi0, plain
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, I_host, phi0_host, args.cpu_seconds,
+                                           what="the 512^3 phantom (one sub-volume's evolution)")
     print(json.dumps(out), flush=True)
     return 0
+
+
+def curtained_extents(n: int, block: int, curtain: int) -> list:
+    """Extents along one axis of the volume driver's sub-volumes: near-equal
+    cores of at most `block` voxels, each with `curtain` voxels beyond every
+    face it shares with a neighbour."""
+    parts = -(-n // block)
+    base, extra = divmod(n, parts)
+    cores = [base + (1 if k < extra else 0) for k in range(parts)]
+    return [c + curtain * ((k > 0) + (k < parts - 1)) for k, c in enumerate(cores)]
 
 
 INIT_WORKLOAD = "init512_sb2"   # seeds (sigma_b 2, threshold 0.05) and 2 sweep rounds on 512^3
@@ -780,7 +807,7 @@ def main() -> int:
         "roofline": roofline(prof, pb, vox, args.workload),
         "hbm_frac_path": round(value * iter_bytes / HBM_PEAK_GBS, 4),
         "path_bytes_per_voxel_iter": iter_bytes,
-        "passes_ms_per_launch": {k: round(v[1] / max(v[0], 1), 4) for k, v in prof.items()},
+        "passes_ms_per_launch": {k: round(v[1] / v[0], 4) for k, v in prof.items() if v[0]},
         "copy_gbs": round(copy_gbs, 1),
         "iters_run": iters_run,
         "finite": ok,
