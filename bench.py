@@ -24,12 +24,19 @@ sys.path.insert(0, ROOT)
 METRIC = "Gvoxel-iter/s at 512^3 sigma=3 (% HBM peak); p50/p99 tile latency"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
-def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4, paper: bool = False) -> dict:
+def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4, paper: bool = False,
+               fused: bool = False) -> dict:
     """Algorithmic HBM bytes per voxel for one launch of each pass: the reads
     and writes the pass must make, each field once (phi is always FP32).
     paper: the Sec. 4.2 force with sigma2 = 0 (no second Gaussian stage; the
-    force itself is FP32)."""
+    force itself is FP32).  fused: the paper force's update also writes the
+    next iteration's stage-1 pair, so z_heaviside runs once per evolution."""
     i, s = image_bytes, storage_bytes
+    if paper and fused:
+        return {
+            "xy_fits": 3 * s + i + 4,       # Kz*(HI), Kz*H, K*I, I -> F_d
+            "z_update": 12 + i + 2 * s,     # F_d, phi, I -> phi', Kz*(H'I), Kz*H'
+        }
     if paper:
         return {
             "z_heaviside": 4 + i + 2 * s,   # phi, I -> Kz*(HI), Kz*H
@@ -779,6 +786,10 @@ def main() -> int:
     prof = ctx.profile_read()
     _, iters_run, last_s, _ = ctx.stats(cap=0)
     ok = bool(torch.isfinite(phis[-1]).all().item()) and bool(np.isfinite(last_s))
+    # the fused update launched the stage-1 pass once per evolution
+    fused = paper and prof["z_heaviside"][0] < prof["z_update"][0]
+    if fused:
+        pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2, True, True)
 
     elapsed = t1 - t0
     vox = w.voxels
@@ -807,6 +818,7 @@ def main() -> int:
         "roofline": roofline(prof, pb, vox, args.workload),
         "hbm_frac_path": round(value * iter_bytes / HBM_PEAK_GBS, 4),
         "path_bytes_per_voxel_iter": iter_bytes,
+        "fused_stage1": fused,
         "passes_ms_per_launch": {k: round(v[1] / v[0], 4) for k, v in prof.items() if v[0]},
         "copy_gbs": round(copy_gbs, 1),
         "iters_run": iters_run,

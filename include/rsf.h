@@ -335,6 +335,13 @@ typedef struct {
     double ms[RSF_PASS_COUNT];      /* summed event time per pass */
 } rsf_profile;
 
+/* With the Sec. 4.2 force, when every tile's update pass marches its whole
+ * z extent, the update also forms the next iteration's stage-1 z Gaussian
+ * from the phi it has just written, so that pass is not launched again
+ * (on != 0, the default).  Results are bitwise the same either way; off runs
+ * the passes separately.  Affects later rsf_evolve* calls on this context. */
+rsf_status rsf_set_fusion(rsf_context *ctx, int on);
+
 /* Start (on != 0) or stop recording events on later launches. */
 rsf_status rsf_profile_enable(rsf_context *ctx, int on);
 

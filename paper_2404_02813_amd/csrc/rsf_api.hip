@@ -51,6 +51,7 @@ struct rsf_context {
     bool has_last = false;
     // per-pass event timing
     bool prof = false;
+    bool fuse = true;   // fused update + next stage-1 pass where a batch allows it
     struct Rec {
         int kind;
         hipEvent_t a, b;
@@ -246,6 +247,9 @@ struct Plan {
     bool k2;             // K2*I and K2*I^2 for the Sec. 4.2 force with sigma2 > 0
     int R2;
     Taps taps2;
+    // Sec. 4.2 force with every tile's update marched whole in z: the update
+    // also writes the next iteration's stage-1 z pass
+    bool fuse;
 };
 
 Grid3 grid_of(const rsf_tile &t) { return rsf::host::grid_of(t.nx, t.ny, t.nz); }
@@ -341,6 +345,8 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.blocks_xy = rsf::host::balance_xcds(P.xy, rsf::host::PASS_XY, gs, sps, P.R);
     P.blocks_z = rsf::host::balance_xcds(P.z, rsf::host::PASS_Z, gs, sps, P.R);
     P.blocks_u = rsf::host::balance_xcds(P.u, rsf::host::PASS_U, gs, sps, P.R);
+    P.fuse = P.c.force == RSF_FORCE_PAPER && !probe;
+    for (const Split &sp : sps) P.fuse = P.fuse && sp.u == 1;
     return RSF_OK;
 }
 
@@ -373,15 +379,28 @@ rsf_status prologue(rsf_context *ctx, const Plan &P, hipStream_t s)
     return RSF_OK;
 }
 
-// One iteration of every running tile of the batch.
-rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
+// The stage-1 z pass on its own (each iteration, or once before a fused loop).
+rsf_status stage1(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
 {
-    const Batch &z = P.z, &u = P.u;
     HIP_TRY(timed(ctx, RSF_PASS_Z_HEAVISIDE, s, [&] {
-                return rsf::launch_z_heaviside(P.R, P.image, P.storage, z, P.blocks_z, P.taps,
+                return rsf::launch_z_heaviside(P.R, P.image, P.storage, P.z, P.blocks_z, P.taps,
                                                P.c, probe, s);
             }),
             "z(H)");
+    return RSF_OK;
+}
+
+// One iteration of every running tile of the batch.  fused: the stage-1 pass
+// of this iteration was written by the previous update (or by stage1 before
+// the loop), and this update writes the next one.
+rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s,
+                     bool fused = false)
+{
+    const Batch &u = P.u;
+    if (!fused) {
+        const rsf_status st = stage1(ctx, P, probe, s);
+        if (st != RSF_OK) return st;
+    }
     const bool paper = P.c.force == RSF_FORCE_PAPER;
     HIP_TRY(timed(ctx, RSF_PASS_XY_FITS, s, [&] {
                 return rsf::launch_xy(P.R,
@@ -399,6 +418,9 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s)
                 }),
                 "xy(g)");
     HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s, [&] {
+                if (fused)
+                    return rsf::launch_z_update_fused(P.R, P.image, P.storage, u, P.blocks_u,
+                                                      P.taps, P.c, s);
                 return paper ? rsf::launch_z_update_paper(P.image, P.storage, u, P.blocks_u, P.c,
                                                           probe, s)
                              : rsf::launch_z_update(P.R, P.image, P.storage, u, P.blocks_u,
@@ -445,8 +467,13 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     if (st != RSF_OK) return st;
     st = prologue(ctx, P, s);
     if (st != RSF_OK) return st;
+    const bool fused = P.fuse && iters > 0 && ctx->fuse;
+    if (fused) {
+        st = stage1(ctx, P, false, s);
+        if (st != RSF_OK) return st;
+    }
     for (int it = 0; it < iters; ++it) {
-        st = iteration(ctx, P, false, s);
+        st = iteration(ctx, P, false, s, fused);
         if (st != RSF_OK) return st;
     }
     // tiles that ended on an odd iteration have it in the workspace buffer
@@ -565,6 +592,13 @@ void rsf_destroy(rsf_context *ctx)
     } catch (...) {
     }
     delete ctx;
+}
+
+rsf_status rsf_set_fusion(rsf_context *ctx, int on)
+{
+    if (!ctx) return RSF_ERR_INVALID_ARG;
+    ctx->fuse = on != 0;
+    return RSF_OK;
 }
 
 rsf_status rsf_profile_enable(rsf_context *ctx, int on)

@@ -604,6 +604,15 @@ hipError_t launch_z_update(int R, int it, int st, const Batch &b, int64_t blocks
 #undef C
 }
 
+hipError_t launch_z_update_fused(int R, int it, int st, const Batch &b, int64_t blocks,
+                                 const Taps &t, const Coeffs &c, hipStream_t s)
+{
+#define C(RR, IT, ST) \
+    case RR: return launch_z_update_fused_r<RR, IT, ST>(b, blocks, t, c, s);
+    RSF_DISPATCH(C)
+#undef C
+}
+
 hipError_t launch_z_update_paper(int it, int st, const Batch &b, int64_t blocks, const Coeffs &c,
                                  bool probe, hipStream_t s)
 {

@@ -404,12 +404,21 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
 // n, V of z+2 overwrite those of z-1, last read in step z-1; a barrier
 // separates each pair.
 //
-// PAPER: the force of Sec. 4.2 with sigma2 = 0 was formed by the xy pass and
-// is read pointwise (float F_d in Q); there is no stage-2 ring and no image
-// read, and R only sets the unroll.
-template <int R, bool PROBE, class ST, class IT, bool PAPER = false>
+// PAPER: the force of Sec. 4.2 was formed by the xy pass and is read
+// pointwise (float F_d in Q); there is no stage-2 ring and no image read, and
+// R only sets the unroll.
+//
+// FUSE (with PAPER, a tile marched whole in z): the pass also forms the next
+// iteration's stage-1 z Gaussian of (H(phi') I, H(phi')) from the phi' it has
+// just computed, in a register ring of the real radius R, and writes it to P
+// in place of the next z_heaviside pass.  At step z it pushes slice z and
+// emits output slice z - R; R more steps past the end push the zero padding.
+// The products and the tap order are those of z_heaviside, so P is bitwise
+// the same.
+template <int R, bool PROBE, class ST, class IT, bool PAPER = false, bool FUSE = false>
 __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t, Coeffs ua)
 {
+    static_assert(!FUSE || (PAPER && !PROBE), "the fused stage-1 pass is the Sec. 4.2 force's");
     constexpr int TX = kUx, TY = kUy, NT = kUThreads;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int QX = TX + 2, QY = TY + 2;
@@ -532,9 +541,18 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // loads are in flight would wait for them), so the march is unrolled
         // by an even count M and the conv ring has M >= 2R + 1 slots.
         constexpr int W = 2 * R + 1;
-        constexpr int PF = R <= 10 ? 2 : 1;
+        constexpr int PF = R <= (FUSE ? 9 : 10) ? 2 : 1;   // FUSE holds a second ring
         constexpr int M = PF == 2 ? W + 1 : W;
         float ra[M], rb[M];
+        // FUSE: ring of (H(phi') I, H(phi')); slices before the volume are
+        // the zero padding (the tile starts at z = 0)
+        float ha[FUSE ? M : 1], hb[FUSE ? M : 1];
+        if constexpr (FUSE) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) ha[j] = hb[j] = 0.f;
+        }
+        const gptr<Pair<ST>> tout = glb(static_cast<Pair<ST> *>(d.P));
+        const gptr<const IT> imgp = glb(static_cast<const IT *>(d.I));
         if constexpr (!PAPER) {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) {
@@ -561,6 +579,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             Vec2<ST> t;    // conv inputs of slice z + R
             IRaw I;        // image (PAPER: F_d) of slice z
             float cz;      // z edge factor of slice z
+            IT img;        // FUSE: image of slice z
         };
         auto stage = [&](int z) {
             Stage st;
@@ -568,13 +587,33 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
             st.I = iraw(min(z, zmax));
             st.cz = PAPER ? 0.f : czp[min(z, zmax)];
+            if constexpr (FUSE) st.img = (imgp + (int64_t)min(z, zmax) * g.sxy)[col];
             return st;
         };
         Stage sa = stage(z0), sb{};
         if constexpr (PF == 2) sb = stage(z0 + 1);
+        // FUSE: push (H I, H) of slice z (s its index in the unrolled block)
+        // and write the stage-1 z Gaussian of slice z - R, taps in the order
+        // of z_heaviside
+        auto emit = [&](const int s, const int z, float hi, float h) {
+            if constexpr (FUSE) {
+                pin(hi);
+                pin(h);
+                ha[(s + 2 * R) % M] = hi;
+                hb[(s + 2 * R) % M] = h;
+                float acc_a = 0.f, acc_b = 0.f;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    acc_a = fmaf(t.w[k], ha[(s + k) % M], acc_a);
+                    acc_b = fmaf(t.w[k], hb[(s + k) % M], acc_b);
+                }
+                if (z >= R && zt.active) st_pair<ST>(tout + (int64_t)(z - R) * g.sxy, col, acc_a, acc_b);
+            }
+        };
         // step z (s = its index in the unrolled block) consumes stage `cur`
         // and refills it with the loads of step z + PF
         auto step = [&](Stage &cur, const int s, const int z) {
+            float Hs = 0.f, HIs = 0.f;   // FUSE: (H(phi'), H(phi') I) of slice z
             store_phi(cur.phi, z + 3);
             if constexpr (!PAPER) {
                 const bool in = z + R < g.nz;   // zero padding past the volume
@@ -583,6 +622,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             }
             const IRaw I_cur = cur.I;   // PAPER: F_d of slice z
             const float cz_cur = cur.cz;
+            const IT img_cur = cur.img;
             cur = stage(z + PF);
             __syncthreads();
             float nzpp, vzpp;
@@ -624,6 +664,10 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 const float nxt = cphi + ua.dt * E;
                 (phi_out + zo)[col] = nxt;
                 acc += fabs((double)nxt - (double)cphi);
+                if constexpr (FUSE) {
+                    Hs = heaviside(nxt, ua.eps);
+                    HIs = Hs * to_f(img_cur);
+                }
                 if (PROBE) {
                     if (d.probe_Fd) (glb(d.probe_Fd) + zo)[col] = Fd;
                     if (d.probe_kappa) (glb(d.probe_kappa) + zo)[col] = kappa;
@@ -633,14 +677,18 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 }
             }
             nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
+            if constexpr (FUSE) emit(s, z, HIs, Hs);
         };
-        for (int zb = z0; zb < zt.z1; zb += M) {
+        const int zend = zt.z1 + (FUSE ? R : 0);
+        for (int zb = z0; zb < zend; zb += M) {
 #pragma unroll
             for (int s = 0; s < M; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
                     if (PF == 2 && (s & 1)) step(sb, s, z);
                     else step(sa, s, z);
+                } else if (FUSE && z < zend) {
+                    emit(s, z, 0.f, 0.f);   // past the volume: the zero padding
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -746,6 +794,15 @@ hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs 
     return hipGetLastError();
 }
 
+template <int R, class IT, class ST>
+hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
+                       dim3(kUThreads), 0, s, b, t, c);
+    return hipGetLastError();
+}
+
 #define RSF_INSTANTIATE_PAPER(IT, ST)                                                      \
     template hipError_t launch_z_update_paper_r<IT, ST>(const Batch &, int64_t, const Coeffs &, \
                                                         bool, hipStream_t);
@@ -759,6 +816,9 @@ hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs 
     template hipError_t launch_z_heaviside_r<RR, IT, ST>(const Batch &, int64_t, const Taps &, \
                                                          const Coeffs &, bool, hipStream_t);  \
     template hipError_t launch_z_update_r<RR, IT, ST>(const Batch &, int64_t, const Taps &,   \
-                                                      const Coeffs &, bool, hipStream_t);
+                                                      const Coeffs &, bool, hipStream_t);     \
+    template hipError_t launch_z_update_fused_r<RR, IT, ST>(const Batch &, int64_t,           \
+                                                            const Taps &, const Coeffs &,     \
+                                                            hipStream_t);
 
 }  // namespace rsf

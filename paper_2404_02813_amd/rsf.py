@@ -40,7 +40,7 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_profile_enable", "rsf_profile_read", "rsf_batch_workspace_bytes",
            "rsf_evolve_batch", "rsf_get_tile_stats", "rsf_autotune", "rsf_autotune_reset",
            "rsf_set_split_targets", "rsf_evolve_volume", "rsf_workspace_bytes_params",
-           "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi",
+           "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi", "rsf_set_fusion",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy")
@@ -160,6 +160,8 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params), i,
                                ctypes.POINTER(ctypes.c_int64), vp]
     L.rsf_autotune.restype = i
+    L.rsf_set_fusion.argtypes = [vp, i]
+    L.rsf_set_fusion.restype = i
     i64p = ctypes.POINTER(ctypes.c_int64)
     L.rsf_seeds.argtypes = [vp, vp, i, i64, i64, i64, f, f, vp, i64p, vp]
     L.rsf_seeds.restype = i
@@ -357,6 +359,10 @@ def rsf_batch_workspace_bytes_params(shapes, iters: int, params: rsf_params) -> 
                                                       ctypes.byref(params)))
 
 
+def rsf_set_fusion(ctx, on: bool) -> None:
+    _check(ctx, lib().rsf_set_fusion(ctx, 1 if on else 0))
+
+
 def rsf_seeds(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
               mask: torch.Tensor | None = None, stream=None):
     """Seed mask (uint8 tensor) and the seed count."""
@@ -522,6 +528,9 @@ class Context:
                       stream=None):
         rsf_evolve_volume(self.handle, volume, phi, params, iters, block, curtain, budget_bytes,
                           stream)
+
+    def set_fusion(self, on: bool) -> None:
+        rsf_set_fusion(self.handle, on)
 
     def seeds(self, volume, sigma_b, threshold, mask=None, stream=None):
         return rsf_seeds(self.handle, volume, sigma_b, threshold, mask, stream)

@@ -263,3 +263,81 @@ def test_paper_force_sigma2_limits(rsf):
         assert e.value.status == mod.RSF_ERR_INVALID_ARG
     torch.cuda.synchronize()
     assert torch.equal(phi, before)
+
+
+# --- the update fused with the next iteration's stage-1 z pass -------------
+
+# Fusion needs every tile's update marched whole in z: volumes whose xy plane
+# alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
+# tiles of at most 8 slices.
+FUSE_CASES = [  # (shape zyx, image, storage, sigma, sigma2, iters, tol)
+    ((40, 770, 256), "f32", "f32", 3.0, 0.0, 9, 0.0),
+    ((8, 47, 29), "u16", "f16", 2.0, 0.0, 12, 0.0),
+    ((30, 780, 260), "f32", "bf16", 4.0, 0.0, 5, 0.0),
+    ((7, 44, 38), "f32", "f32", 2.0, 1.5, 7, 0.0),
+    ((8, 34, 34), "f32", "f32", 3.0, 0.0, 80, 2e-3),
+    ((6, 21, 23), "f32", "f32", 1.0, 0.0, 4, 0.0),
+]
+
+
+def fuse_case(mod, shape, image, seed):
+    if image == "u16":
+        vol = torch.from_numpy(inputs.u16_phantom(shape, 6, 1.0, 3.0, seed)).cuda()
+    else:
+        vol = dev(inputs.vessel_phantom(shape, 6, 1.0, 3.0, seed))
+    return vol, dev(inputs.box_phi0(shape))
+
+
+@pytest.mark.parametrize("shape,image,storage,sigma,sigma2,iters,tol", FUSE_CASES)
+def test_fused_update_is_bitwise_the_separate_passes(rsf, shape, image, storage, sigma, sigma2,
+                                                     iters, tol):
+    """The fused update writes the next stage-1 pair exactly as the stage-1
+    pass would: the whole evolution is bitwise the same, and the stage-1 pass
+    is launched once instead of once per iteration."""
+    mod, ctx = rsf
+    say(f"fused update {shape} {image}/{storage} sigma={sigma} sigma2={sigma2} iters={iters}")
+    vol, phi0 = fuse_case(mod, shape, image, 311)
+    p = mod.make_params(sigma, 1.0, 1.0, 0.001, 1.0, 0.1, 1.0, storage=storage,
+                        force=mod.RSF_FORCE_PAPER, sigma2=sigma2)
+    out = {}
+    for fuse in (False, True):
+        ctx.set_fusion(fuse)
+        phi = phi0.clone()
+        ctx.profile(True)
+        ctx.evolve_ex(vol, phi, p, iters, tol=tol)
+        ctx.profile(False)
+        prof = ctx.profile_read()
+        _, run, last, _ = ctx.stats(cap=0)
+        out[fuse] = (phi, run, last, prof["z_heaviside"][0])
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    (a, run_a, last_a, zh_a), (b, run_b, last_b, zh_b) = out[False], out[True]
+    say(f"  iterations {run_a}/{run_b}, stage-1 launches {zh_a} -> {zh_b}")
+    assert torch.equal(a, b)
+    assert run_a == run_b and last_a == last_b
+    assert zh_a == iters and zh_b == 1   # stopped tiles exit launched passes early
+    if tol > 0:
+        assert run_a < iters
+
+
+def test_fused_update_in_a_batch(rsf):
+    """Tiles of one batch, each marched whole in z, fused together; each is
+    bitwise the separate passes' result."""
+    mod, ctx = rsf
+    say("fused update: batch of tiles")
+    shapes = [(8, 40, 50), (6, 36, 28), (8, 24, 33)]
+    cases = [fuse_case(mod, sh, "f32", 320 + k) for k, sh in enumerate(shapes)]
+    p = mod.make_params(3.0, 1.0, 1.0, 0.001, 1.0, 0.1, 1.0, force=mod.RSF_FORCE_PAPER)
+    res = {}
+    for fuse in (False, True):
+        ctx.set_fusion(fuse)
+        phis = [c[1].clone() for c in cases]
+        ctx.profile(True)
+        ctx.evolve_batch([c[0] for c in cases], phis, p, 6)
+        ctx.profile(False)
+        res[fuse] = (phis, ctx.profile_read()["z_heaviside"][0])
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    assert res[True][1] == 1 and res[False][1] == 6
+    for a, b in zip(res[False][0], res[True][0]):
+        assert torch.equal(a, b)
