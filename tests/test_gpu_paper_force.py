@@ -341,3 +341,57 @@ def test_fused_update_in_a_batch(rsf):
     assert res[True][1] == 1 and res[False][1] == 6
     for a, b in zip(res[False][0], res[True][0]):
         assert torch.equal(a, b)
+
+
+# --- the Sec. 4.2 workload at full size (512^3, sigma 3, fused update) -------
+
+@pytest.fixture(scope="module")
+def large():
+    w = inputs.LARGE_512
+    say(f"generating {w.name}")
+    return w, w.image(), w.phi0()
+
+
+def test_full_size_two_iterations_sampled(rsf, large):
+    """Two iterations as the throughput workload runs them (the second reads
+    the stage-1 pair the fused first update wrote), against the oracle on
+    crops whose inner faces lie beyond two iterations' reach."""
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name} (Sec. 4.2 force): two iterations, sampled voxels")
+    p = mod.make_params(**w.params(), force=mod.RSF_FORCE_PAPER)
+    phi = dev(phi0)
+    ctx.profile(True)
+    ctx.evolve_ex(dev(I), phi, p, 2)
+    ctx.profile(False)
+    assert ctx.profile_read()["z_heaviside"][0] == 1   # the fused path ran
+    got = host(phi)
+    R = oracle.radius(w.sigma)
+    margin = 2 * (2 * R + 3)
+    po = oracle.params_array(**w.params(), eta=1e-10, force=oracle.FORCE_PAPER)
+    r = np.random.default_rng(21)
+    centers = [tuple(int(v) for v in r.integers(0, 512, 3)) for _ in range(4)]
+    centers += [(0, 0, 0), (511, 511, 511), (256, 3, 500), (300, 200, 100)]
+    for c in centers:
+        sl = tuple(slice(max(0, k - margin), min(n, k + margin + 1)) for k, n in zip(c, I.shape))
+        want, _ = oracle.evolve(I[sl], phi0[sl], po, 2)
+        local = tuple(k - s.start for k, s in zip(c, sl))
+        assert abs(got[c] - want[local]) < 4e-6, (c, got[c], want[local])
+
+
+def test_full_size_fused_equals_separate_passes(rsf, large):
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name} (Sec. 4.2 force): {w.iters} iterations fused vs separate")
+    p = mod.make_params(**w.params(), force=mod.RSF_FORCE_PAPER)
+    vol = dev(I)
+    out = []
+    for fuse in (True, False):
+        ctx.set_fusion(fuse)
+        phi = dev(phi0)
+        ctx.evolve_ex(vol, phi, p, w.iters)
+        out.append(phi)
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[1])
+    assert bool(torch.isfinite(out[0]).all())
