@@ -29,9 +29,15 @@ def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4, paper: bool = False
     """Algorithmic HBM bytes per voxel for one launch of each pass: the reads
     and writes the pass must make, each field once (phi is always FP32).
     paper: the Sec. 4.2 force with sigma2 = 0 (no second Gaussian stage; the
-    force itself is FP32).  fused: the paper force's update also writes the
-    next iteration's stage-1 pair, so z_heaviside runs once per evolution."""
+    force itself is FP32).  fused: the update also writes the next
+    iteration's stage-1 pair, so z_heaviside runs once per evolution."""
     i, s = image_bytes, storage_bytes
+    if fused and not paper:
+        return {
+            "xy_fits": 5 * s,                  # Kz*(HI), Kz*H, K*I -> g1, g2
+            "xy_force": 4 * s,                 # g1, g2 -> Kxy*g1, Kxy*g2
+            "z_update": 8 + i + 4 * s,         # Kxy*g1, Kxy*g2, I, phi -> phi', Kz*(H'I), Kz*H'
+        }
     if paper and fused:
         return {
             "xy_fits": 3 * s + i + 4,       # Kz*(HI), Kz*H, K*I, I -> F_d
@@ -700,6 +706,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="vessel512_s3_it200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="run the stage-1 z pass separately every iteration")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--iters", type=int, default=0,
                     help="override the workload's iteration count (profiling runs)")
@@ -764,6 +772,8 @@ def main() -> int:
                              force=rsf.RSF_FORCE_PAPER if paper else rsf.RSF_FORCE_RSF)
     phis = [torch.empty_like(phi0) for _ in range(K)]
     ctx = rsf.Context(0)
+    if args.no_fusion:
+        ctx.set_fusion(False)
     scratch = torch.empty_like(phi0)
 
     for _ in range(W):
@@ -787,9 +797,9 @@ def main() -> int:
     _, iters_run, last_s, _ = ctx.stats(cap=0)
     ok = bool(torch.isfinite(phis[-1]).all().item()) and bool(np.isfinite(last_s))
     # the fused update launched the stage-1 pass once per evolution
-    fused = paper and prof["z_heaviside"][0] < prof["z_update"][0]
+    fused = prof["z_heaviside"][0] < prof["z_update"][0]
     if fused:
-        pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2, True, True)
+        pb = pass_bytes(2 if image_t == "u16" else 4, 4 if storage_t == "f32" else 2, paper, True)
 
     elapsed = t1 - t0
     vox = w.voxels

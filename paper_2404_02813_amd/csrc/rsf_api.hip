@@ -247,8 +247,8 @@ struct Plan {
     bool k2;             // K2*I and K2*I^2 for the Sec. 4.2 force with sigma2 > 0
     int R2;
     Taps taps2;
-    // Sec. 4.2 force with every tile's update marched whole in z: the update
-    // also writes the next iteration's stage-1 z pass
+    // every tile's update marched whole in z: the update also writes the
+    // next iteration's stage-1 z pass
     bool fuse;
 };
 
@@ -345,7 +345,7 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.blocks_xy = rsf::host::balance_xcds(P.xy, rsf::host::PASS_XY, gs, sps, P.R);
     P.blocks_z = rsf::host::balance_xcds(P.z, rsf::host::PASS_Z, gs, sps, P.R);
     P.blocks_u = rsf::host::balance_xcds(P.u, rsf::host::PASS_U, gs, sps, P.R);
-    P.fuse = P.c.force == RSF_FORCE_PAPER && !probe;
+    P.fuse = !probe && (P.c.force == RSF_FORCE_PAPER || P.R <= rsf::kFuseMaxR);
     for (const Split &sp : sps) P.fuse = P.fuse && sp.u == 1;
     return RSF_OK;
 }
@@ -420,7 +420,7 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s,
     HIP_TRY(timed(ctx, RSF_PASS_Z_UPDATE, s, [&] {
                 if (fused)
                     return rsf::launch_z_update_fused(P.R, P.image, P.storage, u, P.blocks_u,
-                                                      P.taps, P.c, s);
+                                                      P.taps, P.c, paper, s);
                 return paper ? rsf::launch_z_update_paper(P.image, P.storage, u, P.blocks_u, P.c,
                                                           probe, s)
                              : rsf::launch_z_update(P.R, P.image, P.storage, u, P.blocks_u,

@@ -164,10 +164,15 @@ hipError_t launch_z_update(int R, int image_dtype, int storage_dtype, const Batc
 // The update reading the Sec. 4.2 force (sigma2 = 0) that XY_PAPER wrote.
 hipError_t launch_z_update_paper(int image_dtype, int storage_dtype, const Batch &b,
                                  int64_t blocks, const Coeffs &c, bool probe, hipStream_t s);
-// The same update fused with the next iteration's stage-1 z pass (writes P
-// from phi' as launch_z_heaviside would); every tile marched whole in z.
+// Largest Gaussian radius whose RSF-force update is fused with the next
+// stage-1 pass (the Sec. 4.2 force's update has no stage-2 ring: any radius).
+constexpr int kFuseMaxR = 10;
+// The update (RSF force, or the Sec. 4.2 force if `paper`) fused with the
+// next iteration's stage-1 z pass (writes P from phi' as launch_z_heaviside
+// would); every tile marched whole in z.
 hipError_t launch_z_update_fused(int R, int image_dtype, int storage_dtype, const Batch &b,
-                                 int64_t blocks, const Taps &t, const Coeffs &c, hipStream_t s);
+                                 int64_t blocks, const Taps &t, const Coeffs &c, bool paper,
+                                 hipStream_t s);
 // One workgroup per tile: fixed-order FP64 sum of the partials; counts the
 // iteration and stops the tile at its tolerance or its last iteration.
 hipError_t launch_reduce(const Batch &b, const Coeffs &c, hipStream_t s);
@@ -235,6 +240,6 @@ hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs 
                                    hipStream_t s);
 template <int R, class IT, class ST>
 hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
-                                   hipStream_t s);
+                                   bool paper, hipStream_t s);
 
 }  // namespace rsf

@@ -605,10 +605,10 @@ hipError_t launch_z_update(int R, int it, int st, const Batch &b, int64_t blocks
 }
 
 hipError_t launch_z_update_fused(int R, int it, int st, const Batch &b, int64_t blocks,
-                                 const Taps &t, const Coeffs &c, hipStream_t s)
+                                 const Taps &t, const Coeffs &c, bool paper, hipStream_t s)
 {
 #define C(RR, IT, ST) \
-    case RR: return launch_z_update_fused_r<RR, IT, ST>(b, blocks, t, c, s);
+    case RR: return launch_z_update_fused_r<RR, IT, ST>(b, blocks, t, c, paper, s);
     RSF_DISPATCH(C)
 #undef C
 }

@@ -408,17 +408,19 @@ __device__ __forceinline__ void normal_flux(float gx, float gy, float gz, float 
 // pointwise (float F_d in Q); there is no stage-2 ring and no image read, and
 // R only sets the unroll.
 //
-// FUSE (with PAPER, a tile marched whole in z): the pass also forms the next
+// FUSE (every tile marched whole in z): the pass also forms the next
 // iteration's stage-1 z Gaussian of (H(phi') I, H(phi')) from the phi' it has
-// just computed, in a register ring of the real radius R, and writes it to P
-// in place of the next z_heaviside pass.  At step z it pushes slice z and
-// emits output slice z - R; R more steps past the end push the zero padding.
-// The products and the tap order are those of z_heaviside, so P is bitwise
-// the same.
+// just computed, in a register ring of radius R, and writes it to P in place
+// of the next z_heaviside pass.  At step z it pushes slice z and emits output
+// slice z - R; R more steps past the end push the zero padding.  The
+// products and the tap order are those of z_heaviside, so P is bitwise the
+// same.  With the RSF force P is also this pass's stage-2 input; the z
+// Gaussian reads P only in the thread's own column, and slice z - R entered
+// the register ring steps before it is overwritten.
 template <int R, bool PROBE, class ST, class IT, bool PAPER = false, bool FUSE = false>
 __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t, Coeffs ua)
 {
-    static_assert(!FUSE || (PAPER && !PROBE), "the fused stage-1 pass is the Sec. 4.2 force's");
+    static_assert(!(FUSE && PROBE), "probes run the passes separately");
     constexpr int TX = kUx, TY = kUy, NT = kUThreads;
     constexpr int PX = TX + 4, PY = TY + 4;
     constexpr int QX = TX + 2, QY = TY + 2;
@@ -541,7 +543,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // loads are in flight would wait for them), so the march is unrolled
         // by an even count M and the conv ring has M >= 2R + 1 slots.
         constexpr int W = 2 * R + 1;
-        constexpr int PF = R <= (FUSE ? 9 : 10) ? 2 : 1;   // FUSE holds a second ring
+        // FUSE holds a second ring: with the RSF force's stage-2 ring there
+        // are registers for one prefetch stage only
+        constexpr int PF = R <= (FUSE ? (PAPER ? 9 : 0) : 10) ? 2 : 1;
         constexpr int M = PF == 2 ? W + 1 : W;
         float ra[M], rb[M];
         // FUSE: ring of (H(phi') I, H(phi')); slices before the volume are
@@ -587,7 +591,8 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
             st.I = iraw(min(z, zmax));
             st.cz = PAPER ? 0.f : czp[min(z, zmax)];
-            if constexpr (FUSE) st.img = (imgp + (int64_t)min(z, zmax) * g.sxy)[col];
+            // (RSF force: the image of slice z is already st.I)
+            if constexpr (FUSE && PAPER) st.img = (imgp + (int64_t)min(z, zmax) * g.sxy)[col];
             return st;
         };
         Stage sa = stage(z0), sb{};
@@ -622,7 +627,11 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             }
             const IRaw I_cur = cur.I;   // PAPER: F_d of slice z
             const float cz_cur = cur.cz;
-            const IT img_cur = cur.img;
+            IT img_cur{};
+            if constexpr (FUSE) {
+                if constexpr (PAPER) img_cur = cur.img;
+                else img_cur = I_cur;
+            }
             cur = stage(z + PF);
             __syncthreads();
             float nzpp, vzpp;
@@ -796,10 +805,18 @@ hipError_t launch_z_update_paper_r(const Batch &b, int64_t blocks, const Coeffs 
 
 template <int R, class IT, class ST>
 hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
-                                   hipStream_t s)
+                                   bool paper, hipStream_t s)
 {
-    hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
-                       dim3(kUThreads), 0, s, b, t, c);
+    if (paper) {
+        hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
+                           dim3(kUThreads), 0, s, b, t, c);
+    } else {
+        // with the stage-2 ring, larger radii spill: those run the passes separately
+        if constexpr (R > kFuseMaxR) return hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, false, true>),
+                               dim3((unsigned)blocks), dim3(kUThreads), 0, s, b, t, c);
+    }
     return hipGetLastError();
 }
 
@@ -819,6 +836,6 @@ hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t
                                                       const Coeffs &, bool, hipStream_t);     \
     template hipError_t launch_z_update_fused_r<RR, IT, ST>(const Batch &, int64_t,           \
                                                             const Taps &, const Coeffs &,     \
-                                                            hipStream_t);
+                                                            bool, hipStream_t);
 
 }  // namespace rsf

@@ -476,3 +476,64 @@ def test_autotune_keeps_results(rsf):
             assert torch.equal(probe[k], ref[k]), k
     finally:
         ctx.autotune_reset()
+
+
+# --- the update fused with the next iteration's stage-1 z pass -----------------------
+
+# Fusion needs every tile's update marched whole in z: volumes whose xy plane
+# alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
+# tiles of at most 8 slices; with the RSF force only up to radius 10.
+RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
+    ((40, 770, 256), "f32", "f32", 3.0, 9, 0.0, True),
+    ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, True),
+    ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, True),
+    ((8, 34, 34), "f32", "f32", 3.0, 80, 2e-3, True),
+    ((6, 21, 23), "f32", "f32", 1.0, 4, 0.0, True),
+    ((8, 30, 30), "f32", "f32", 3.4, 5, 0.0, False),   # R = 11: separate passes
+]
+
+
+@pytest.mark.parametrize("shape,image,storage,sigma,iters,tol,fused", RSF_FUSE_CASES)
+def test_fused_update_is_bitwise_the_separate_passes(rsf, shape, image, storage, sigma, iters,
+                                                     tol, fused):
+    mod, ctx = rsf
+    say(f"fused update (RSF force) {shape} {image}/{storage} sigma={sigma} iters={iters}")
+    if image == "u16":
+        vol = torch.from_numpy(inputs.u16_phantom(shape, 6, 1.0, 3.0, 341)).cuda()
+    else:
+        vol = dev(inputs.vessel_phantom(shape, 6, 1.0, 3.0, 341))
+    phi0 = dev(inputs.box_phi0(shape))
+    p = mod.make_params(sigma, 1.0, 1.0, 0.001, 1.0, 0.1, 1.0, storage=storage)
+    out = {}
+    for fuse in (False, True):
+        ctx.set_fusion(fuse)
+        phi = phi0.clone()
+        ctx.profile(True)
+        ctx.evolve_ex(vol, phi, p, iters, tol=tol)
+        ctx.profile(False)
+        zh = ctx.profile_read()["z_heaviside"][0]
+        _, run, last, _ = ctx.stats(cap=0)
+        out[fuse] = (phi, run, last, zh)
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    (a, run_a, last_a, zh_a), (b, run_b, last_b, zh_b) = out[False], out[True]
+    say(f"  iterations {run_a}/{run_b}, stage-1 launches {zh_a} -> {zh_b}")
+    assert torch.equal(a, b)
+    assert run_a == run_b and last_a == last_b
+    assert zh_a == iters and zh_b == (1 if fused else iters)
+
+
+def test_full_size_fused_equals_separate_passes(rsf, large):
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name}: {w.iters} iterations fused vs separate")
+    vol = dev(I)
+    out = []
+    for fuse in (True, False):
+        ctx.set_fusion(fuse)
+        phi = dev(phi0)
+        ctx.evolve(vol, phi, w.iters, **w.params())
+        out.append(phi)
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[1])
