@@ -262,6 +262,8 @@ def run_tiles(args, w) -> int:
     interior = sum(int(np.prod([n - 2 * w.halo for n in v.shape])) for v in vols)
     params = rsf.make_params(**w.params())
     ctx = rsf.Context(0)
+    if args.no_fusion:
+        ctx.set_fusion(False)
 
     def fresh():
         return [p.clone() for p in phi0]
@@ -360,6 +362,8 @@ def run_volume(args, w, block: int) -> int:
     phi0 = torch.from_numpy(phi0_host).cuda()
     params = rsf.make_params(**w.params())
     ctx = rsf.Context(0)
+    if args.no_fusion:
+        ctx.set_fusion(False)
     R = int(np.ceil(3 * w.sigma - 1e-9))
     for _ in range(W):
         ph = phi0.clone()
@@ -444,6 +448,8 @@ def run_init(args, w) -> int:
     vol = torch.from_numpy(I_host).cuda()
     phi = torch.empty_like(vol)
     ctx = rsf.Context(0)
+    if args.no_fusion:
+        ctx.set_fusion(False)
     n_seeds = 0
     for _ in range(W):
         n_seeds = ctx.init_phi(vol, phi, INIT_SIGMA_B, INIT_THRESHOLD, 0.0, INIT_ROUNDS)
@@ -631,6 +637,8 @@ def run_serve(args, w) -> int:
     # (3) FIFO one at a time over the saturation sample
     print("[serve] (3) FIFO one at a time over the saturation sample", file=sys.stderr, flush=True)
     ctx = rsf.Context(0)
+    if args.no_fusion:
+        ctx.set_fusion(False)
     torch.cuda.synchronize()
     t0 = time.monotonic()
     for r in reqs[:sample]:
