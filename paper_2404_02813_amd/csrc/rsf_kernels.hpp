@@ -543,11 +543,20 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // loads are in flight would wait for them), so the march is unrolled
         // by an even count M and the conv ring has M >= 2R + 1 slots.
         constexpr int W = 2 * R + 1;
-        // FUSE holds a second ring: with the RSF force's stage-2 ring there
-        // are registers for one prefetch stage only
-        constexpr int PF = R <= (FUSE ? (PAPER ? 9 : 0) : 10) ? 2 : 1;
+        // With FP16 storage the stage-2 ring holds the raw pairs, one
+        // register per slot, converted where the FMA reads them (the
+        // conversion is exact, so the sums are unchanged), which leaves
+        // registers for two prefetch stages at every radius and removes the
+        // fused update's spills.  (BF16 would pay an extra instruction per
+        // tap for its conversion: it keeps the FP32 ring.)  FUSE holds a
+        // second (FP32) ring: with the RSF force's stage-2 ring it runs one
+        // prefetch stage.
+        constexpr bool PACK = std::is_same<ST, _Float16>::value;
+        constexpr int PF = FUSE ? (R <= (PAPER ? 9 : 0) ? 2 : 1)
+                                : ((PACK || R <= 10) ? 2 : 1);
         constexpr int M = PF == 2 ? W + 1 : W;
-        float ra[M], rb[M];
+        float ra[PACK ? 1 : M], rb[PACK ? 1 : M];
+        Vec2<ST> rv[PACK ? M : 1];
         // FUSE: ring of (H(phi') I, H(phi')); slices before the volume are
         // the zero padding (the tile starts at z = 0)
         float ha[FUSE ? M : 1], hb[FUSE ? M : 1];
@@ -562,8 +571,12 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             for (int j = 0; j < 2 * R; ++j) {
                 const int z = z0 - R + j;
                 const Vec2<ST> v = (z >= 0 && z < g.nz) ? pair_at(z) : Vec2<ST>{};
-                ra[j] = to_f(v.x);
-                rb[j] = to_f(v.y);
+                if constexpr (PACK) {
+                    rv[j] = v;
+                } else {
+                    ra[j] = to_f(v.x);
+                    rb[j] = to_f(v.y);
+                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -622,8 +635,13 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             store_phi(cur.phi, z + 3);
             if constexpr (!PAPER) {
                 const bool in = z + R < g.nz;   // zero padding past the volume
-                ra[(s + 2 * R) % M] = in ? to_f(cur.t.x) : 0.f;
-                rb[(s + 2 * R) % M] = in ? to_f(cur.t.y) : 0.f;
+                if constexpr (PACK) {
+                    const uint32_t bits = __builtin_bit_cast(uint32_t, cur.t);
+                    rv[(s + 2 * R) % M] = __builtin_bit_cast(Vec2<ST>, in ? bits : 0u);
+                } else {
+                    ra[(s + 2 * R) % M] = in ? to_f(cur.t.x) : 0.f;
+                    rb[(s + 2 * R) % M] = in ? to_f(cur.t.y) : 0.f;
+                }
             }
             const IRaw I_cur = cur.I;   // PAPER: F_d of slice z
             const float cz_cur = cur.cz;
@@ -640,8 +658,13 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             if constexpr (!PAPER) {
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    KG1 = fmaf(t.w[k], ra[(s + k) % M], KG1);
-                    KG2 = fmaf(t.w[k], rb[(s + k) % M], KG2);
+                    if constexpr (PACK) {
+                        KG1 = fmaf(t.w[k], to_f(rv[(s + k) % M].x), KG1);
+                        KG2 = fmaf(t.w[k], to_f(rv[(s + k) % M].y), KG2);
+                    } else {
+                        KG1 = fmaf(t.w[k], ra[(s + k) % M], KG1);
+                        KG2 = fmaf(t.w[k], rb[(s + k) % M], KG2);
+                    }
                 }
             }
             if (zt.active) {
