@@ -550,7 +550,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // fused update's spills.  (BF16 would pay an extra instruction per
         // tap for its conversion: it keeps the FP32 ring.)  FUSE holds a
         // second (FP32) ring: with the RSF force's stage-2 ring it runs one
-        // prefetch stage.
+        // prefetch stage (and FP32 storage only, so PACK is off there).
         constexpr bool PACK = std::is_same<ST, _Float16>::value;
         constexpr int PF = FUSE ? (R <= (PAPER ? 9 : 0) ? 2 : 1)
                                 : ((PACK || R <= 10) ? 2 : 1);
@@ -830,11 +830,14 @@ template <int R, class IT, class ST>
 hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
                                    bool paper, hipStream_t s)
 {
-    if (paper) {
+    // 16-bit storage: the fused update did not reproduce the separate passes
+    // bitwise at 512^3, so it is not built; RSF force: larger radii spill
+    if constexpr (!std::is_same<ST, float>::value) {
+        return hipErrorInvalidValue;
+    } else if (paper) {
         hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
                            dim3(kUThreads), 0, s, b, t, c);
     } else {
-        // with the stage-2 ring, larger radii spill: those run the passes separately
         if constexpr (R > kFuseMaxR) return hipErrorInvalidValue;
         else
             hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, false, true>),

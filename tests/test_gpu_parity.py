@@ -482,11 +482,13 @@ def test_autotune_keeps_results(rsf):
 
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
 # alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
-# tiles of at most 8 slices; with the RSF force only up to radius 10.
+# tiles of at most 8 slices; with the RSF force only up to radius 10 and in
+# FP32 storage (with 16-bit storage the fused update did not reproduce the
+# separate passes bitwise at 512^3, so those run separately).
 RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
     ((40, 770, 256), "f32", "f32", 3.0, 9, 0.0, True),
-    ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, True),
-    ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, True),
+    ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, False),   # 16-bit storage: separate
+    ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, False),
     ((8, 34, 34), "f32", "f32", 3.0, 80, 2e-3, True),
     ((6, 21, 23), "f32", "f32", 1.0, 4, 0.0, True),
     ((8, 30, 30), "f32", "f32", 3.4, 5, 0.0, False),   # R = 11: separate passes
@@ -523,16 +525,21 @@ def test_fused_update_is_bitwise_the_separate_passes(rsf, shape, image, storage,
     assert zh_a == iters and zh_b == (1 if fused else iters)
 
 
-def test_full_size_fused_equals_separate_passes(rsf, large):
+@pytest.mark.parametrize("storage", ["f32"])
+def test_full_size_fused_equals_separate_passes(rsf, large, storage):
     mod, ctx = rsf
     w, I, phi0 = large
-    say(f"{w.name}: {w.iters} iterations fused vs separate")
+    say(f"{w.name}: {w.iters} iterations fused vs separate, {storage} storage")
     vol = dev(I)
+    p = mod.make_params(**w.params(), storage=storage)
     out = []
     for fuse in (True, False):
         ctx.set_fusion(fuse)
         phi = dev(phi0)
-        ctx.evolve(vol, phi, w.iters, **w.params())
+        ctx.profile(True)
+        ctx.evolve_ex(vol, phi, p, w.iters)
+        ctx.profile(False)
+        assert ctx.profile_read()["z_heaviside"][0] == (1 if fuse else w.iters)
         out.append(phi)
     ctx.set_fusion(True)
     torch.cuda.synchronize()
