@@ -335,8 +335,8 @@ typedef struct {
     double ms[RSF_PASS_COUNT];      /* summed event time per pass */
 } rsf_profile;
 
-/* With FP32 storage, when every tile's update pass marches its whole z
- * extent (and, for the RSF force, a single volume with ceil(3 sigma) <= 10),
+/* When every tile's update pass marches its whole z extent (and, for the
+ * RSF force, a single volume with ceil(3 sigma) <= 10),
  * the update also forms the next iteration's stage-1 z Gaussian (Sec. 3 fits)
  * from the phi it has just written, so that pass is not launched again
  * (on != 0, the default).  Results are bitwise the same either way; off runs

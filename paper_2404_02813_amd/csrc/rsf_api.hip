@@ -345,12 +345,9 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.blocks_xy = rsf::host::balance_xcds(P.xy, rsf::host::PASS_XY, gs, sps, P.R);
     P.blocks_z = rsf::host::balance_xcds(P.z, rsf::host::PASS_Z, gs, sps, P.R);
     P.blocks_u = rsf::host::balance_xcds(P.u, rsf::host::PASS_U, gs, sps, P.R);
-    // FP32 storage only: with 16-bit storage the fused update did not
-    // reproduce the separate passes bitwise at 512^3 (both forces).  RSF
-    // force: single volumes only (on batches of uneven tiles the fused update
-    // measured about 2 % slower than the separate passes).
-    P.fuse = !probe && P.storage == RSF_F32 &&
-             (P.c.force == RSF_FORCE_PAPER || (P.R <= rsf::kFuseMaxR && n == 1));
+    // RSF force: single volumes only (on batches of uneven tiles the fused
+    // update measured about 2 % slower than the separate passes).
+    P.fuse = !probe && (P.c.force == RSF_FORCE_PAPER || (P.R <= rsf::kFuseMaxR && n == 1));
     for (const Split &sp : sps) P.fuse = P.fuse && sp.u == 1;
     return RSF_OK;
 }

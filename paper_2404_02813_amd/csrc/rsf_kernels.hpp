@@ -362,6 +362,11 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t,
             return make_float2(H * to_f(raw.img), H);
         },
         [&](int z, float va, float vb) {
+            if constexpr (!std::is_same<ST, float>::value) {
+                // as in the fused update: round the FP32 sums, then convert
+                pin(va);
+                pin(vb);
+            }
             st_pair<ST>(tp + (int64_t)z * g.sxy, col, va, vb);
         });
 }
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // fused update's spills.  (BF16 would pay an extra instruction per
         // tap for its conversion: it keeps the FP32 ring.)  FUSE holds a
         // second (FP32) ring: with the RSF force's stage-2 ring it runs one
-        // prefetch stage (and FP32 storage only, so PACK is off there).
+        // prefetch stage.
         constexpr bool PACK = std::is_same<ST, _Float16>::value;
         constexpr int PF = FUSE ? (R <= (PAPER ? 9 : 0) ? 2 : 1)
                                 : ((PACK || R <= 10) ? 2 : 1);
@@ -624,6 +629,13 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 for (int k = 0; k < W; ++k) {
                     acc_a = fmaf(t.w[k], ha[(s + k) % M], acc_a);
                     acc_b = fmaf(t.w[k], hb[(s + k) % M], acc_b);
+                }
+                // 16-bit storage: opaque sums, so that the compiler cannot
+                // merge the last FMA with the conversion (one rounding to 16
+                // bits) here and not in z_heaviside, or the reverse
+                if constexpr (!std::is_same<ST, float>::value) {
+                    pin(acc_a);
+                    pin(acc_b);
                 }
                 if (z >= R && zt.active) st_pair<ST>(tout + (int64_t)(z - R) * g.sxy, col, acc_a, acc_b);
             }
@@ -830,11 +842,8 @@ template <int R, class IT, class ST>
 hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t, const Coeffs &c,
                                    bool paper, hipStream_t s)
 {
-    // 16-bit storage: the fused update did not reproduce the separate passes
-    // bitwise at 512^3, so it is not built; RSF force: larger radii spill
-    if constexpr (!std::is_same<ST, float>::value) {
-        return hipErrorInvalidValue;
-    } else if (paper) {
+    // RSF force: larger radii spill and keep the separate passes
+    if (paper) {
         hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
                            dim3(kUThreads), 0, s, b, t, c);
     } else {

@@ -270,11 +270,10 @@ def test_paper_force_sigma2_limits(rsf):
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
 # alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
 # tiles of at most 8 slices.
-# FP32 storage only: with 16-bit storage the passes run separately.
 FUSE_CASES = [  # (shape zyx, image, storage, sigma, sigma2, iters, tol)
     ((40, 770, 256), "f32", "f32", 3.0, 0.0, 9, 0.0),
-    ((8, 47, 29), "u16", "f32", 2.0, 0.0, 12, 0.0),
-    ((30, 780, 260), "f32", "f32", 4.0, 0.0, 5, 0.0),
+    ((8, 47, 29), "u16", "f16", 2.0, 0.0, 12, 0.0),
+    ((30, 780, 260), "f32", "bf16", 4.0, 0.0, 5, 0.0),
     ((7, 44, 38), "f32", "f32", 2.0, 1.5, 7, 0.0),
     ((8, 34, 34), "f32", "f32", 3.0, 0.0, 80, 2e-3),
     ((6, 21, 23), "f32", "f32", 1.0, 0.0, 4, 0.0),
@@ -380,7 +379,7 @@ def test_full_size_two_iterations_sampled(rsf, large):
         assert abs(got[c] - want[local]) < 4e-6, (c, got[c], want[local])
 
 
-@pytest.mark.parametrize("storage", ["f32"])
+@pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_full_size_fused_equals_separate_passes(rsf, large, storage):
     mod, ctx = rsf
     w, I, phi0 = large

@@ -482,13 +482,11 @@ def test_autotune_keeps_results(rsf):
 
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
 # alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
-# tiles of at most 8 slices; with the RSF force only up to radius 10 and in
-# FP32 storage (with 16-bit storage the fused update did not reproduce the
-# separate passes bitwise at 512^3, so those run separately).
+# tiles of at most 8 slices; with the RSF force only up to radius 10.
 RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
     ((40, 770, 256), "f32", "f32", 3.0, 9, 0.0, True),
-    ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, False),   # 16-bit storage: separate
-    ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, False),
+    ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, True),
+    ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, True),
     ((8, 34, 34), "f32", "f32", 3.0, 80, 2e-3, True),
     ((6, 21, 23), "f32", "f32", 1.0, 4, 0.0, True),
     ((8, 30, 30), "f32", "f32", 3.4, 5, 0.0, False),   # R = 11: separate passes
@@ -525,7 +523,7 @@ def test_fused_update_is_bitwise_the_separate_passes(rsf, shape, image, storage,
     assert zh_a == iters and zh_b == (1 if fused else iters)
 
 
-@pytest.mark.parametrize("storage", ["f32"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_full_size_fused_equals_separate_passes(rsf, large, storage):
     mod, ctx = rsf
     w, I, phi0 = large
@@ -544,3 +542,19 @@ def test_full_size_fused_equals_separate_passes(rsf, large, storage):
     ctx.set_fusion(True)
     torch.cuda.synchronize()
     assert torch.equal(out[0], out[1])
+
+
+def test_full_size_f16_storage_deterministic_and_resumable(rsf, large):
+    mod, ctx = rsf
+    w, I, phi0 = large
+    say(f"{w.name}: FP16 storage, determinism and resume")
+    vol = dev(I)
+    p = mod.make_params(**w.params(), storage="f16")
+    a, b, c = dev(phi0), dev(phi0), dev(phi0)
+    ctx.evolve_ex(vol, a, p, w.iters)
+    ctx.evolve_ex(vol, b, p, w.iters)
+    ctx.evolve_ex(vol, c, p, 120)
+    ctx.evolve_ex(vol, c, p, w.iters - 120)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert bool(torch.isfinite(a).all())
