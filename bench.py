@@ -57,6 +57,11 @@ def pass_bytes(image_bytes: int = 4, storage_bytes: int = 4, paper: bool = False
     }
 
 
+# The paper's own per-step time (Table 1: 500^3 volume, unstated GPU and
+# precision, sigma2 = 0 so no force convolution), quoted as context only.
+PAPER_CONTEXT = {"ms_per_step": 585.0, "gvoxel_iter_s": 0.214, "volume": "500^3",
+                 "hardware": "unstated CUDA GPU", "source": "Table 1 (sum of per-kernel times)"}
+
 PASS_BYTES = pass_bytes()               # FP32 image and fields
 ITER_BYTES = sum(PASS_BYTES.values())   # 72 B per voxel-iteration
 COPY_BYTES = 1 << 30
@@ -178,9 +183,48 @@ def ingest_counters(fetch_dir: str, write_dir: str, workload: str, copy_bytes: i
     return data
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def cpu_one_core_small(force: int = 0) -> dict:
+    """The oracle on one core on the small parity configuration (64^3 vessel
+    phantom, sigma 3, 20 iterations), whole."""
+    import oracle
+    from paper_2404_02813_amd import inputs
+
+    w = inputs.SMALL_64
+    I, phi0 = w.image(), w.phi0()
+    p = oracle.params_array(**w.params(), eta=1e-10, force=force)
+    before = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.evolve(I, phi0, p, w.iters)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(before)
+    return {"workload": w.name, "value": round(w.voxels * w.iters / dt / 1e9, 6),
+            "unit": "Gvoxel-iter/s", "cores": 1, "seconds": round(dt, 2)}
+
+
 def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = "", force: int = 0):
     """The FP64 oracle on a centred crop (at most 192 per axis) of the same
-    image and phi0 (bounded sample)."""
+    image and phi0 (bounded sample), on every core the process may use."""
     import numpy as np
 
     import oracle
@@ -202,7 +246,8 @@ def cpu_baseline(w, I, phi0, seconds_hint: float = 20.0, what: str = "", force: 
     return {"value": vox_iters / dt / 1e9, "unit": "Gvoxel-iter/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{shape} (z,y,x) centre crop of {what or 'the ' + w.name + ' phantom'} "
-                      f"and its phi0, {iters} iterations, {dt:.1f} s"}
+                      f"and its phi0, {iters} iterations, {dt:.1f} s",
+            **host_cpu()}
 
 
 def copy_bandwidth(torch) -> float:
@@ -292,13 +337,17 @@ def run_tiles(args, w) -> int:
         ctx.evolve_batch(vols, ph, params, w.iters)
     steps = [fresh() for _ in range(K)]
     copy_gbs = copy_bandwidth(torch)
-    ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ph in steps:
         ctx.evolve_batch(vols, ph, params, w.iters)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # per-pass launch times from one more (untimed) batch with the events on
+    ph = fresh()
+    ctx.profile(True)
+    ctx.evolve_batch(vols, ph, params, w.iters)
+    torch.cuda.synchronize()
     ctx.profile(False)
     prof = ctx.profile_read()
     same = all(torch.equal(a, b) for a, b in zip(steps[-1], loop_result))
@@ -370,14 +419,19 @@ def run_volume(args, w, block: int) -> int:
         ctx.evolve_volume(vol, ph, params, w.iters, block)
     phis = [phi0.clone() for _ in range(K)]
     torch.cuda.synchronize()
-    ctx.profile(True)
     t0 = time.perf_counter()
     for ph in phis:
         ctx.evolve_volume(vol, ph, params, w.iters, block)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # per-pass launch times from one more (untimed) run with the events on
+    ph = phi0.clone()
+    ctx.profile(True)
+    ctx.evolve_volume(vol, ph, params, w.iters, block)
+    torch.cuda.synchronize()
     ctx.profile(False)
     prof = ctx.profile_read()
+    del ph
     plain = phi0.clone()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -669,7 +723,7 @@ def run_serve(args, w) -> int:
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f16 storage, u16 image)",
+        "dtype": "f32",   # arithmetic type; storage and image types are in config
         "data": "synthetic",
         "config": {"workload": w.name, "volume_zyx": list(w.shape), "requests": len(reqs),
                    "edges": [w.edges[0], w.edges[-1], w.edges[1] - w.edges[0]],
@@ -793,17 +847,23 @@ def main() -> int:
 
     copy_gbs = copy_bandwidth(torch)
 
-    ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for ph in phis:
         ctx.evolve_ex(vol, ph, params, w.iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.profile(False)
-    prof = ctx.profile_read()
     _, iters_run, last_s, _ = ctx.stats(cap=0)
     ok = bool(torch.isfinite(phis[-1]).all().item()) and bool(np.isfinite(last_s))
+    # per-pass launch times from one more evolution with the library's HIP
+    # events on (outside the timed steps: the events add host work per launch)
+    scratch.copy_(phi0)
+    ctx.profile(True)
+    ctx.evolve_ex(vol, scratch, params, w.iters)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    prof = ctx.profile_read()
+    same = torch.equal(scratch, phis[-1])
     # the fused update launched the stage-1 pass once per evolution
     fused = prof["z_heaviside"][0] < prof["z_update"][0]
     if fused:
@@ -825,7 +885,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32",   # arithmetic type; the storage type is config.storage
         "data": "synthetic",
         "config": {"workload": args.workload, "shape_zyx": list(w.shape), "sigma": w.sigma,
                    "image": image_t, "storage": storage_t,
@@ -841,7 +901,9 @@ def main() -> int:
         "copy_gbs": round(copy_gbs, 1),
         "iters_run": iters_run,
         "finite": ok,
+        "profiled_run_equals_timed_bitwise": bool(same),
         "input_gen_s": round(t_gen, 1),
+        "paper_context": PAPER_CONTEXT,
     }
     ctx.close()
     del phis, vol, phi0, scratch
@@ -850,8 +912,9 @@ def main() -> int:
         img = I_host.astype("float64") / 65535.0 if image_t == "u16" else I_host
         out["cpu_baseline"] = cpu_baseline(w, img, phi0_host, args.cpu_seconds,
                                            force=1 if paper else 0)
+        out["cpu_baseline"]["one_core_small"] = cpu_one_core_small(force=1 if paper else 0)
     print(json.dumps(out), flush=True)
-    return 0 if ok else 1
+    return 0 if ok and same else 1
 
 
 if __name__ == "__main__":

@@ -29,7 +29,14 @@
  *   - Every entry validates its arguments before enqueuing anything and leaves
  *     its outputs untouched on a validation error.  No C++ exception crosses
  *     the ABI.  rsf_last_error() describes the last failure on a context.
- *   - A context is not thread-safe: use one per host thread.
+ *   - A context is not thread-safe: use one per host thread.  Calls on one
+ *     context may use different streams: a call that uses the context's own
+ *     workspace first makes its stream wait (on the device) for the end of
+ *     the previous such call.  A caller-supplied workspace is the caller's
+ *     to order.
+ *   - Every xy plane is at most 2^28 voxels (nx * ny <= 268435456): kernels
+ *     address a slice with 32-bit offsets.  Larger planes give
+ *     RSF_ERR_INVALID_ARG.
  */
 #ifndef RSF_H
 #define RSF_H

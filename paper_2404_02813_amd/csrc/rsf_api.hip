@@ -38,6 +38,12 @@ struct rsf_context {
     std::string err;
     void *ws = nullptr;          // owned workspace
     size_t ws_bytes = 0;
+    // the stream of the last call that used the owned workspace and an event
+    // recorded at its end: a call on another stream waits for it on the
+    // device before it touches the workspace
+    hipStream_t ws_stream = nullptr;
+    hipEvent_t ws_ev = nullptr;
+    bool ws_pending = false;
     // pinned staging of the tile table, and the event of its last upload
     void *stage = nullptr;
     size_t stage_bytes = 0;
@@ -210,6 +216,27 @@ rsf_status ensure_ws(rsf_context *ctx, size_t bytes)
     HIP_TRY(hipMalloc(&p, bytes), "hipMalloc(workspace)");
     ctx->ws = p;
     ctx->ws_bytes = bytes;
+    return RSF_OK;
+}
+
+// Order a call that uses the owned workspace on stream s after the previous
+// such call: on another stream, s first waits (on the device) for the event
+// recorded at the end of that call.  ws_leave records it.
+rsf_status ws_enter(rsf_context *ctx, hipStream_t s)
+{
+    if (ctx->ws_pending && ctx->ws_stream != s)
+        HIP_TRY(hipStreamWaitEvent(s, ctx->ws_ev, 0), "hipStreamWaitEvent(workspace)");
+    return RSF_OK;
+}
+
+rsf_status ws_leave(rsf_context *ctx, hipStream_t s)
+{
+    if (!ctx->ws_ev)
+        HIP_TRY(hipEventCreateWithFlags(&ctx->ws_ev, hipEventDisableTiming),
+                "hipEventCreate(workspace)");
+    HIP_TRY(hipEventRecord(ctx->ws_ev, s), "hipEventRecord(workspace)");
+    ctx->ws_stream = s;
+    ctx->ws_pending = true;
     return RSF_OK;
 }
 
@@ -464,6 +491,10 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     }
     char *base = static_cast<char *>(workspace ? workspace : ctx->ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!workspace) {
+        st = ws_enter(ctx, s);
+        if (st != RSF_OK) return st;
+    }
     Plan P;
     st = make_plan(ctx, P, tiles, n, vdt, p, tol, iters, base, s);
     if (st != RSF_OK) return st;
@@ -480,6 +511,10 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     }
     // tiles that ended on an odd iteration have it in the workspace buffer
     if (iters > 0) HIP_TRY(rsf::launch_finish(P.z, P.blocks_z, s), "finish");
+    if (!workspace) {
+        st = ws_leave(ctx, s);
+        if (st != RSF_OK) return st;
+    }
     ctx->last_stream = s;
     ctx->last_hist.clear();
     ctx->last_flags.clear();
@@ -591,6 +626,7 @@ void rsf_destroy(rsf_context *ctx)
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->stage) (void)hipHostFree(ctx->stage);
         if (ctx->stage_ev) (void)hipEventDestroy(ctx->stage_ev);
+        if (ctx->ws_ev) (void)hipEventDestroy(ctx->ws_ev);
         for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     } catch (...) {
     }
@@ -768,7 +804,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                         const rsf_params *params, int trial_iters, int64_t *chosen,
                         void *stream)
 {
-    float *scratch = nullptr;
+    float *trial_phi = nullptr;
     try {
         if (!ctx) return RSF_ERR_INVALID_ARG;
         ctx->err.clear();
@@ -791,14 +827,14 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
             off.push_back(total);
             total += align_up((size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float));
         }
-        HIP_TRY(hipMalloc(&scratch, total), "hipMalloc(autotune scratch)");
+        HIP_TRY(hipMalloc(&trial_phi, total), "hipMalloc(autotune trial_phi)");
         std::vector<rsf_tile> tt(tiles, tiles + n_tiles);
         for (int t = 0; t < n_tiles; ++t) {
-            tt[t].phi = reinterpret_cast<float *>(reinterpret_cast<char *>(scratch) + off[t]);
+            tt[t].phi = reinterpret_cast<float *>(reinterpret_cast<char *>(trial_phi) + off[t]);
             const size_t bytes = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float);
             hipError_t e = hipMemcpyAsync(tt[t].phi, tiles[t].phi, bytes, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) {
-                (void)hipFree(scratch);
+                (void)hipFree(trial_phi);
                 return hip_fail(ctx, e, "autotune copy");
             }
         }
@@ -836,6 +872,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                                 splits_for(ctx, tt.data(), n_tiles, R),
                                 rsf::host::needs_k2(*params)).total;
                 st = ensure_ws(ctx, need);
+                if (st == RSF_OK) st = ws_enter(ctx, s);
                 if (st != RSF_OK) break;
                 ctx->has_last = false;   // the trials overwrite the workspace
                 Plan P;
@@ -848,6 +885,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 float ms = 0.f;
                 if (st == RSF_OK) st = iteration(ctx, P, false, s, fused);   // warm-up
                 if (st == RSF_OK) st = time_iterations(ctx, P, trial_iters, s, &ms, fused);
+                if (st == RSF_OK) st = ws_leave(ctx, s);
                 if (st != RSF_OK) break;
                 if (best_ms < 0.f || ms < best_ms) {
                     best_ms = ms;
@@ -869,10 +907,10 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 ctx->tuned.erase({tiles[t].nx, tiles[t].ny, tiles[t].nz, R});
         }
         (void)hipStreamSynchronize(s);
-        (void)hipFree(scratch);
+        (void)hipFree(trial_phi);
         return st;
     } catch (...) {
-        if (scratch) (void)hipFree(scratch);
+        if (trial_phi) (void)hipFree(trial_phi);
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
 }
@@ -1245,11 +1283,15 @@ rsf_status rsf_gauss3d(rsf_context *ctx, const float *in, float *out, int64_t nx
                                 .total);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
+        st = ws_enter(ctx, s);
+        if (st != RSF_OK) return st;
+        ctx->has_last = false;   // the workspace is reused
         Plan P;
         st = make_plan(ctx, P, &t, 1, RSF_F32, p, 0.0, 0, static_cast<char *>(ctx->ws), s,
                        nullptr, out);
+        if (st == RSF_OK) st = prologue(ctx, P, s);
         if (st != RSF_OK) return st;
-        return prologue(ctx, P, s);
+        return ws_leave(ctx, s);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
@@ -1280,13 +1322,16 @@ rsf_status rsf_probe(rsf_context *ctx, const void *volume, int volume_dtype, con
                                 .total);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
+        st = ws_enter(ctx, s);
+        if (st != RSF_OK) return st;
+        ctx->has_last = false;   // the workspace is reused
         Plan P;
         st = make_plan(ctx, P, &t, 1, volume_dtype, *params, 0.0, 1,
                        static_cast<char *>(ctx->ws), s, fields);
+        if (st == RSF_OK) st = prologue(ctx, P, s);
+        if (st == RSF_OK) st = iteration(ctx, P, true, s);
         if (st != RSF_OK) return st;
-        st = prologue(ctx, P, s);
-        if (st != RSF_OK) return st;
-        return iteration(ctx, P, true, s);
+        return ws_leave(ctx, s);
     } catch (...) {
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }

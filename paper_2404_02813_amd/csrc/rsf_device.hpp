@@ -9,17 +9,42 @@ namespace rsf {
 
 namespace {
 
-constexpr float kInvPi = 0.318309886183790671538f;
 constexpr float kTwoPi = 6.28318530717958647693f;
 
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// H_eps(phi) = 1/2 (1 + (2/pi) atan(phi/eps)) (Sec. 3, regularised
+// Heaviside).  With a = |phi| and t = min(a, eps)/max(a, eps) in [0, 1],
+// q = atan(t)/pi = t P(t^2), and
+//   a <= eps:    H = 1/2 + sign(phi) q
+//   phi < -eps:  H = q        (= atan(eps/|phi|)/pi: full relative precision
+//                              as H -> 0, like atan2(eps, -phi)/pi)
+//   phi > eps:   H = 1 - q
+// P is the degree-8 polynomial of least maximum relative error for
+// atan(sqrt(u))/(pi sqrt(u)) on u in [0, 1] (Remez exchange; 1.5e-8, below
+// a quarter FP32 ulp), so H is within about 1e-7 of the exact value: as
+// accurate as the library atan2f at a third of its instructions, with one
+// reciprocal and no range-reduction branches (csrc/atan_poly.py prints the
+// coefficients).
 __device__ __forceinline__ float heaviside(float phi, float eps)
 {
-    // 1/2 (1 + (2/pi) atan(phi/eps)) written as atan2(eps, -phi)/pi, which
-    // keeps full relative precision for large negative phi.
-    return atan2f(eps, -phi) * kInvPi;
+    const float a = fabsf(phi);
+    const float t = fminf(a, eps) * rcp(fmaxf(a, eps));
+    const float u = t * t;
+    float p = 9.071479804014546e-4f;
+    p = fmaf(p, u, -5.114803217655306e-3f);
+    p = fmaf(p, u, 1.358913226569387e-2f);
+    p = fmaf(p, u, -2.3886911108485072e-2f);
+    p = fmaf(p, u, 3.387114486444002e-2f);
+    p = fmaf(p, u, -4.521160451520202e-2f);
+    p = fmaf(p, u, 6.363848403138736e-2f);
+    p = fmaf(p, u, -1.0610246782661932e-1f);
+    p = fmaf(p, u, 3.183098813345913e-1f);
+    const float q = t * p;
+    const float inner = 0.5f + copysignf(q, phi);
+    const float outer = phi < 0.f ? q : 1.f - q;
+    return a <= eps ? inner : outer;
 }
-
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // The tile table hands the kernels generic pointers.  Recasting them to the
 // global address space lets the compiler use global instead of flat memory
@@ -31,6 +56,27 @@ template <class T>
 __device__ __forceinline__ gptr<T> glb(T *p)
 {
     return (gptr<T>)p;
+}
+
+// Element i of a slice: a wave-uniform 64-bit slice base (scalar registers)
+// plus a 32-bit unsigned in-slice byte offset.  The compiler then emits the
+// scalar-base form of the global loads and stores, with one 32-bit offset
+// register per lane and no 64-bit address arithmetic per access.  Planes
+// are limited so that every such offset fits (kMaxPlane).
+template <class T>
+__device__ __forceinline__ gptr<T> at32(gptr<T> base, uint32_t i)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return (gptr<T>)((gptr<B>)base + i * (uint32_t)sizeof(T));
+}
+
+// A wave-uniform element of read-only device data (tables written before the
+// kernel starts) through the scalar data cache: one scalar load, no vector
+// register.
+template <class T>
+__device__ __forceinline__ T uniform_ld(const T *p, int i)
+{
+    return ((__attribute__((address_space(4))) const T *)p)[i];
 }
 
 // Storage and image element types: fields may be stored as float, FP16 or
@@ -78,6 +124,15 @@ __device__ __forceinline__ void st_pair(gptr<Pair<T>> p, int64_t i, float a, flo
     v.x = from_f<T>(a);
     v.y = from_f<T>(b);
     ((gptr<Vec2<T>>)p)[i] = v;
+}
+
+template <class T>
+__device__ __forceinline__ void st_pair32(gptr<Pair<T>> p, uint32_t i, float a, float b)
+{
+    Vec2<T> v;
+    v.x = from_f<T>(a);
+    v.y = from_f<T>(b);
+    *at32((gptr<Vec2<T>>)p, i) = v;
 }
 
 // Value of lane `src` (wave-uniform) of v.  Lanes past a volume edge store

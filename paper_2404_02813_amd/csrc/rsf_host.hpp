@@ -57,9 +57,11 @@ inline Coeffs make_coeffs(const rsf_params &p, double tol)
 inline const char *dims_error(int64_t nx, int64_t ny, int64_t nz)
 {
     if (nx < 3 || ny < 3 || nz < 3) return "every dimension must be >= 3";
-    // column indices y nx + x (plus a workgroup's overhang) stay below 2^31
+    // in-slice byte offsets of 8-byte elements, y nx + x plus a workgroup's
+    // overhang, stay below 2^32 (kernels address a slice with a 32-bit
+    // unsigned offset from a 64-bit slice base)
     if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) ||
-        nx * ny > ((int64_t)1 << 31) - 1024 || nx * ny > INT64_MAX / nz)
+        nx * ny > kMaxPlane || nx * ny > INT64_MAX / nz)
         return "volume too large";
     return nullptr;
 }

@@ -20,6 +20,9 @@ constexpr int kThreads = 256;      // z pass block: consecutive columns
 constexpr int kUx = 64;            // update pass: columns per block along x
 constexpr int kUy = 8;             // update pass: columns per block along y
 constexpr int kUThreads = kUx * kUy;
+// Largest xy plane (voxels): every in-slice byte offset of an 8-byte
+// element, with a workgroup's overhang, fits a 32-bit unsigned offset.
+constexpr int64_t kMaxPlane = (int64_t)1 << 28;
 
 // Image/storage combinations other than (F32, F32) are built for radii
 // kMinRMixed..kMaxRMixed.

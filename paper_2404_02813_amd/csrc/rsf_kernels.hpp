@@ -23,8 +23,20 @@ namespace {
 // reads the pair P and K*I and writes the pair Q; XY_TWO reads the pair Q and
 // writes the pair P; XY_PAPER reads the pair P, K*I and the image (IMG) and
 // writes the force of Sec. 4.2 with sigma2 = 0 to Q as float.
+// At least five waves per SIMD (at most 96 registers) where the ring of
+// 2R + 2 rows and the stages fit without spilling: radius <= 8, or 9 except
+// for the fits of 16-bit storage.  Otherwise, and for the Sec. 4.2 force
+// modes (more pointwise inputs), the compiler's own choice (no bound).
+template <int R, int MODE, class ST>
+constexpr int xy_waves_per_eu =
+    (MODE == XY_ONE || MODE == XY_TWO || MODE == XY_FITS) &&
+            (R <= 8 || (R == 9 && (std::is_same<ST, float>::value || MODE != XY_FITS)))
+        ? 5
+        : 1;
+
 template <int R, int MODE, class IN, class ST, class IMG = float>
-__global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(xy_waves_per_eu<R, MODE, ST>)))
+void xy_kernel(Batch bt, Taps t, Coeffs c)
 {
     constexpr bool PAPER_F = MODE == XY_PAPER || MODE == XY_PAPER2;
     constexpr bool FITS = MODE == XY_FITS || PAPER_F;
@@ -80,20 +92,26 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         }
         return r;
     };
-    // stage row y (fetched) into LDS slot `slot`, x-convolve it, return the
-    // lane's value
-    auto xrow = [&](const Raw &r, int y, int slot) -> float2 {
+    // Stage row y (fetched) into LDS slot `slot`, run `between` (work that
+    // does not touch the row: the next y convolution, whose two sums it
+    // returns), x-convolve the row and return the lane's value.  `between`
+    // and the x-convolution's LDS reads share one scheduling region (the
+    // wave sync opens it, one `pin` of all four sums closes it), so its FMAs
+    // can fill the reads' latency.  Values outside the slice are zeroed by a
+    // bit mask, not a branch, so staging opens no new region either.
+    auto xrow = [&](const Raw &r, int y, int slot, auto &&between, float2 &yv) -> float2 {
         const bool yok = y >= 0 && y < g.ny;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = lane + 64 * h;
             const int gx = x0 - R + j;
-            const bool ok = yok && gx >= 0 && gx < g.nx;
+            const int keep = (yok && gx >= 0 && gx < g.nx) ? -1 : 0;
+            auto masked = [&](float v) { return __int_as_float(__float_as_int(v) & keep); };
             if (NF == 2) {
-                row[slot][0][j] = ok ? to_f(r.p[h].x) : 0.f;
-                row[slot][NF - 1][j] = ok ? to_f(r.p[h].y) : 0.f;
+                row[slot][0][j] = masked(to_f(r.p[h].x));
+                row[slot][NF - 1][j] = masked(to_f(r.p[h].y));
             } else {
-                const float v = ok ? to_f(r.s[h]) : 0.f;
+                const float v = masked(to_f(r.s[h]));
                 row[slot][0][j] = c.square ? v * v : v;
             }
         }
@@ -101,22 +119,28 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         // (a workgroup barrier's fence would also wait for the global stores
         // and loads in flight)
         __syncwarp();
+        yv = between();
         float ca = 0.f, cb = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             ca = fmaf(t.w[k], row[slot][0][lane + k], ca);
             if (NF == 2) cb = fmaf(t.w[k], row[slot][NF - 1][lane + k], cb);
         }
-        pin(ca);
-        if (NF == 2) pin(cb);
+        __asm__ volatile("" : "+v"(ca), "+v"(cb), "+v"(yv.x), "+v"(yv.y));
         return make_float2(ca, cb);
     };
+    auto nothing = [] { return make_float2(0.f, 0.f); };
 
     // Prefetch depth as in the update pass: two stages (a row and the
     // pointwise inputs of one step) alternate by step parity where the
-    // registers allow, so the march is unrolled by an even M >= 2R + 1.
+    // registers allow.  The x convolution runs one row ahead of the y
+    // convolution: step y x-convolves row y + R + 1 (for the next step) while
+    // it y-convolves output y from rows already in the ring, so the LDS reads
+    // of the one overlap the FMAs of the other.  The ring therefore holds
+    // 2R + 2 rows, and the march is unrolled by M = 2R + 2 (even, as the
+    // alternating stages need).
     constexpr int PF = R <= 10 ? 2 : 1;
-    constexpr int M = PF == 2 ? W + 1 : W;
+    constexpr int M = W + 1;
     const int xc = min(x, g.nx - 1);
     const int last = min(63, g.nx - 1 - x0);   // last in-slice lane of the strip
     const gptr<const ST> ki_slice = glb(static_cast<const ST *>(d.KI)) + zb;
@@ -125,7 +149,7 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     const gptr<const ST> k2q_slice = glb(static_cast<const ST *>(d.K2I2)) + zb;
     const gptr<const float> cyp = glb(d.cy);
     const float cxz = FITS ? glb(d.cx)[xc] * glb(d.cz)[z] : 0.f;
-    // the loads of step y: row y + R and the fits' pointwise inputs of row y
+    // the loads of step y: row y + R + 1 and the fits' pointwise inputs of row y
     struct Stage {
         Raw row;
         ST ki, k2i, k2q;
@@ -134,7 +158,7 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
     };
     auto stage = [&](int y) {
         Stage st;
-        st.row = fetch(y + R);
+        st.row = fetch(y + R + 1);
         if (FITS) {
             const int yy = min(y, g.ny - 1);
             const int o = yy * g.nx + xc;
@@ -149,20 +173,23 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         return st;
     };
 
+    // prologue: rows y0 - R .. y0 + R x-convolved into ring slots 0..2R (row
+    // y0 - R + j staged in LDS slot j & 1)
     float ra[M], rb[M];
     Stage sa, sb;
     {
         Raw nxt = fetch(y0 - R);
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) {
+        for (int j = 0; j <= 2 * R; ++j) {
             const Raw cur = nxt;
-            if (j + 1 < 2 * R) {
+            if (j < 2 * R) {
                 nxt = fetch(y0 - R + j + 1);
             } else {
                 sa = stage(y0);
                 if (PF == 2) sb = stage(y0 + 1);
             }
-            const float2 v = xrow(cur, y0 - R + j, j & 1);
+            float2 unused;
+            const float2 v = xrow(cur, y0 - R + j, j & 1, nothing, unused);
             ra[j] = v.x;
             rb[j] = v.y;
             __builtin_amdgcn_sched_barrier(0);
@@ -180,17 +207,33 @@ __global__ __launch_bounds__(64) void xy_kernel(Batch bt, Taps t, Coeffs c)
         const ST ki_raw = cur.ki, k2i_raw = cur.k2i, k2q_raw = cur.k2q;
         const IMG im_raw = cur.im;
         const float cyv = cur.cy;
-        // row y + R is the (y - y0 + 2R)-th staged row: slot parity (y - y0) & 1
-        const float2 xv = xrow(rw, y + R, (y - y0) & 1);
-        cur = stage(y + PF);
-        ra[(s + 2 * R) % M] = xv.x;
-        rb[(s + 2 * R) % M] = xv.y;
-        float acc_a = 0.f, acc_b = 0.f;
+        // Output y from ring rows y - R .. y + R (slots s .. s + 2R), computed
+        // while row y + R + 1 is x-convolved for the next step (also on a
+        // chunk's last step: no branch; the row is clamped and zero-padded
+        // like any other).  That row is the (y - y0 + 2R + 1)-th staged one:
+        // LDS slot parity (y - y0 + 1) & 1.
+        auto yconv = [&] {
+            float a = 0.f, b = 0.f;
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            acc_a = fmaf(t.w[k], ra[(s + k) % M], acc_a);
-            if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % M], acc_b);
+            for (int k = 0; k < W; ++k) {
+                a = fmaf(t.w[k], ra[(s + k) % M], a);
+                if (NF == 2) b = fmaf(t.w[k], rb[(s + k) % M], b);
+            }
+            return make_float2(a, b);
+        };
+        float2 acc, xv;
+        if constexpr (MODE == XY_PAPER2) {
+            // four pointwise inputs per step: interleaving would spill
+            float2 unused;
+            acc = yconv();
+            xv = xrow(rw, y + R + 1, (y - y0 + 1) & 1, nothing, unused);
+        } else {
+            xv = xrow(rw, y + R + 1, (y - y0 + 1) & 1, yconv, acc);
         }
+        const float acc_a = acc.x, acc_b = acc.y;
+        ra[(s + 2 * R + 1) % M] = xv.x;
+        rb[(s + 2 * R + 1) % M] = xv.y;
+        cur = stage(y + PF);
         // every lane stores: one past the slice edge (x >= nx) writes the
         // value of the last in-slice lane to that lane's element (same bits)
         const int v = y * g.nx + xc;     // offset within the slice
@@ -432,7 +475,10 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
     constexpr int QS = QY * QX;
     constexpr int NPHI = 6, NQ = 3;
     constexpr int NLD = (PX * PY + NT - 1) / NT;
-    __shared__ float sphi[NPHI][PY * PX];
+    // each slot is padded to NLD * NT entries, so that every thread stores
+    // its NLD loaded points with no branch (points past the tile land in
+    // the padding, never read)
+    __shared__ float sphi[NPHI][NLD * NT];
     __shared__ float sq[NQ][4][QS];   // n_x, V_x, n_y, V_y
     __shared__ double wsum[NT / 64];
 
@@ -455,16 +501,14 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
 
     {
         // phi tile loads: reflected in-slice offsets of this thread's points
-        int loff[NLD];
-        bool lok[NLD];
+        uint32_t loff[NLD];
 #pragma unroll
         for (int r = 0; r < NLD; ++r) {
             const int i = tid + r * NT;
-            lok[r] = i < PX * PY;
             const int px = i % PX, py = i / PX;
             const int gx = reflect(min(x0 - 2 + px, g.nx + 1), g.nx);
-            const int gy = reflect(min(y0 - 2 + py, g.ny + 1), g.ny);
-            loff[r] = gy * g.nx + gx;
+            const int gy = reflect(min(y0 - 2 + min(py, PY - 1), g.ny + 1), g.ny);
+            loff[r] = (uint32_t)(gy * g.nx + gx);
         }
         struct PhiRaw {
             float v[NLD];
@@ -472,22 +516,21 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         // Slices used for outputs lie in [-2, nz + 1]; the march also touches
         // up to nz + 4 (prefetch and n, V past the chunk end, never used), so
         // clamp before reflecting to keep every address inside the volume.
-        // Lanes past the tile (!lok) load a reflected in-volume point too and
-        // drop it: every prefetch is an unconditional load, so no branch
-        // forces a wait on the loads in flight.
+        // Lanes past the tile load a reflected in-volume point too and store
+        // it to the slot's padding: every prefetch is an unconditional load,
+        // so no branch forces a wait on the loads in flight.
         auto fetch_phi = [&](int j) {
             PhiRaw r;
             const gptr<const float> base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
 #pragma unroll
-            for (int k = 0; k < NLD; ++k) r.v[k] = base[loff[k]];
+            for (int k = 0; k < NLD; ++k) r.v[k] = *at32(base, loff[k]);
             return r;
         };
         auto phi_slot = [&](int j) { return sphi[(j + 2 * NPHI) % NPHI]; };
         auto store_phi = [&](const PhiRaw &r, int j) {
             float *dst = phi_slot(j);
 #pragma unroll
-            for (int k = 0; k < NLD; ++k)
-                if (lok[k]) dst[tid + k * NT] = r.v[k];
+            for (int k = 0; k < NLD; ++k) dst[tid + k * NT] = r.v[k];
         };
         // n and V at phi-tile point (cx, cy) of slice j
         auto qcalc = [&](int j, int cx, int cy, float &nx_, float &vx_, float &ny_, float &vy_,
@@ -527,11 +570,12 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             }
         };
 
-        const int col = min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1);
+        const uint32_t col = (uint32_t)(min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1));
         const float cxy = glb(d.cx)[min(zt.x, g.nx - 1)] * glb(d.cy)[min(zt.y, g.ny - 1)];
-        const gptr<const float> czp = glb(d.cz);
         const gptr<const IT> img = glb(static_cast<const IT *>(d.I));
-        auto pair_at = [&](int z) { return ld_pair_raw<ST>(tp + (int64_t)z * g.sxy, col); };
+        auto pair_at = [&](int z) {
+            return *at32((gptr<const Vec2<ST>>)(tp + (int64_t)z * g.sxy), col);
+        };
         const int z0 = zt.z0;
         // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
 #pragma unroll
@@ -595,7 +639,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         const gptr<const float> fdp = glb(static_cast<const float *>(d.Q));
         using IRaw = typename std::conditional<PAPER, float, IT>::type;
         const gptr<const IRaw> ip = PAPER ? (gptr<const IRaw>)fdp : (gptr<const IRaw>)img;
-        auto iraw = [&](int z) { return (ip + (int64_t)z * g.sxy)[col]; };
+        auto iraw = [&](int z) { return *at32(ip + (int64_t)z * g.sxy, col); };
         struct Stage {
             PhiRaw phi;    // phi slice z + 3
             Vec2<ST> t;    // conv inputs of slice z + R
@@ -608,9 +652,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             st.phi = fetch_phi(z + 3);
             if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
             st.I = iraw(min(z, zmax));
-            st.cz = PAPER ? 0.f : czp[min(z, zmax)];
+            st.cz = PAPER ? 0.f : uniform_ld(d.cz, min(z, zmax));
             // (RSF force: the image of slice z is already st.I)
-            if constexpr (FUSE && PAPER) st.img = (imgp + (int64_t)min(z, zmax) * g.sxy)[col];
+            if constexpr (FUSE && PAPER) st.img = *at32(imgp + (int64_t)min(z, zmax) * g.sxy, col);
             return st;
         };
         Stage sa = stage(z0), sb{};
@@ -637,7 +681,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                     pin(acc_a);
                     pin(acc_b);
                 }
-                if (z >= R && zt.active) st_pair<ST>(tout + (int64_t)(z - R) * g.sxy, col, acc_a, acc_b);
+                if (z >= R && zt.active) st_pair32<ST>(tout + (int64_t)(z - R) * g.sxy, col, acc_a, acc_b);
             }
         };
         // step z (s = its index in the unrolled block) consumes stage `cur`
@@ -706,7 +750,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                 const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
                 const float nxt = cphi + ua.dt * E;
-                (phi_out + zo)[col] = nxt;
+                *at32(phi_out + zo, col) = nxt;
                 acc += fabs((double)nxt - (double)cphi);
                 if constexpr (FUSE) {
                     Hs = heaviside(nxt, ua.eps);
