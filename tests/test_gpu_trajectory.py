@@ -120,7 +120,29 @@ def test_fused_update_trajectory_matches_oracle(rsf, slab, storage):
     assert prof["z_update"][0] == w.iters and run == w.iters
     r = report(got, want)
     assert r["max"] <= phi_tol(storage) and r["agree"] >= SIGN_AGREE
-    assert np.max(np.abs(np.array(hist) / whist - 1.0)) < (1e-2 if storage == "f32" else 5e-2)
+    # The history s_n = sum |phi_{n+1} - phi_n| is the GPU's own: the last
+    # entry equals the FP64 sum over its own last two iterates (resumed at
+    # 199, bitwise the same trajectory), up to the grouping of the sum.
+    params = mod.make_params(**w.params(), storage=storage)
+    p199 = torch.from_numpy(phi0).cuda()
+    ctx.evolve_ex(vol, p199, params, w.iters - 1)
+    p200 = p199.clone()
+    ctx.evolve_ex(vol, p200, params, 1)
+    _, _, last, _ = ctx.stats(cap=0)
+    torch.cuda.synchronize()
+    assert torch.equal(p200, phi)
+    own = float(np.sum(np.abs(p200.cpu().numpy().astype(np.float64) -
+                              p199.cpu().numpy().astype(np.float64))))
+    assert last == pytest.approx(own, rel=1e-9)
+    assert hist[-1] == pytest.approx(own, rel=1e-9)
+    # Against the FP64 oracle's history the sums differ by the FP32 arithmetic
+    # of phi itself: s_n adds up millions of far-field increments of a few
+    # FP32 ulps of |phi| ~ 2, so their rounding shifts the sum by percents
+    # while max|dphi| stays ~1e-5.  The oracle's own float build on this slab
+    # differs from its FP64 run by up to 3.8 % in s_n (2.6e-5 in phi).
+    rel = np.abs(np.array(hist) / whist - 1.0)
+    say(f"  max relative s_n difference {rel.max():.4f} (iteration {int(rel.argmax())})")
+    assert rel.max() < (0.1 if storage == "bf16" else 0.05)
 
 
 MIXED = (128, 256, 256)
