@@ -266,6 +266,39 @@ def copy_bandwidth(torch) -> float:
     return 5 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+# Read and write mixes of the passes in 4-byte fields per voxel (FP32 storage):
+# the stage-1 z pass reads phi and I and writes the pair; the fits read the
+# stage-1 pair and K*I and write (g1, g2); the force pass reads and writes one
+# pair; the update reads the stage-2 pair, I and phi and writes phi' (and,
+# fused, the next stage-1 pair).
+STREAM_MIXES = {"copy": (1, 1), "z_heaviside": (2, 2), "xy_fits": (3, 2), "xy_force": (2, 2),
+                "z_update": (4, 1), "z_update_fused": (4, 3)}
+
+
+def achievable_bandwidth(torch, n: int = 1 << 27, reps: int = 5) -> dict:
+    """GB/s of the library's streaming kernel for each pass's read/write mix
+    (fields of n floats, 512 MiB each), timed with events on the current
+    stream (the one the kernel is launched on)."""
+    from paper_2404_02813_amd import rsf
+
+    inp = torch.ones(4 * n, device="cuda")
+    out = torch.empty(3 * n, device="cuda")
+    res = {}
+    for name, (r, w) in STREAM_MIXES.items():
+        a, b = inp[:r * n], out[:w * n]
+        rsf.rsf_stream_probe(a, r, b, w)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rsf.rsf_stream_probe(a, r, b, w)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = round((r + w) * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del inp, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def roofline(prof: dict, pb: dict, voxels: int, workload: str) -> dict:
     """Dominant pass (largest total time) priced at its algorithmic bytes per
     voxel times the voxels one launch covers, over its mean launch time."""
@@ -309,6 +342,8 @@ def run_tiles(args, w) -> int:
     ctx = rsf.Context(0)
     if args.no_fusion:
         ctx.set_fusion(False)
+    if args.no_graphs:
+        ctx.set_graphs(False)
 
     def fresh():
         return [p.clone() for p in phi0]
@@ -372,14 +407,18 @@ def run_tiles(args, w) -> int:
                    "edges": list(w.edges), "halo": w.halo, "sigma": w.sigma, "iters": w.iters,
                    "image": "f32", "storage": "f32", "voxels_with_halo": voxels,
                    "voxels_interior": interior, "parallelism": "single_gpu"},
-        "roofline": roofline(prof, pb, voxels, w.name),
+        "roofline": roofline(prof, pass_bytes(fused=prof["z_heaviside"][0] < prof["z_update"][0]),
+                             voxels, w.name),
         "interior_value": round(interior * w.iters * K / elapsed / 1e9, 3),
         "batch_default_split_value": rate(t_default),
         "per_tile_loop_value": rate(t_loop),
         "gain_over_loop": round(t_loop / (elapsed / K), 3),
         "autotune_s": round(t_tune, 2),
-        "autotune_targets": list(chosen),
+        "autotune_targets": list(chosen[:3]),
+        "autotune_fused": bool(chosen[3]),
         "batch_equals_loop_bitwise": bool(same),
+        "fused_stage1": prof["z_heaviside"][0] < prof["z_update"][0],
+        "graphs": not args.no_graphs,
         "passes_ms_per_launch": {k: round(v[1] / v[0], 4) for k, v in prof.items() if v[0]},
         "copy_gbs": round(copy_gbs, 1),
         "finite": ok,
@@ -413,6 +452,8 @@ def run_volume(args, w, block: int) -> int:
     ctx = rsf.Context(0)
     if args.no_fusion:
         ctx.set_fusion(False)
+    if args.no_graphs:
+        ctx.set_graphs(False)
     R = int(np.ceil(3 * w.sigma - 1e-9))
     for _ in range(W):
         ph = phi0.clone()
@@ -504,6 +545,8 @@ def run_init(args, w) -> int:
     ctx = rsf.Context(0)
     if args.no_fusion:
         ctx.set_fusion(False)
+    if args.no_graphs:
+        ctx.set_graphs(False)
     n_seeds = 0
     for _ in range(W):
         n_seeds = ctx.init_phi(vol, phi, INIT_SIGMA_B, INIT_THRESHOLD, 0.0, INIT_ROUNDS)
@@ -624,7 +667,7 @@ def run_serve(args, w) -> int:
         per-request results and the outputs of the requests in `keep`."""
         bv, order = parse_sched(sched)
         srv = rsf.Server(budget_bytes=budget, chunk_iters=args.chunk_iters, batch_voxels=bv,
-                         order=order)
+                         order=order, separate_passes=args.no_fusion)
         tickets = [None] * len(stream)
         results = [None] * len(stream)
         kept = {}
@@ -693,6 +736,8 @@ def run_serve(args, w) -> int:
     ctx = rsf.Context(0)
     if args.no_fusion:
         ctx.set_fusion(False)
+    if args.no_graphs:
+        ctx.set_graphs(False)
     torch.cuda.synchronize()
     t0 = time.monotonic()
     for r in reqs[:sample]:
@@ -770,6 +815,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fusion", action="store_true",
                     help="run the stage-1 z pass separately every iteration")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every iteration directly (no captured HIP graphs)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--iters", type=int, default=0,
                     help="override the workload's iteration count (profiling runs)")
@@ -836,6 +883,8 @@ def main() -> int:
     ctx = rsf.Context(0)
     if args.no_fusion:
         ctx.set_fusion(False)
+    if args.no_graphs:
+        ctx.set_graphs(False)
     scratch = torch.empty_like(phi0)
 
     for _ in range(W):
@@ -897,6 +946,7 @@ def main() -> int:
         "hbm_frac_path": round(value * iter_bytes / HBM_PEAK_GBS, 4),
         "path_bytes_per_voxel_iter": iter_bytes,
         "fused_stage1": fused,
+        "graphs": not args.no_graphs,
         "passes_ms_per_launch": {k: round(v[1] / v[0], 4) for k, v in prof.items() if v[0]},
         "copy_gbs": round(copy_gbs, 1),
         "iters_run": iters_run,
@@ -908,6 +958,21 @@ def main() -> int:
     ctx.close()
     del phis, vol, phi0, scratch
     torch.cuda.empty_cache()
+    # the achievable bandwidth of each pass's read/write mix (own streaming
+    # kernel) beside the 8 TB/s peak
+    ach = achievable_bandwidth(torch)
+    out["achievable_gbs"] = ach
+    mix_of = lambda k: "z_update_fused" if (k == "z_update" and fused) else k  # noqa: E731
+    passes = {}
+    for k, (launches, ms) in prof.items():
+        if k in pb and launches:
+            gbs = pb[k] * vox / (ms / launches * 1e-3) / 1e9
+            passes[k] = {"gbs": round(gbs, 1), "of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                         "of_achievable": round(gbs / ach[mix_of(k)], 4)}
+    out["passes_algorithmic_bandwidth"] = passes
+    dom = out["roofline"]["kernel"]
+    out["roofline"]["achievable"] = ach[mix_of(dom)]
+    out["roofline"]["frac_of_achievable"] = passes[dom]["of_achievable"]
     if not args.no_cpu_baseline:
         img = I_host.astype("float64") / 65535.0 if image_t == "u16" else I_host
         out["cpu_baseline"] = cpu_baseline(w, img, phi0_host, args.cpu_seconds,

@@ -206,12 +206,18 @@ rsf_status rsf_evolve_batch(rsf_context *ctx, const rsf_tile *tiles, int n_tiles
 /* Autotuner.  Times `trial_iters` iterations of these tiles (on copies of
  * their phi; the caller's buffers are not modified) for candidate workgroup
  * splits of each pass (row chunks of the xy passes, z chunks of the z and
- * update passes), one pass at a time, and keeps the fastest split per tile
- * shape and radius in the context.  Later evolutions of the same shapes use
- * it.  phi after an evolution is bitwise independent of the split; the FP64
- * sums of |dphi| are grouped per update workgroup, so they may differ in the
- * last bits.  Synchronises `stream`; allocates a scratch copy of phi for the
- * duration of the call; invalidates the statistics of the last evolution. */
+ * update passes), one pass at a time with the passes separate, and keeps the
+ * fastest split per tile shape and radius in the context.  Then, where the
+ * force and radius allow the fused update (rsf_set_fusion), it times that
+ * schedule against the separate passes and keeps the faster for this set of
+ * tile shapes.  Later evolutions of the same shapes use both.
+ *   chosen : NULL or int64_t[4]: the xy, z and update workgroup targets, and
+ *            1 if the fused update was chosen (else 0).
+ * phi after an evolution is bitwise independent of the split and schedule;
+ * the FP64 sums of |dphi| are grouped per update workgroup, so they may
+ * differ in the last bits.  Synchronises `stream`; allocates a scratch copy
+ * of phi for the duration of the call; invalidates the statistics of the
+ * last evolution. */
 rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
                         const rsf_params *params, int trial_iters, int64_t *chosen,
                         void *stream);
@@ -220,11 +226,11 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
  * pass workgroups) from which untuned splits are derived, each tile taking
  * its share of the batch's voxels; 0 keeps the built-in value (16384, 2048,
  * 1024).  rsf_autotune starts its search from these and reports the targets
- * it chose in chosen[0..2] (may be NULL).  Results do not depend on them. */
+ * it chose in chosen[0..2].  Results do not depend on them. */
 rsf_status rsf_set_split_targets(rsf_context *ctx, int64_t xy_waves, int64_t z_blocks,
                                  int64_t u_blocks);
 
-/* Forget all autotuned splits of the context. */
+/* Forget all autotuned splits and schedules of the context. */
 void rsf_autotune_reset(rsf_context *ctx);
 
 /* Statistics of tile `tile` of the last evolution (tile 0 for rsf_evolve). */
@@ -342,13 +348,35 @@ typedef struct {
     double ms[RSF_PASS_COUNT];      /* summed event time per pass */
 } rsf_profile;
 
-/* When every tile's update pass marches its whole z extent (and, for the
- * RSF force, a single volume with ceil(3 sigma) <= 10),
- * the update also forms the next iteration's stage-1 z Gaussian (Sec. 3 fits)
- * from the phi it has just written, so that pass is not launched again
- * (on != 0, the default).  Results are bitwise the same either way; off runs
- * the passes separately.  Affects later rsf_evolve* calls on this context. */
+/* The update also forms the next iteration's stage-1 z Gaussian (Sec. 3
+ * fits) from the phi it has just written, so that pass is not launched again
+ * (on != 0, the default).  Applies to single volumes and batches alike when
+ * the RSF force's radius ceil(3 sigma) <= 10 (any radius for the Sec. 4.2
+ * force); every tile's update then marches its whole z extent.  Results are
+ * bitwise the same either way; off runs the passes separately.  Affects later
+ * rsf_evolve* calls on this context. */
 rsf_status rsf_set_fusion(rsf_context *ctx, int on);
+
+/* Iterations replayed from a captured HIP graph (on != 0, the default): with
+ * at least 8 iterations and per-pass timing off, rsf_evolve, rsf_evolve_ex
+ * and rsf_evolve_batch capture one group of 16 iterations' launches (kernel
+ * launches only) and replay it on the caller's stream; the rest of the count
+ * launches directly.  A later call whose launches are the same replays the
+ * kept graph without capturing again.  Results are bitwise the same either
+ * way; off launches every iteration directly. */
+rsf_status rsf_set_graphs(rsf_context *ctx, int on);
+
+/* Measurement aid: one launch of a streaming kernel with a pass's read/write
+ * mix, for the achievable HBM bandwidth the passes are compared against.
+ *   in  : device, n_read (1..4) float fields of n floats each, contiguous
+ *         (field k at in + k n); 16-byte aligned
+ *   out : device, n_write (1..3) float fields of n floats, likewise;
+ *         out_j[i] = j + sum_k in_k[i]
+ *   n   : floats per field, a positive multiple of 4
+ * Enqueued on `stream` on the current device; RSF_ERR_INVALID_ARG for bad
+ * arguments, RSF_ERR_DEVICE if the launch fails. */
+rsf_status rsf_stream_probe(const float *in, int n_read, float *out, int n_write, int64_t n,
+                            void *stream);
 
 /* Start (on != 0) or stop recording events on later launches. */
 rsf_status rsf_profile_enable(rsf_context *ctx, int on);
@@ -397,6 +425,10 @@ typedef struct {
                               this per chunk; 0 = every resident tile runs    */
     int order;             /* rsf_order                                        */
     int64_t split_targets[3]; /* as rsf_set_split_targets; 0 = built-in       */
+    int separate_passes;   /* 0: a group whose force and radius allow it runs
+                              the update fused with the next stage-1 z pass
+                              (one stage-1 pass per chunk); 1: every pass
+                              separately.  Bitwise the same results.         */
 } rsf_server_config;
 
 typedef struct {

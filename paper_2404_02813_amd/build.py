@@ -17,13 +17,18 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librsf.so")
-SOURCES = ["rsf_kernels.hip", "rsf_split.hip", "rsf_api.hip", "rsf_server.hip"] + sorted(
+SOURCES = ["rsf_kernels.hip", "rsf_split.hip", "rsf_api.hip", "rsf_server.hip",
+           "rsf_stream.hip"] + sorted(
     f for f in os.listdir(CSRC) if f.startswith("rsf_inst_") and f.endswith(".hip"))
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# The marches unroll by their register-ring length (up to 2R + 2 steps of a
+# large body); the raised limit keeps every ring slot a compile-time register
+# (a partly unrolled march indexes its ring at run time, in scratch memory).
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-pragma-unroll-threshold=200000",
          "-Wall", "-Wno-unused-result",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

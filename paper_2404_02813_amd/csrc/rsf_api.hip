@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -58,6 +59,18 @@ struct rsf_context {
     // per-pass event timing
     bool prof = false;
     bool fuse = true;   // fused update + next stage-1 pass where a batch allows it
+    // iteration groups replayed from a captured HIP graph (see run_iterations)
+    bool graphs = true;
+    hipStream_t cap_stream = nullptr;      // capture only: nothing runs on it
+    hipGraphExec_t graph_exec = nullptr;   // the last group's executable graph
+    std::vector<char> graph_key;           // what it was captured from
+    hipEvent_t graph_ev = nullptr;         // recorded after its last launch
+    // replaced graphs, destroyed once their last replay has completed
+    struct Retired {
+        hipGraphExec_t exec;
+        hipEvent_t ev;
+    };
+    std::vector<Retired> retired;
     struct Rec {
         int kind;
         hipEvent_t a, b;
@@ -67,6 +80,10 @@ struct rsf_context {
     std::vector<Rec> recs;
     // autotuned splits by tile shape and radius
     std::map<std::vector<int64_t>, Split> tuned;
+    // autotuned schedule (fused update or separate passes) by batch: the
+    // sorted tile shapes, radius, force, image and storage types
+    std::map<std::vector<int64_t>, bool> tuned_fuse;
+    int force_schedule = -1;   // autotune trials: -1 none, 0 separate, 1 fused
     // workgroup targets of a batch when no tuned split applies
     rsf::Targets targets = rsf::kDefaultTargets;
 };
@@ -292,8 +309,60 @@ std::vector<double> shares_of(const rsf_tile *tiles, int n)
     return sh;
 }
 
-// Tuned split of the shape if there is one, else the default for its share.
-std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R)
+// Whether an evolution of this batch carries the next stage-1 z pass in its
+// update: the context allows it, no probe, and the RSF force's stage-2 ring
+// leaves room for the stage-1 ring (radius <= fuse_max_r; the Sec. 4.2 force
+// has no stage-2 ring).  Every tile is then marched whole in z (one update
+// chunk per column tile).
+std::vector<int64_t> schedule_key(const rsf_tile *tiles, int n, const rsf_params &p, int image)
+{
+    std::vector<std::array<int64_t, 3>> shapes;
+    for (int t = 0; t < n; ++t) shapes.push_back({tiles[t].nx, tiles[t].ny, tiles[t].nz});
+    std::sort(shapes.begin(), shapes.end());
+    std::vector<int64_t> key{radius_of(p.sigma), p.force, image, p.storage};
+    for (const auto &a : shapes) key.insert(key.end(), a.begin(), a.end());
+    return key;
+}
+
+// Whether the force and radius allow the fused update at all (the context's
+// switch on, no probe).
+bool fusable(const rsf_context *ctx, const rsf_params &p, bool probe)
+{
+    return ctx && ctx->fuse && !probe &&
+           (p.force == RSF_FORCE_PAPER || radius_of(p.sigma) <= rsf::fuse_max_r(p.storage));
+}
+
+std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R,
+                              bool whole_z = false);
+
+// The schedule of a batch: an autotune trial's forced choice, else the
+// autotuned choice for these tile shapes, else fused when the update keeps
+// enough parallelism marching every tile whole in z: the tiles' own splits
+// already do, or their column tiles alone fill 3/4 of the resident update
+// workgroups (small volumes keep the separate passes and their z chunks).
+bool decide_fuse(const rsf_context *ctx, const rsf_params &p, bool probe, const rsf_tile *tiles,
+                 int n, int image)
+{
+    if (!fusable(ctx, p, probe)) return false;
+    if (ctx->force_schedule >= 0) return ctx->force_schedule == 1;
+    const auto it = ctx->tuned_fuse.find(schedule_key(tiles, n, p, image));
+    if (it != ctx->tuned_fuse.end()) return it->second;
+    const int R = radius_of(p.sigma);
+    bool whole = true;
+    int64_t cols = 0;
+    const std::vector<Split> sps = splits_for(const_cast<rsf_context *>(ctx), tiles, n, R, false);
+    for (int t = 0; t < n; ++t) {
+        whole = whole && sps[t].u == 1;
+        cols += (int64_t)((tiles[t].nx + rsf::kUx - 1) / rsf::kUx) *
+                ((tiles[t].ny + rsf::kUy - 1) / rsf::kUy);
+    }
+    return whole || 4 * cols >= 3 * rsf::kResidentU;
+}
+
+// Tuned split of the shape if there is one, else the default for its share;
+// `whole_z`: one update chunk per tile (the fused update).
+std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R,
+                              bool whole_z)
 {
     const std::vector<double> sh = shares_of(tiles, n);
     std::vector<Split> splits;
@@ -309,6 +378,7 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
             auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
             if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) s = it->second;
         }
+        if (whole_z) s.u = 1;
         splits.push_back(s);
     }
     return splits;
@@ -329,7 +399,8 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.k2 = rsf::host::needs_k2(p);
     P.R2 = P.k2 ? radius_of(p.sigma2) : 0;
     if (P.k2) P.taps2 = make_taps(p.sigma2, P.R2);
-    P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R), P.k2);
+    const bool fuse = decide_fuse(ctx, p, probe != nullptr, tiles, n, image);
+    P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R, fuse), P.k2);
     P.base = base;
     rsf_status st = ensure_stage(ctx, P.L.table_bytes);
     if (st != RSF_OK) return st;
@@ -372,9 +443,7 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     P.blocks_xy = rsf::host::balance_xcds(P.xy, rsf::host::PASS_XY, gs, sps, P.R);
     P.blocks_z = rsf::host::balance_xcds(P.z, rsf::host::PASS_Z, gs, sps, P.R);
     P.blocks_u = rsf::host::balance_xcds(P.u, rsf::host::PASS_U, gs, sps, P.R);
-    // RSF force: single volumes only (on batches of uneven tiles the fused
-    // update measured about 2 % slower than the separate passes).
-    P.fuse = !probe && (P.c.force == RSF_FORCE_PAPER || (P.R <= rsf::kFuseMaxR && n == 1));
+    P.fuse = fuse;
     for (const Split &sp : sps) P.fuse = P.fuse && sp.u == 1;
     return RSF_OK;
 }
@@ -461,6 +530,108 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s,
     return RSF_OK;
 }
 
+// Iterations of a planned batch.  Every iteration launches the same kernels
+// with the same arguments (each tile's current iterate and stop flag are read
+// on the device), so a group of kGraphGroup iterations is captured once into
+// a HIP graph and replayed on `s`; the rest of the count launches directly.
+// The executable graph is kept and replayed by later calls whose launches are
+// the same (same workspace, tile table, taps and coefficients); a different
+// one replaces it once its last replay has completed.  The captured region
+// holds kernel launches only (no memset, no copy, no event).  Per-pass event
+// timing, or a caller that passes allow_graph false, launches every
+// iteration directly.
+constexpr int kGraphMinIters = 8;
+constexpr int kGraphGroup = 16;
+
+void append_key(std::vector<char> &k, const void *p, size_t n)
+{
+    const char *c = static_cast<const char *>(p);
+    k.insert(k.end(), c, c + n);
+}
+
+// Retire the current graph (with the event after its last replay) and
+// destroy the retired graphs whose replays have completed; never waits.
+rsf_status retire_graph(rsf_context *ctx)
+{
+    if (ctx->graph_exec) {
+        ctx->retired.push_back({ctx->graph_exec, ctx->graph_ev});
+        ctx->graph_exec = nullptr;
+        ctx->graph_ev = nullptr;
+        ctx->graph_key.clear();
+    }
+    std::vector<rsf_context::Retired> keep;
+    for (const auto &r : ctx->retired) {
+        if (!r.ev || hipEventQuery(r.ev) == hipSuccess) {
+            HIP_TRY(hipGraphExecDestroy(r.exec), "hipGraphExecDestroy");
+            if (r.ev) HIP_TRY(hipEventDestroy(r.ev), "hipEventDestroy(graph)");
+        } else {
+            keep.push_back(r);
+        }
+    }
+    ctx->retired.swap(keep);
+    return RSF_OK;
+}
+
+rsf_status run_iterations(rsf_context *ctx, const Plan &P, int iters, hipStream_t s, bool fused,
+                          bool allow_graph)
+{
+    int done = 0;
+    if (allow_graph && ctx->graphs && !ctx->prof && iters >= kGraphMinIters) {
+        const int G = std::min(iters, kGraphGroup);
+        std::vector<char> key;
+        append_key(key, &G, sizeof(G));
+        append_key(key, &fused, sizeof(fused));
+        append_key(key, &P.R, sizeof(P.R));
+        append_key(key, &P.image, sizeof(P.image));
+        append_key(key, &P.storage, sizeof(P.storage));
+        append_key(key, &P.taps, sizeof(P.taps));
+        append_key(key, &P.c, sizeof(P.c));
+        for (const Batch *b : {&P.xy, &P.z, &P.u, &P.tile}) append_key(key, b, sizeof(Batch));
+        for (const int64_t *v : {&P.blocks_xy, &P.blocks_z, &P.blocks_u})
+            append_key(key, v, sizeof(*v));
+        append_key(key, &P.k2, sizeof(P.k2));
+        if (!ctx->graph_exec || key != ctx->graph_key) {
+            rsf_status st = retire_graph(ctx);
+            if (st != RSF_OK) return st;
+            if (!ctx->cap_stream)
+                HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking),
+                        "hipStreamCreate(capture)");
+            // A capture or instantiation the runtime refuses leaves the
+            // iterations to the direct launches below; a launch error inside
+            // the capture is the call's error.
+            hipGraphExec_t exec = nullptr;
+            if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) ==
+                hipSuccess) {
+                for (int k = 0; k < G && st == RSF_OK; ++k)
+                    st = iteration(ctx, P, false, ctx->cap_stream, fused);
+                hipGraph_t graph = nullptr;
+                const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+                if (st == RSF_OK && ec == hipSuccess &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                    exec = nullptr;
+                if (graph) (void)hipGraphDestroy(graph);
+                if (st != RSF_OK) return st;
+            }
+            (void)hipGetLastError();   // a refused capture leaves no error behind
+            ctx->graph_exec = exec;
+            if (exec) ctx->graph_key = std::move(key);
+        }
+        if (ctx->graph_exec) {
+            for (; done + G <= iters; done += G)
+                HIP_TRY(hipGraphLaunch(ctx->graph_exec, s), "hipGraphLaunch");
+            if (!ctx->graph_ev)
+                HIP_TRY(hipEventCreateWithFlags(&ctx->graph_ev, hipEventDisableTiming),
+                        "hipEventCreate(graph)");
+            HIP_TRY(hipEventRecord(ctx->graph_ev, s), "hipEventRecord(graph)");
+        }
+    }
+    for (; done < iters; ++done) {
+        const rsf_status st = iteration(ctx, P, false, s, fused);
+        if (st != RSF_OK) return st;
+    }
+    return RSF_OK;
+}
+
 rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
                        const rsf_params &p, int iters, double tol, void *workspace,
                        size_t ws_bytes, void *stream)
@@ -505,10 +676,8 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
         st = stage1(ctx, P, false, s);
         if (st != RSF_OK) return st;
     }
-    for (int it = 0; it < iters; ++it) {
-        st = iteration(ctx, P, false, s, fused);
-        if (st != RSF_OK) return st;
-    }
+    st = run_iterations(ctx, P, iters, s, fused, true);
+    if (st != RSF_OK) return st;
     // tiles that ended on an odd iteration have it in the workspace buffer
     if (iters > 0) HIP_TRY(rsf::launch_finish(P.z, P.blocks_z, s), "finish");
     if (!workspace) {
@@ -622,11 +791,20 @@ void rsf_destroy(rsf_context *ctx)
     if (!ctx) return;
     try {
         (void)hipSetDevice(ctx->device);
-        if (ctx->ws || !ctx->ev_pool.empty() || ctx->stage) (void)hipDeviceSynchronize();
+        if (ctx->ws || !ctx->ev_pool.empty() || ctx->stage || ctx->graph_exec ||
+            !ctx->retired.empty())
+            (void)hipDeviceSynchronize();
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->stage) (void)hipHostFree(ctx->stage);
         if (ctx->stage_ev) (void)hipEventDestroy(ctx->stage_ev);
         if (ctx->ws_ev) (void)hipEventDestroy(ctx->ws_ev);
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph_ev) (void)hipEventDestroy(ctx->graph_ev);
+        for (const auto &r : ctx->retired) {
+            (void)hipGraphExecDestroy(r.exec);
+            if (r.ev) (void)hipEventDestroy(r.ev);
+        }
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
         for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     } catch (...) {
     }
@@ -637,6 +815,13 @@ rsf_status rsf_set_fusion(rsf_context *ctx, int on)
 {
     if (!ctx) return RSF_ERR_INVALID_ARG;
     ctx->fuse = on != 0;
+    return RSF_OK;
+}
+
+rsf_status rsf_set_graphs(rsf_context *ctx, int on)
+{
+    if (!ctx) return RSF_ERR_INVALID_ARG;
+    ctx->graphs = on != 0;
     return RSF_OK;
 }
 
@@ -856,6 +1041,37 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                     rsf::make_split(g, part(tg[0]), part(tg[1]), part(tg[2]));
             }
         };
+        // time what rsf_evolve_batch would run under the current splits and
+        // schedule: one warm-up iteration, then the timed ones
+        auto trial = [&](float &ms) -> rsf_status {
+            const int runs = trial_iters + 1;
+            const size_t need = plan_layout(tt.data(), n_tiles, runs, params->storage,
+                                            splits_for(ctx, tt.data(), n_tiles, R),
+                                            rsf::host::needs_k2(*params))
+                                    .total;
+            rsf_status r = ensure_ws(ctx, need);
+            if (r == RSF_OK) r = ws_enter(ctx, s);
+            if (r != RSF_OK) return r;
+            ctx->has_last = false;   // the trials overwrite the workspace
+            Plan P;
+            r = make_plan(ctx, P, tt.data(), n_tiles, volume_dtype, *params, 0.0, runs,
+                          static_cast<char *>(ctx->ws), s);
+            if (r == RSF_OK) r = prologue(ctx, P, s);
+            const bool fused = P.fuse && ctx->fuse;
+            if (r == RSF_OK && fused) r = stage1(ctx, P, false, s);
+            if (r == RSF_OK) r = iteration(ctx, P, false, s, fused);   // warm-up
+            if (r == RSF_OK) r = time_iterations(ctx, P, trial_iters, s, &ms, fused);
+            if (r == RSF_OK) r = ws_leave(ctx, s);
+            return r;
+        };
+        // The splits are searched with the passes separate (all three
+        // targets then matter); then the schedule: the update fused with
+        // the next stage-1 pass (each tile one update chunk) against the
+        // separate passes, where the force and radius allow fusing.
+        const std::vector<int64_t> skey = schedule_key(tiles, n_tiles, *params, volume_dtype);
+        ctx->tuned_fuse.erase(skey);
+        const bool can_fuse = fusable(ctx, *params, false);
+        ctx->force_schedule = 0;
         float best_ms = -1.f;
         for (int axis = 0; axis < 3; ++axis) {
             const int64_t *cands = axis == 0 ? cand_xy : (axis == 1 ? cand_z : cand_u);
@@ -865,27 +1081,8 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 int64_t tg[3] = {best[0], best[1], best[2]};
                 tg[axis] = cands[c];
                 apply(tg);
-                // one warm-up iteration, then the timed ones
-                const int runs = trial_iters + 1;
-                const size_t need =
-                    plan_layout(tt.data(), n_tiles, runs, params->storage,
-                                splits_for(ctx, tt.data(), n_tiles, R),
-                                rsf::host::needs_k2(*params)).total;
-                st = ensure_ws(ctx, need);
-                if (st == RSF_OK) st = ws_enter(ctx, s);
-                if (st != RSF_OK) break;
-                ctx->has_last = false;   // the trials overwrite the workspace
-                Plan P;
-                st = make_plan(ctx, P, tt.data(), n_tiles, volume_dtype, *params, 0.0, runs,
-                               static_cast<char *>(ctx->ws), s);
-                if (st == RSF_OK) st = prologue(ctx, P, s);
-                // time what rsf_evolve_batch would run under this split
-                const bool fused = P.fuse && ctx->fuse;
-                if (st == RSF_OK && fused) st = stage1(ctx, P, false, s);
                 float ms = 0.f;
-                if (st == RSF_OK) st = iteration(ctx, P, false, s, fused);   // warm-up
-                if (st == RSF_OK) st = time_iterations(ctx, P, trial_iters, s, &ms, fused);
-                if (st == RSF_OK) st = ws_leave(ctx, s);
+                st = trial(ms);
                 if (st != RSF_OK) break;
                 if (best_ms < 0.f || ms < best_ms) {
                     best_ms = ms;
@@ -895,12 +1092,27 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
             if (st != RSF_OK) break;
             best[axis] = keep;
         }
+        int fused_choice = 0;
         if (st == RSF_OK) {
             apply(best);
+            if (can_fuse) {
+                float sep = 0.f, fus = 0.f;
+                st = trial(sep);
+                ctx->force_schedule = 1;
+                if (st == RSF_OK) st = trial(fus);
+                if (st == RSF_OK) {
+                    fused_choice = fus < sep ? 1 : 0;
+                    ctx->tuned_fuse[skey] = fused_choice == 1;
+                }
+            }
+        }
+        ctx->force_schedule = -1;
+        if (st == RSF_OK) {
             if (chosen) {
                 chosen[0] = best[0];
                 chosen[1] = best[1];
                 chosen[2] = best[2];
+                chosen[3] = fused_choice;
             }
         } else {
             for (int t = 0; t < n_tiles; ++t)
@@ -910,6 +1122,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
         (void)hipFree(trial_phi);
         return st;
     } catch (...) {
+        if (ctx) ctx->force_schedule = -1;
         if (trial_phi) (void)hipFree(trial_phi);
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
@@ -917,7 +1130,9 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
 
 void rsf_autotune_reset(rsf_context *ctx)
 {
-    if (ctx) ctx->tuned.clear();
+    if (!ctx) return;
+    ctx->tuned.clear();
+    ctx->tuned_fuse.clear();
 }
 
 rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,

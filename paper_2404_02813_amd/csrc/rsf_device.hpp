@@ -58,16 +58,56 @@ __device__ __forceinline__ gptr<T> glb(T *p)
     return (gptr<T>)p;
 }
 
-// Element i of a slice: a wave-uniform 64-bit slice base (scalar registers)
-// plus a 32-bit unsigned in-slice byte offset.  The compiler then emits the
-// scalar-base form of the global loads and stores, with one 32-bit offset
-// register per lane and no 64-bit address arithmetic per access.  Planes
-// are limited so that every such offset fits (kMaxPlane).
-template <class T>
-__device__ __forceinline__ gptr<T> at32(gptr<T> base, uint32_t i)
+// Buffer-resource access.  The wave-uniform 64-bit base of an array (a
+// slice, or any array under 4 GiB) lives in a scalar resource descriptor and
+// each lane supplies only a 32-bit byte offset, so no 64-bit address
+// arithmetic is done per lane and no 64-bit offsets occupy vector registers.
+// Planes are limited so that every in-slice offset fits (kMaxPlane).  The
+// descriptor has stride 0 (raw), no range limit and the 32-bit data format
+// gfx9 raw buffer instructions expect.  Raw elements are converted only where
+// they are used: converting right after the load would make the load's
+// consumer wait for it there, and a load issued a step ahead would no longer
+// overlap anything.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcFlags = 0x00020000;
+__device__ __forceinline__ rsrc_t rsrc(const void *base)
 {
-    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
-    return (gptr<T>)((gptr<B>)base + i * (uint32_t)sizeof(T));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, kRsrcFlags);
+}
+template <class T>
+__device__ __forceinline__ rsrc_t rsrc(gptr<T> base)
+{
+    return rsrc((const void *)base);
+}
+
+// Element i of the array behind r (T of 2, 4 or 8 bytes); `soff` is a
+// wave-uniform byte offset added to the lane's.
+template <class T>
+__device__ __forceinline__ T bld(rsrc_t r, uint32_t i, uint32_t soff = 0)
+{
+    const uint32_t off = i * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 2) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    } else {
+        static_assert(sizeof(T) == 8, "2, 4 or 8-byte elements");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+    }
+}
+template <class T>
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t i, T v, uint32_t soff = 0)
+{
+    const uint32_t off = i * (uint32_t)sizeof(T);
+    if constexpr (sizeof(T) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, soff, 0);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, soff, 0);
+    } else {
+        static_assert(sizeof(T) == 8, "2, 4 or 8-byte elements");
+        using U2 = unsigned int __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, soff, 0);
+    }
 }
 
 // A wave-uniform element of read-only device data (tables written before the
@@ -101,38 +141,14 @@ struct alignas(2 * sizeof(T)) Pair {
 template <class T>
 using Vec2 = T __attribute__((ext_vector_type(2)));
 
+// Pair element i of the array behind r, stored through the descriptor.
 template <class T>
-__device__ __forceinline__ float2 ld_pair(gptr<const Pair<T>> p, int64_t i)
-{
-    const Vec2<T> v = ((gptr<const Vec2<T>>)p)[i];
-    return make_float2(to_f(v.x), to_f(v.y));
-}
-
-// The raw element pair, converted only where it is used: converting right
-// after the load would make the load's consumer wait for it there, and a
-// load issued a step ahead would no longer overlap anything.
-template <class T>
-__device__ __forceinline__ Vec2<T> ld_pair_raw(gptr<const Pair<T>> p, int64_t i)
-{
-    return ((gptr<const Vec2<T>>)p)[i];
-}
-
-template <class T>
-__device__ __forceinline__ void st_pair(gptr<Pair<T>> p, int64_t i, float a, float b)
+__device__ __forceinline__ void bst_pair(rsrc_t r, uint32_t i, float a, float b, uint32_t soff = 0)
 {
     Vec2<T> v;
     v.x = from_f<T>(a);
     v.y = from_f<T>(b);
-    ((gptr<Vec2<T>>)p)[i] = v;
-}
-
-template <class T>
-__device__ __forceinline__ void st_pair32(gptr<Pair<T>> p, uint32_t i, float a, float b)
-{
-    Vec2<T> v;
-    v.x = from_f<T>(a);
-    v.y = from_f<T>(b);
-    *at32((gptr<Vec2<T>>)p, i) = v;
+    bst<Vec2<T>>(r, i, v, soff);
 }
 
 // Value of lane `src` (wave-uniform) of v.  Lanes past a volume edge store

@@ -75,20 +75,26 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
         Vec2<IN> p[2];
         IN s[2];
     };
-    const gptr<const Pair<IN>> in2 = glb(static_cast<const Pair<IN> *>(in_));
-    const gptr<const IN> in1 = glb(static_cast<const IN *>(in_));
+    // the slice through a buffer descriptor: a row is a uniform byte offset,
+    // each lane's column a loop-invariant 32-bit one
+    const rsrc_t rin = rsrc(static_cast<const char *>(in_) +
+                            zb * (int64_t)(NF == 2 ? sizeof(Pair<IN>) : sizeof(IN)));
+    uint32_t gxo[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        // lanes past the staged width load the last staged column: same
+        // cache line, no extra traffic
+        gxo[h] = (uint32_t)min(max(x0 - R + min(lane + 64 * h, RW - 1), 0), g.nx - 1);
+    }
     auto fetch = [&](int y) {
         Raw r;
-        // uniform row bases, 32-bit lane offsets
         const int yy = min(max(y, 0), g.ny - 1);
-        const int64_t rowo = zb + (int64_t)yy * g.nx;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            // lanes past the staged width load the last staged column: same
-            // cache line, no extra traffic
-            const int gx = min(max(x0 - R + min(lane + 64 * h, RW - 1), 0), g.nx - 1);
-            if (NF == 2) r.p[h] = ld_pair_raw<IN>(in2 + rowo, gx);
-            else r.s[h] = (in1 + rowo)[gx];
+            if (NF == 2)
+                r.p[h] = bld<Vec2<IN>>(rin, gxo[h], (uint32_t)(yy * g.nx) * (uint32_t)sizeof(Pair<IN>));
+            else
+                r.s[h] = bld<IN>(rin, gxo[h], (uint32_t)(yy * g.nx) * (uint32_t)sizeof(IN));
         }
         return r;
     };
@@ -143,12 +149,12 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
     constexpr int M = W + 1;
     const int xc = min(x, g.nx - 1);
     const int last = min(63, g.nx - 1 - x0);   // last in-slice lane of the strip
-    const gptr<const ST> ki_slice = glb(static_cast<const ST *>(d.KI)) + zb;
-    const gptr<const IMG> im_slice = glb(static_cast<const IMG *>(d.I)) + zb;
-    const gptr<const ST> k2i_slice = glb(static_cast<const ST *>(d.K2I)) + zb;
-    const gptr<const ST> k2q_slice = glb(static_cast<const ST *>(d.K2I2)) + zb;
-    const gptr<const float> cyp = glb(d.cy);
+    const rsrc_t rki = rsrc(static_cast<const ST *>(d.KI) + zb);
+    const rsrc_t rim = rsrc(static_cast<const IMG *>(d.I) + zb);
+    const rsrc_t rk2i = rsrc(static_cast<const ST *>(d.K2I) + zb);
+    const rsrc_t rk2q = rsrc(static_cast<const ST *>(d.K2I2) + zb);
     const float cxz = FITS ? glb(d.cx)[xc] * glb(d.cz)[z] : 0.f;
+    const float *const cyp = d.cy;   // read once: the loop's stores could alias the table
     // the loads of step y: row y + R + 1 and the fits' pointwise inputs of row y
     struct Stage {
         Raw row;
@@ -161,13 +167,13 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
         st.row = fetch(y + R + 1);
         if (FITS) {
             const int yy = min(y, g.ny - 1);
-            const int o = yy * g.nx + xc;
-            st.ki = ki_slice[o];
-            st.cy = cyp[yy];
-            if (MODE == XY_PAPER) st.im = im_slice[o];
+            const uint32_t row = (uint32_t)(yy * g.nx);
+            st.ki = bld<ST>(rki, (uint32_t)xc, row * (uint32_t)sizeof(ST));
+            st.cy = uniform_ld(cyp, yy);   // one value for the wave: a scalar load
+            if (MODE == XY_PAPER) st.im = bld<IMG>(rim, (uint32_t)xc, row * (uint32_t)sizeof(IMG));
             if (MODE == XY_PAPER2) {
-                st.k2i = k2i_slice[o];
-                st.k2q = k2q_slice[o];
+                st.k2i = bld<ST>(rk2i, (uint32_t)xc, row * (uint32_t)sizeof(ST));
+                st.k2q = bld<ST>(rk2q, (uint32_t)xc, row * (uint32_t)sizeof(ST));
             }
         }
         return st;
@@ -197,9 +203,10 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
     }
     const gptr<float> probe_f1 = glb(d.probe_f1), probe_f2 = glb(d.probe_f2),
                       probe_fd = glb(d.probe_Fd);
-    const gptr<ST> o1_s = glb(static_cast<ST *>(out_)) + zb;
-    const gptr<Pair<ST>> o2_s = glb(static_cast<Pair<ST> *>(out_)) + zb;
-    const gptr<float> of_s = glb(static_cast<float *>(out_)) + zb;
+    // outputs of the slice: one ST field, the pair, or the float force
+    const rsrc_t rout = rsrc(static_cast<char *>(out_) +
+                             zb * (int64_t)(PAPER_F ? sizeof(float)
+                                                    : (NF == 2 ? sizeof(Pair<ST>) : sizeof(ST))));
     // step y (s = its index in the unrolled block) consumes stage `cur` and
     // refills it with the loads of step y + PF
     auto step = [&](Stage &cur, const int s, const int y) {
@@ -236,7 +243,8 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
         cur = stage(y + PF);
         // every lane stores: one past the slice edge (x >= nx) writes the
         // value of the last in-slice lane to that lane's element (same bits)
-        const int v = y * g.nx + xc;     // offset within the slice
+        const uint32_t v = (uint32_t)(y * g.nx + xc);   // offset within the slice
+        const uint32_t row = (uint32_t)(y * g.nx);
         auto edge = [&](float val) { return x < g.nx ? val : lane_value(val, last); };
         if (FITS) {
             const float ki = to_f(ki_raw);
@@ -251,7 +259,7 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
                 const float im = to_f(im_raw);
                 const float d1 = im - f1, d2 = im - f2;
                 const float Fd = edge(c.l1 * d1 * d1 - c.l2 * d2 * d2);
-                of_s[v] = Fd;
+                bst<float>(rout, (uint32_t)xc, Fd, row * 4u);
                 if (probe_fd) probe_fd[zb + v] = Fd;
             } else if (MODE == XY_PAPER2) {
                 // F+- = K2*I^2 - 2 r+- K2*I + r+-^2 (Sec. 4.2 expansion)
@@ -259,19 +267,21 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
                 const float F1 = q - 2.f * f1 * a + f1 * f1;
                 const float F2 = q - 2.f * f2 * a + f2 * f2;
                 const float Fd = edge(c.l1 * F1 - c.l2 * F2);
-                of_s[v] = Fd;
+                bst<float>(rout, (uint32_t)xc, Fd, row * 4u);
                 if (probe_fd) probe_fd[zb + v] = Fd;
             } else {
                 // force-convolution inputs g1, g2
-                st_pair<ST>(o2_s, v, edge(c.l1 * f1 - c.l2 * f2),
-                            edge(c.l1 * f1 * f1 - c.l2 * f2 * f2));
+                bst_pair<ST>(rout, (uint32_t)xc, edge(c.l1 * f1 - c.l2 * f2),
+                             edge(c.l1 * f1 * f1 - c.l2 * f2 * f2),
+                             row * (uint32_t)sizeof(Pair<ST>));
             }
             if (probe_f1) probe_f1[zb + v] = edge(f1);
             if (probe_f2) probe_f2[zb + v] = edge(f2);
         } else if (NF == 2) {
-            st_pair<ST>(o2_s, v, edge(acc_a), edge(acc_b));
+            bst_pair<ST>(rout, (uint32_t)xc, edge(acc_a), edge(acc_b),
+                         row * (uint32_t)sizeof(Pair<ST>));
         } else {
-            o1_s[v] = from_f<ST>(edge(acc_a));
+            bst<ST>(rout, (uint32_t)xc, from_f<ST>(edge(acc_a)), row * (uint32_t)sizeof(ST));
         }
     };
     for (int yb = y0; yb < y1; yb += M) {
@@ -368,12 +378,12 @@ __global__ __launch_bounds__(kThreads) void z_plain_kernel(Batch bt, Taps t, int
         target == Z_TO_KI ? d.KI : (target == Z_TO_K2I ? d.K2I : d.K2I2)));
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
-    const int col = zt.col;   // nx * ny < 2^31 - 1024
+    const uint32_t col = (uint32_t)zt.col;   // nx * ny <= kMaxPlane
     z_march<R, 1>(
         g.nz, zt.z0, zt.z1, t,
-        [&](int z) { return (in + (int64_t)z * g.sxy)[col]; },
+        [&](int z) { return bld<ST>(rsrc(in + (int64_t)z * g.sxy), col); },
         [&](ST raw, int) { return make_float2(to_f(raw), 0.f); },
-        [&](int z, float va, float) { (out + (int64_t)z * g.sxy)[col] = from_f<ST>(va); });
+        [&](int z, float va, float) { bst<ST>(rsrc(out + (int64_t)z * g.sxy), col, from_f<ST>(va)); });
 }
 
 // Stage-1 z pass: H_eps(phi) and H I formed as slices enter the ring.
@@ -392,12 +402,12 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t,
     const float eps = c.eps;
     const ZCols zt = z_cols(g, d.sp.z, wh.lb);
     if (!zt.active) return;
-    const int col = zt.col;   // nx * ny < 2^31 - 1024
+    const uint32_t col = (uint32_t)zt.col;   // nx * ny <= kMaxPlane
     z_march<R, 2>(
         g.nz, zt.z0, zt.z1, t,
         [&](int z) {
             const int64_t zo = (int64_t)z * g.sxy;
-            return PhiImg<IT>{(phi + zo)[col], (I + zo)[col]};
+            return PhiImg<IT>{bld<float>(rsrc(phi + zo), col), bld<IT>(rsrc(I + zo), col)};
         },
         [&](const PhiImg<IT> &raw, int z) {
             const float H = heaviside(raw.phi, eps);
@@ -410,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void z_heaviside_kernel(Batch bt, Taps t,
                 pin(va);
                 pin(vb);
             }
-            st_pair<ST>(tp + (int64_t)z * g.sxy, col, va, vb);
+            bst_pair<ST>(rsrc(tp + (int64_t)z * g.sxy), col, va, vb);
         });
 }
 
@@ -522,8 +532,9 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         auto fetch_phi = [&](int j) {
             PhiRaw r;
             const gptr<const float> base = phi + (int64_t)reflect(min(j, g.nz + 1), g.nz) * g.sxy;
+            const rsrc_t rb = rsrc(base);
 #pragma unroll
-            for (int k = 0; k < NLD; ++k) r.v[k] = *at32(base, loff[k]);
+            for (int k = 0; k < NLD; ++k) r.v[k] = bld<float>(rb, loff[k]);
             return r;
         };
         auto phi_slot = [&](int j) { return sphi[(j + 2 * NPHI) % NPHI]; };
@@ -573,9 +584,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         const uint32_t col = (uint32_t)(min(zt.y, g.ny - 1) * g.nx + min(zt.x, g.nx - 1));
         const float cxy = glb(d.cx)[min(zt.x, g.nx - 1)] * glb(d.cy)[min(zt.y, g.ny - 1)];
         const gptr<const IT> img = glb(static_cast<const IT *>(d.I));
-        auto pair_at = [&](int z) {
-            return *at32((gptr<const Vec2<ST>>)(tp + (int64_t)z * g.sxy), col);
-        };
+        auto pair_at = [&](int z) { return bld<Vec2<ST>>(rsrc(tp + (int64_t)z * g.sxy), col); };
         const int z0 = zt.z0;
         // prologue: phi(z0-2..z0+2), then n, V of z0-1, z0, z0+1
 #pragma unroll
@@ -639,7 +648,8 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
         const gptr<const float> fdp = glb(static_cast<const float *>(d.Q));
         using IRaw = typename std::conditional<PAPER, float, IT>::type;
         const gptr<const IRaw> ip = PAPER ? (gptr<const IRaw>)fdp : (gptr<const IRaw>)img;
-        auto iraw = [&](int z) { return *at32(ip + (int64_t)z * g.sxy, col); };
+        auto iraw = [&](int z) { return bld<IRaw>(rsrc(ip + (int64_t)z * g.sxy), col); };
+        const float *const czp = d.cz;   // read once: the loop's stores could alias the table
         struct Stage {
             PhiRaw phi;    // phi slice z + 3
             Vec2<ST> t;    // conv inputs of slice z + R
@@ -652,9 +662,10 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             st.phi = fetch_phi(z + 3);
             if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
             st.I = iraw(min(z, zmax));
-            st.cz = PAPER ? 0.f : uniform_ld(d.cz, min(z, zmax));
+            st.cz = PAPER ? 0.f : uniform_ld(czp, min(z, zmax));
             // (RSF force: the image of slice z is already st.I)
-            if constexpr (FUSE && PAPER) st.img = *at32(imgp + (int64_t)min(z, zmax) * g.sxy, col);
+            if constexpr (FUSE && PAPER)
+                st.img = bld<IT>(rsrc(imgp + (int64_t)min(z, zmax) * g.sxy), col);
             return st;
         };
         Stage sa = stage(z0), sb{};
@@ -681,7 +692,8 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                     pin(acc_a);
                     pin(acc_b);
                 }
-                if (z >= R && zt.active) st_pair32<ST>(tout + (int64_t)(z - R) * g.sxy, col, acc_a, acc_b);
+                if (z >= R && zt.active)
+                    bst_pair<ST>(rsrc(tout + (int64_t)(z - R) * g.sxy), col, acc_a, acc_b);
             }
         };
         // step z (s = its index in the unrolled block) consumes stage `cur`
@@ -750,7 +762,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                 const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
                 const float nxt = cphi + ua.dt * E;
-                *at32(phi_out + zo, col) = nxt;
+                bst<float>(rsrc(phi_out + zo), col, nxt);
                 acc += fabs((double)nxt - (double)cphi);
                 if constexpr (FUSE) {
                     Hs = heaviside(nxt, ua.eps);
@@ -891,7 +903,7 @@ hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t
         hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
                            dim3(kUThreads), 0, s, b, t, c);
     } else {
-        if constexpr (R > kFuseMaxR) return hipErrorInvalidValue;
+        if constexpr (R > fuse_max_r_t<ST>) return hipErrorInvalidValue;
         else
             hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, false, true>),
                                dim3((unsigned)blocks), dim3(kUThreads), 0, s, b, t, c);

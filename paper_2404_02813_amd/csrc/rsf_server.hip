@@ -335,6 +335,7 @@ bool launch_chunk(rsf_server *s, std::string &why)
         int iters;
         View run_xy, run_z, run_u, run_tile, new_xy, new_z, new_tile, fin_z;
         int n_new, n_run, n_fin;
+        bool fuse;
     };
     std::vector<Launch> launches;
 
@@ -351,6 +352,14 @@ bool launch_chunk(rsf_server *s, std::string &why)
             if (t->remaining == 0 || t->stopped) fin.push_back(t);
         if (run.empty() && fin.empty()) continue;
 
+        // The group's update carries the next stage-1 z pass when its force
+        // and radius allow it (the RSF force's stage-2 ring leaves room up to
+        // radius fuse_max_r); its tiles are then marched whole in z, and one
+        // stage-1 pass opens the chunk.
+        const Tile *gp = kv.second.front();
+        const bool fuse = !s->cfg.separate_passes &&
+                          (gp->req.params.force == RSF_FORCE_PAPER ||
+                           gp->R <= rsf::fuse_max_r(gp->req.params.storage));
         // splits from each tile's share of the group's running voxels
         double vox = 0.0;
         for (Tile *t : run) vox += (double)t->g.nx * t->g.ny * t->g.nz;
@@ -358,7 +367,8 @@ bool launch_chunk(rsf_server *s, std::string &why)
         for (Tile *t : fin) vox_fin += (double)t->g.nx * t->g.ny * t->g.nz;
         auto desc_of = [&](Tile *t, double total) {
             const double share = (double)t->g.nx * t->g.ny * t->g.nz / total;
-            const Split sp = rsf::default_split(t->g, share, s->targets);
+            Split sp = rsf::default_split(t->g, share, s->targets);
+            if (fuse) sp.u = 1;
             int *flags = reinterpret_cast<int *>(reinterpret_cast<char *>(s->flags_dev) +
                                                  (size_t)t->slot * kSlotBytes);
             return tile_desc(t->g, sp, t->req.volume, t->req.phi, t->base, t->T, t->req.iters,
@@ -405,6 +415,7 @@ bool launch_chunk(rsf_server *s, std::string &why)
         L.n_run = (int)run.size();
         L.n_new = (int)fresh.size();
         L.n_fin = (int)fin.size();
+        L.fuse = fuse;
         const TileDesc *dr = reinterpret_cast<const TileDesc *>(tw.dev + o_run);
         const TileDesc *df = reinterpret_cast<const TileDesc *>(tw.dev + o_fin);
         auto ip = [&](size_t o) { return reinterpret_cast<const int *>(tw.dev + o); };
@@ -488,10 +499,16 @@ bool launch_chunk(rsf_server *s, std::string &why)
                 return false;
         }
         const bool paper = L.c.force == RSF_FORCE_PAPER;
+        // fused: one stage-1 pass opens the chunk, each update writes the next
+        if (L.fuse && L.iters > 0 &&
+            !ok(rsf::launch_z_heaviside(L.R, L.image, L.storage, L.run_z.b, L.run_z.blocks,
+                                        L.taps, L.c, false, st),
+                "z(H)"))
+            return false;
         for (int it = 0; it < L.iters; ++it) {
-            if (!ok(rsf::launch_z_heaviside(L.R, L.image, L.storage, L.run_z.b, L.run_z.blocks,
-                                            L.taps, L.c, false, st),
-                    "z(H)") ||
+            if ((!L.fuse && !ok(rsf::launch_z_heaviside(L.R, L.image, L.storage, L.run_z.b,
+                                                        L.run_z.blocks, L.taps, L.c, false, st),
+                                "z(H)")) ||
                 !ok(rsf::launch_xy(L.R,
                                    paper ? (L.k2 ? rsf::XY_PAPER2 : rsf::XY_PAPER) : rsf::XY_FITS,
                                    L.image, L.storage, L.run_xy.b, L.run_xy.blocks, L.taps, L.c,
@@ -500,10 +517,12 @@ bool launch_chunk(rsf_server *s, std::string &why)
                 (!paper && !ok(rsf::launch_xy(L.R, rsf::XY_TWO, L.image, L.storage, L.run_xy.b,
                                               L.run_xy.blocks, L.taps, L.c, false, st),
                                "xy(g)")) ||
-                !ok(paper ? rsf::launch_z_update_paper(L.image, L.storage, L.run_u.b,
-                                                       L.run_u.blocks, L.c, false, st)
-                          : rsf::launch_z_update(L.R, L.image, L.storage, L.run_u.b,
-                                                 L.run_u.blocks, L.taps, L.c, false, st),
+                !ok(L.fuse ? rsf::launch_z_update_fused(L.R, L.image, L.storage, L.run_u.b,
+                                                        L.run_u.blocks, L.taps, L.c, paper, st)
+                    : paper ? rsf::launch_z_update_paper(L.image, L.storage, L.run_u.b,
+                                                         L.run_u.blocks, L.c, false, st)
+                            : rsf::launch_z_update(L.R, L.image, L.storage, L.run_u.b,
+                                                   L.run_u.blocks, L.taps, L.c, false, st),
                     "z(update)") ||
                 !ok(rsf::launch_reduce(L.run_tile.b, L.c, st), "reduce"))
                 return false;
@@ -682,7 +701,8 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
     *out = nullptr;
     if (!cfg || cfg->budget_bytes == 0) return RSF_ERR_INVALID_ARG;
     if (cfg->chunk_iters < 0 || cfg->max_resident < 0 || cfg->max_resident > kMaxResident ||
-        cfg->batch_voxels < 0 || (cfg->order != RSF_ORDER_ARRIVAL && cfg->order != RSF_ORDER_SHORTEST))
+        cfg->batch_voxels < 0 || (cfg->order != RSF_ORDER_ARRIVAL && cfg->order != RSF_ORDER_SHORTEST) ||
+        (cfg->separate_passes != 0 && cfg->separate_passes != 1))
         return RSF_ERR_INVALID_ARG;
     for (int k = 0; k < 3; ++k)
         if (cfg->split_targets[k] < 0 || cfg->split_targets[k] > (1 << 24)) return RSF_ERR_INVALID_ARG;

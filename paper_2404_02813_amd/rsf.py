@@ -43,7 +43,8 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi", "rsf_set_fusion",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
-           "rsf_server_destroy")
+           "rsf_server_destroy", "rsf_set_graphs", "rsf_stream_probe")
+
 
 PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce",
               "init_smooth", "init_hessian", "init_select", "init_sweep", "init_offset")
@@ -86,7 +87,8 @@ class rsf_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
                 ("segment_bytes", ctypes.c_size_t), ("chunk_iters", ctypes.c_int),
                 ("max_resident", ctypes.c_int), ("batch_voxels", ctypes.c_int64),
-                ("order", ctypes.c_int), ("split_targets", ctypes.c_int64 * 3)]
+                ("order", ctypes.c_int), ("split_targets", ctypes.c_int64 * 3),
+                ("separate_passes", ctypes.c_int)]
 
 
 class rsf_request(ctypes.Structure):
@@ -162,6 +164,10 @@ def lib() -> ctypes.CDLL:
     L.rsf_autotune.restype = i
     L.rsf_set_fusion.argtypes = [vp, i]
     L.rsf_set_fusion.restype = i
+    L.rsf_set_graphs.argtypes = [vp, i]
+    L.rsf_set_graphs.restype = i
+    L.rsf_stream_probe.argtypes = [vp, i, vp, i, i64, vp]
+    L.rsf_stream_probe.restype = i
     i64p = ctypes.POINTER(ctypes.c_int64)
     L.rsf_seeds.argtypes = [vp, vp, i, i64, i64, i64, f, f, vp, i64p, vp]
     L.rsf_seeds.restype = i
@@ -338,10 +344,11 @@ def _tiles(volumes, phis):
 
 def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
                  stream=None) -> tuple:
-    """Pick and keep per-shape workgroup splits by timing (phis untouched);
-    returns the chosen (xy, z, update) workgroup targets."""
+    """Pick and keep per-shape workgroup splits and the schedule by timing
+    (phis untouched); returns the chosen (xy, z, update) workgroup targets and
+    1 if the fused update was chosen, else 0."""
     arr, vdt = _tiles(volumes, phis)
-    chosen = (ctypes.c_int64 * 3)()
+    chosen = (ctypes.c_int64 * 4)()
     _check(ctx, lib().rsf_autotune(ctx, arr, len(volumes), vdt, ctypes.byref(params),
                                    int(trial_iters), chosen, _stream(stream)))
     return tuple(chosen)
@@ -361,6 +368,28 @@ def rsf_batch_workspace_bytes_params(shapes, iters: int, params: rsf_params) -> 
 
 def rsf_set_fusion(ctx, on: bool) -> None:
     _check(ctx, lib().rsf_set_fusion(ctx, 1 if on else 0))
+
+
+def rsf_set_graphs(ctx, on: bool) -> None:
+    _check(ctx, lib().rsf_set_graphs(ctx, 1 if on else 0))
+
+
+def rsf_stream_probe(inp: torch.Tensor, n_read: int, out: torch.Tensor, n_write: int,
+                     stream=None) -> None:
+    """One launch of the streaming kernel: n_read float fields of inp (flat,
+    n_read * n floats) summed into n_write fields of out."""
+    for t, k, name in ((inp, n_read, "inp"), (out, n_write, "out")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        if t.numel() % k:
+            raise ValueError(f"{name} must hold a whole number of fields")
+    n = inp.numel() // n_read
+    if out.numel() // n_write != n:
+        raise ValueError("inp and out fields must have the same length")
+    st = lib().rsf_stream_probe(inp.data_ptr(), int(n_read), out.data_ptr(), int(n_write), n,
+                                _stream(stream))
+    if st != RSF_OK:
+        raise RsfError(st, "rsf_stream_probe failed")
 
 
 def rsf_seeds(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
@@ -529,6 +558,9 @@ class Context:
         rsf_evolve_volume(self.handle, volume, phi, params, iters, block, curtain, budget_bytes,
                           stream)
 
+    def set_graphs(self, on: bool) -> None:
+        rsf_set_graphs(self.handle, on)
+
     def set_fusion(self, on: bool) -> None:
         rsf_set_fusion(self.handle, on)
 
@@ -574,10 +606,12 @@ def _server_check(srv, status: int) -> None:
 
 def rsf_server_create(budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
                       segment_bytes: int = 0, device: int = 0, batch_voxels: int = 0,
-                      order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0)) -> ctypes.c_void_p:
+                      order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0),
+                      separate_passes: bool = False) -> ctypes.c_void_p:
     cfg = rsf_server_config(device, int(budget_bytes), int(segment_bytes), int(chunk_iters),
                             int(max_resident), int(batch_voxels), int(order),
-                            (ctypes.c_int64 * 3)(*[int(v) for v in split_targets]))
+                            (ctypes.c_int64 * 3)(*[int(v) for v in split_targets]),
+                            1 if separate_passes else 0)
     h = ctypes.c_void_p()
     st = lib().rsf_server_create(ctypes.byref(h), ctypes.byref(cfg))
     if st != RSF_OK:
@@ -641,9 +675,11 @@ class Server:
 
     def __init__(self, budget_bytes: int, chunk_iters: int = 0, max_resident: int = 0,
                  segment_bytes: int = 0, device: int = 0, batch_voxels: int = 0,
-                 order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0)):
+                 order: int = RSF_ORDER_ARRIVAL, split_targets=(0, 0, 0),
+                 separate_passes: bool = False):
         self.handle = rsf_server_create(budget_bytes, chunk_iters, max_resident, segment_bytes,
-                                        device, batch_voxels, order, split_targets)
+                                        device, batch_voxels, order, split_targets,
+                                        separate_passes)
         self._held = {}
 
     def submit(self, volume, phi, params, iters, tol=0.0) -> int:

@@ -482,7 +482,8 @@ def test_autotune_keeps_results(rsf):
 
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
 # alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
-# tiles of at most 8 slices; with the RSF force only up to radius 10.
+# tiles of at most 8 slices; with the RSF force only up to radius 10 (12 with
+# FP16 storage).
 RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
     ((40, 770, 256), "f32", "f32", 3.0, 9, 0.0, True),
     ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, True),
@@ -490,6 +491,8 @@ RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
     ((8, 34, 34), "f32", "f32", 3.0, 80, 2e-3, True),
     ((6, 21, 23), "f32", "f32", 1.0, 4, 0.0, True),
     ((8, 30, 30), "f32", "f32", 3.4, 5, 0.0, False),   # R = 11: separate passes
+    ((8, 38, 41), "u16", "f16", 4.0, 7, 0.0, True),    # R = 12 fuses with FP16 storage
+    ((8, 36, 33), "u16", "bf16", 4.0, 5, 0.0, False),  # R = 12, BF16: separate passes
 ]
 
 
