@@ -173,6 +173,28 @@ rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype,
                          int iters, double tol, void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  As
+ * rsf_evolve_ex with the context's workspace, but that workspace is a fixed
+ * device array of RSF_NOALLOC_MAX_BYTES per GPU, created with the library's
+ * code object on that device and held until the process ends, and the tile
+ * table is written by a kernel from its argument: the call allocates no
+ * device or pinned host memory (no hipMalloc, hipFree or hipHostMalloc, no
+ * events; rsf_profile_enable is ignored for it).  The caller passes the
+ * image and phi as in rsf_evolve_ex.
+ *   RSF_ERR_INVALID_ARG when rsf_workspace_bytes_params(nx, ny, nz, iters,
+ *   params) exceeds RSF_NOALLOC_MAX_BYTES (e.g. 128^3 voxels with FP32
+ *   storage fit, 192^3 with FP16 storage fit), phi untouched.
+ * Every call on one GPU, from any context or stream, shares that GPU's array,
+ * which keeps the last call's contents (each call's set-up clears what must
+ * start at zero): calls that overlap on one GPU race, and the caller must
+ * order them.  rsf_get_stats() reads the last call's sums from the array
+ * until the next such call. */
+#define RSF_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+rsf_status rsf_evolve_noalloc(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                              int64_t nx, int64_t ny, int64_t nz, const rsf_params *params,
+                              int iters, double tol, void *stream);
+
 /* One volume of a batch (device pointers, as in rsf_evolve). */
 typedef struct {
     const void *volume;   /* image I, nx*ny*nz elements of the batch's volume dtype */

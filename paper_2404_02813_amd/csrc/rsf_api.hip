@@ -10,6 +10,7 @@
 #include <cstring>
 #include <exception>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -32,6 +33,41 @@ using rsf::host::make_coeffs;
 using rsf::host::make_taps;
 using rsf::host::radius_of;
 
+// Workspace of rsf_evolve_noalloc: one array per GPU, loaded with the
+// library's code object and held until the process ends.  In host code the
+// name is only a handle: its device address, per device, comes from
+// hipGetSymbolAddress at rsf_create and is used everywhere instead.
+__device__ __align__(256) char scratch[RSF_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current (the caller's current device is restored).
+hipError_t scratch_address(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        e = hipSetDevice(device);
+        if (e != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (e2 != hipSuccess) return e2;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct rsf_context {
@@ -45,6 +81,8 @@ struct rsf_context {
     hipStream_t ws_stream = nullptr;
     hipEvent_t ws_ev = nullptr;
     bool ws_pending = false;
+    // this device's copy of the no-alloc workspace (`scratch`)
+    void *noalloc_ws = nullptr;
     // pinned staging of the tile table, and the event of its last upload
     void *stage = nullptr;
     size_t stage_bytes = 0;
@@ -388,7 +426,8 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
 // `probe` is for rsf_probe (one tile); `ki_out` for rsf_gauss3d.
 rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, int image,
                      const rsf_params &p, double tol, int iters, char *base, hipStream_t s,
-                     const rsf_probe_fields *probe = nullptr, void *ki_out = nullptr)
+                     const rsf_probe_fields *probe = nullptr, void *ki_out = nullptr,
+                     bool table_by_kernel = false)
 {
     P.n = n;
     P.R = radius_of(p.sigma);
@@ -402,9 +441,19 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     const bool fuse = decide_fuse(ctx, p, probe != nullptr, tiles, n, image);
     P.L = plan_layout(tiles, n, iters, p.storage, splits_for(ctx, tiles, n, P.R, fuse), P.k2);
     P.base = base;
-    rsf_status st = ensure_stage(ctx, P.L.table_bytes);
-    if (st != RSF_OK) return st;
-    char *h = static_cast<char *>(ctx->stage);
+    // the table is built on the host: in the pinned staging buffer and
+    // copied, or (table_by_kernel) in a kernel argument, allocating nothing
+    rsf::TableBlob blob;
+    char *h = nullptr;
+    if (table_by_kernel) {
+        if (P.L.table_bytes > sizeof(blob.w))
+            return fail(ctx, RSF_ERR_INVALID_ARG, "tile table too large");
+        h = reinterpret_cast<char *>(blob.w);
+    } else {
+        const rsf_status st = ensure_stage(ctx, P.L.table_bytes);
+        if (st != RSF_OK) return st;
+        h = static_cast<char *>(ctx->stage);
+    }
     std::memset(h, 0, P.L.table_bytes);
     TileDesc *hd = reinterpret_cast<TileDesc *>(h + P.L.descs);
     for (int t = 0; t < n; ++t) {
@@ -423,9 +472,14 @@ rsf_status make_plan(rsf_context *ctx, Plan &P, const rsf_tile *tiles, int n, in
     std::memcpy(h + P.L.start_xy, P.L.pre_xy.data(), sizeof(int) * (n + 1));
     std::memcpy(h + P.L.start_z, P.L.pre_z.data(), sizeof(int) * (n + 1));
     std::memcpy(h + P.L.start_u, P.L.pre_u.data(), sizeof(int) * (n + 1));
-    HIP_TRY(hipMemcpyAsync(base, h, P.L.table_bytes, hipMemcpyHostToDevice, s), "upload tile table");
-    HIP_TRY(hipEventRecord(ctx->stage_ev, s), "hipEventRecord(stage)");
-    ctx->stage_pending = true;
+    if (table_by_kernel) {
+        HIP_TRY(rsf::launch_put_table(base, blob, (int)P.L.table_bytes, s), "write tile table");
+    } else {
+        HIP_TRY(hipMemcpyAsync(base, h, P.L.table_bytes, hipMemcpyHostToDevice, s),
+                "upload tile table");
+        HIP_TRY(hipEventRecord(ctx->stage_ev, s), "hipEventRecord(stage)");
+        ctx->stage_pending = true;
+    }
     P.descs = reinterpret_cast<TileDesc *>(base + P.L.descs);
     auto view = [&](size_t start) {
         return Batch{P.descs, reinterpret_cast<const int *>(base + start), n, {}};
@@ -538,8 +592,8 @@ rsf_status iteration(rsf_context *ctx, const Plan &P, bool probe, hipStream_t s,
 // the same (same workspace, tile table, taps and coefficients); a different
 // one replaces it once its last replay has completed.  The captured region
 // holds kernel launches only (no memset, no copy, no event).  Per-pass event
-// timing, or a caller that passes allow_graph false, launches every
-// iteration directly.
+// timing, and the no-alloc form (graph objects are allocations), launch
+// every iteration directly.
 constexpr int kGraphMinIters = 8;
 constexpr int kGraphGroup = 16;
 
@@ -632,9 +686,12 @@ rsf_status run_iterations(rsf_context *ctx, const Plan &P, int iters, hipStream_
     return RSF_OK;
 }
 
+// `fixed`: the no-alloc form.  The workspace is the device's `scratch`
+// array (in `workspace`), the tile table is written by a kernel, and no
+// per-pass events or graphs are made, so nothing is allocated.
 rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
                        const rsf_params &p, int iters, double tol, void *workspace,
-                       size_t ws_bytes, void *stream)
+                       size_t ws_bytes, void *stream, bool fixed = false)
 {
     if (!ctx) return RSF_ERR_INVALID_ARG;
     ctx->err.clear();
@@ -653,6 +710,9 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
                                     splits_for(ctx, tiles, n, radius_of(p.sigma)),
                                     rsf::host::needs_k2(p))
                             .total;
+    if (fixed && ws_bytes < need)
+        return fail(ctx, RSF_ERR_INVALID_ARG,
+                    "volume too large for the no-alloc workspace (RSF_NOALLOC_MAX_BYTES)");
     if (workspace && ws_bytes < need) return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
     if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
         return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -667,7 +727,7 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
         if (st != RSF_OK) return st;
     }
     Plan P;
-    st = make_plan(ctx, P, tiles, n, vdt, p, tol, iters, base, s);
+    st = make_plan(ctx, P, tiles, n, vdt, p, tol, iters, base, s, nullptr, nullptr, fixed);
     if (st != RSF_OK) return st;
     st = prologue(ctx, P, s);
     if (st != RSF_OK) return st;
@@ -676,7 +736,7 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
         st = stage1(ctx, P, false, s);
         if (st != RSF_OK) return st;
     }
-    st = run_iterations(ctx, P, iters, s, fused, true);
+    st = run_iterations(ctx, P, iters, s, fused, !fixed);
     if (st != RSF_OK) return st;
     // tiles that ended on an odd iteration have it in the workspace buffer
     if (iters > 0) HIP_TRY(rsf::launch_finish(P.z, P.blocks_z, s), "finish");
@@ -776,9 +836,12 @@ rsf_status rsf_create(rsf_context **out, int device_ordinal)
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device_ordinal < 0 || device_ordinal >= n)
             return RSF_ERR_INVALID_ARG;
+        void *sp = nullptr;
+        if (scratch_address(device_ordinal, &sp) != hipSuccess) return RSF_ERR_DEVICE;
         rsf_context *c = new (std::nothrow) rsf_context();
         if (!c) return RSF_ERR_OUT_OF_MEMORY;
         c->device = device_ordinal;
+        c->noalloc_ws = sp;
         *out = c;
         return RSF_OK;
     } catch (...) {
@@ -931,6 +994,29 @@ rsf_status rsf_evolve_ex(rsf_context *ctx, const void *volume, int volume_dtype,
         rsf_tile t{volume, phi, nx, ny, nz};
         return evolve_impl(ctx, &t, 1, volume_dtype, *params, iters, tol, workspace,
                            workspace_bytes, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(ctx, RSF_ERR_INTERNAL, "internal error");
+    }
+}
+
+rsf_status rsf_evolve_noalloc(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                              int64_t nx, int64_t ny, int64_t nz, const rsf_params *params,
+                              int iters, double tol, void *stream)
+{
+    try {
+        if (!ctx) return RSF_ERR_INVALID_ARG;
+        if (!params) return fail(ctx, RSF_ERR_INVALID_ARG, "null params");
+        if (!ctx->noalloc_ws) return fail(ctx, RSF_ERR_DEVICE, "no-alloc workspace not found");
+        rsf_tile t{volume, phi, nx, ny, nz};
+        // no per-pass events: creating them could allocate
+        const bool prof = ctx->prof;
+        ctx->prof = false;
+        const rsf_status st = evolve_impl(ctx, &t, 1, volume_dtype, *params, iters, tol,
+                                          ctx->noalloc_ws, RSF_NOALLOC_MAX_BYTES, stream, true);
+        ctx->prof = prof;
+        return st;
     } catch (const std::bad_alloc &) {
         return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {

@@ -151,6 +151,14 @@ enum ZTarget { Z_TO_KI = 0, Z_TO_K2I = 1, Z_TO_K2I2 = 2 };
 
 // One workgroup per tile: K*1 edge tables, flags cleared.
 hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s);
+// A small host-built table written to device memory by a kernel from its own
+// argument: no pinned staging buffer and no copy, for the entry point that
+// allocates nothing.
+constexpr int kTableBlobBytes = 2048;
+struct TableBlob {
+    uint32_t w[kTableBlobBytes / 4];
+};
+hipError_t launch_put_table(void *dst, const TableBlob &blob, int bytes, hipStream_t s);
 hipError_t launch_xy(int R, int mode, int image_dtype, int storage_dtype, const Batch &b,
                      int64_t blocks, const Taps &t, const Coeffs &c, bool probe, hipStream_t s);
 // K*I: the z pass of P into KI.

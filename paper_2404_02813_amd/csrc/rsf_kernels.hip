@@ -52,6 +52,13 @@ __global__ __launch_bounds__(kThreads) void setup_kernel(Batch bt, Taps t, int R
     }
 }
 
+// The tile table of a batch from the kernel argument (one workgroup).
+__global__ __launch_bounds__(kThreads) void put_table_kernel(uint32_t *dst, TableBlob blob,
+                                                             int words)
+{
+    for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = blob.w[i];
+}
+
 // Fixed-order FP64 sum of one tile's update-pass partials into hist[iters
 // run]; sets the tile's stop flag when the tolerance is met.
 __global__ __launch_bounds__(kThreads) void reduce_kernel(Batch bt, Coeffs c)
@@ -517,6 +524,14 @@ hipError_t launch_fill(float *dst, int64_t n, float v, hipStream_t s)
 hipError_t launch_setup(const Batch &b, const Taps &t, int R, hipStream_t s)
 {
     hipLaunchKernelGGL(setup_kernel, dim3(b.n), dim3(kThreads), 0, s, b, t, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_table(void *dst, const TableBlob &blob, int bytes, hipStream_t s)
+{
+    if (bytes < 0 || bytes > kTableBlobBytes || bytes % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(put_table_kernel, dim3(1), dim3(kThreads), 0, s,
+                       static_cast<uint32_t *>(dst), blob, bytes / 4);
     return hipGetLastError();
 }
 

@@ -43,8 +43,9 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi", "rsf_set_fusion",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
-           "rsf_server_destroy", "rsf_set_graphs", "rsf_stream_probe")
+           "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe")
 
+RSF_NOALLOC_MAX_BYTES = 128 << 20
 
 PASS_NAMES = ("setup", "z_heaviside", "xy_fits", "xy_force", "z_update", "reduce",
               "init_smooth", "init_hessian", "init_select", "init_sweep", "init_offset")
@@ -144,6 +145,9 @@ def lib() -> ctypes.CDLL:
     L.rsf_evolve_ex.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params), i,
                                 ctypes.c_double, vp, ctypes.c_size_t, vp]
     L.rsf_evolve_ex.restype = i
+    L.rsf_evolve_noalloc.argtypes = [vp, vp, i, vp, i64, i64, i64, ctypes.POINTER(rsf_params),
+                                     i, ctypes.c_double, vp]
+    L.rsf_evolve_noalloc.restype = i
     L.rsf_get_stats.argtypes = [vp, ctypes.POINTER(rsf_stats), ctypes.POINTER(ctypes.c_double), i]
     L.rsf_get_stats.restype = i
     L.rsf_gauss3d.argtypes = [vp, vp, vp, i64, i64, i64, f, vp]
@@ -305,6 +309,20 @@ def rsf_evolve_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_para
                                     phi.data_ptr(), nx, ny, nz,
                                     ctypes.byref(params), int(iters), float(tol), ws_ptr,
                                     ws_bytes, _stream(stream)))
+
+
+def rsf_evolve_noalloc(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
+                       iters: int, tol: float = 0.0, stream=None) -> None:
+    """As rsf_evolve_ex, with the library's fixed per-GPU workspace (no
+    device allocation); volumes up to RSF_NOALLOC_MAX_BYTES of workspace."""
+    _field(volume, "volume", "image")
+    _field(phi, "phi")
+    if volume.shape != phi.shape or volume.device != phi.device:
+        raise ValueError("volume and phi must have the same shape and device")
+    nz, ny, nx = phi.shape
+    _check(ctx, lib().rsf_evolve_noalloc(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                         phi.data_ptr(), nx, ny, nz, ctypes.byref(params),
+                                         int(iters), float(tol), _stream(stream)))
 
 
 def rsf_get_stats(ctx, cap: int = 0):
@@ -540,6 +558,9 @@ class Context:
 
     def evolve_ex(self, volume, phi, params, iters, tol=0.0, workspace=None, stream=None):
         rsf_evolve_ex(self.handle, volume, phi, params, iters, tol, workspace, stream)
+
+    def evolve_noalloc(self, volume, phi, params, iters, tol=0.0, stream=None):
+        rsf_evolve_noalloc(self.handle, volume, phi, params, iters, tol, stream)
 
     def stats(self, cap=0):
         return rsf_get_stats(self.handle, cap)
