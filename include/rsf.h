@@ -373,8 +373,10 @@ typedef struct {
 /* The update also forms the next iteration's stage-1 z Gaussian (Sec. 3
  * fits) from the phi it has just written, so that pass is not launched again
  * (on != 0, the default).  Applies to single volumes and batches alike when
- * the RSF force's radius ceil(3 sigma) <= 10 (any radius for the Sec. 4.2
- * force); every tile's update then marches its whole z extent.  Results are
+ * the RSF force's radius ceil(3 sigma) is at most 12 with RSF_F16 storage, 9
+ * with RSF_F32 or RSF_BF16 storage and an RSF_F32 image, 8 with a uint16
+ * image (any radius for the Sec. 4.2 force); every tile's update then marches
+ * its whole z extent.  Results are
  * bitwise the same either way; off runs the passes separately.  Affects later
  * rsf_evolve* calls on this context. */
 rsf_status rsf_set_fusion(rsf_context *ctx, int on);

@@ -364,10 +364,11 @@ std::vector<int64_t> schedule_key(const rsf_tile *tiles, int n, const rsf_params
 
 // Whether the force and radius allow the fused update at all (the context's
 // switch on, no probe).
-bool fusable(const rsf_context *ctx, const rsf_params &p, bool probe)
+bool fusable(const rsf_context *ctx, const rsf_params &p, bool probe, int image)
 {
     return ctx && ctx->fuse && !probe &&
-           (p.force == RSF_FORCE_PAPER || radius_of(p.sigma) <= rsf::fuse_max_r(p.storage));
+           (p.force == RSF_FORCE_PAPER ||
+            radius_of(p.sigma) <= rsf::fuse_max_r(p.storage, image));
 }
 
 std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R,
@@ -381,7 +382,7 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
 bool decide_fuse(const rsf_context *ctx, const rsf_params &p, bool probe, const rsf_tile *tiles,
                  int n, int image)
 {
-    if (!fusable(ctx, p, probe)) return false;
+    if (!fusable(ctx, p, probe, image)) return false;
     if (ctx->force_schedule >= 0) return ctx->force_schedule == 1;
     const auto it = ctx->tuned_fuse.find(schedule_key(tiles, n, p, image));
     if (it != ctx->tuned_fuse.end()) return it->second;
@@ -1156,7 +1157,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
         // separate passes, where the force and radius allow fusing.
         const std::vector<int64_t> skey = schedule_key(tiles, n_tiles, *params, volume_dtype);
         ctx->tuned_fuse.erase(skey);
-        const bool can_fuse = fusable(ctx, *params, false);
+        const bool can_fuse = fusable(ctx, *params, false, volume_dtype);
         ctx->force_schedule = 0;
         float best_ms = -1.f;
         for (int axis = 0; axis < 3; ++axis) {

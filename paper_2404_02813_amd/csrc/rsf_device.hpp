@@ -58,6 +58,15 @@ __device__ __forceinline__ gptr<T> glb(T *p)
     return (gptr<T>)p;
 }
 
+// Tap k of the 2R + 1 Gaussian taps.  The taps are symmetric by
+// construction (w[R + k] = w[R - k]), so only w[0..R] are read and R fewer
+// scalar registers hold the kernel.
+template <int R>
+__device__ __forceinline__ float tap(const Taps &t, int k)
+{
+    return t.w[k <= R ? k : 2 * R - k];
+}
+
 // Buffer-resource access.  The wave-uniform 64-bit base of an array (a
 // slice, or any array under 4 GiB) lives in a scalar resource descriptor and
 // each lane supplies only a 32-bit byte offset, so no 64-bit address

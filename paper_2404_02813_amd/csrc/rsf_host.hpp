@@ -35,7 +35,9 @@ inline Taps make_taps(float sigma, int R)
         w[k + R] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
         sum += w[k + R];
     }
-    for (int k = 0; k < 2 * R + 1; ++k) t.w[k] = (float)(w[k] / sum);
+    // mirrored, so that the taps are exactly symmetric (the kernels read
+    // w[0..R] only)
+    for (int k = 0; k <= R; ++k) t.w[R - k] = t.w[R + k] = (float)(w[R + k] / sum);
     return t;
 }
 

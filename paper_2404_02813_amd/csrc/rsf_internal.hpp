@@ -179,15 +179,20 @@ hipError_t launch_z_update_paper(int image_dtype, int storage_dtype, const Batch
 // Largest Gaussian radius whose RSF-force update is fused with the next
 // stage-1 pass (the Sec. 4.2 force's update has no stage-2 ring: any radius).
 // A stage-2 ring slot holds two floats with FP32 or BF16 storage and one
-// packed pair with FP16 storage, which leaves room for the stage-1 ring up to
-// radius 12 (storage dtype 1 is FP16, as in rsf_dtype).
-constexpr int kFuseMaxR = 10;
+// packed pair with FP16 storage, which leaves room for the stage-1 ring and
+// the prefetched stage with no spill in the march up to radius 9 (8 with a
+// uint16 image), resp. 12 (storage and image dtypes as in rsf_dtype: 1 is
+// FP16, 3 uint16).
+constexpr int kFuseMaxR = 9;
+constexpr int kFuseMaxRU16 = 8;
 constexpr int kFuseMaxRPacked = 12;
-template <class ST>
-constexpr int fuse_max_r_t = std::is_same<ST, _Float16>::value ? kFuseMaxRPacked : kFuseMaxR;
-inline int fuse_max_r(int storage_dtype)
+template <class ST, class IT>
+constexpr int fuse_max_r_t = std::is_same<ST, _Float16>::value
+                                 ? kFuseMaxRPacked
+                                 : (std::is_same<IT, uint16_t>::value ? kFuseMaxRU16 : kFuseMaxR);
+inline int fuse_max_r(int storage_dtype, int image_dtype)
 {
-    return storage_dtype == 1 ? kFuseMaxRPacked : kFuseMaxR;
+    return storage_dtype == 1 ? kFuseMaxRPacked : (image_dtype == 3 ? kFuseMaxRU16 : kFuseMaxR);
 }
 // The update (RSF force, or the Sec. 4.2 force if `paper`) fused with the
 // next iteration's stage-1 z pass (writes P from phi' as launch_z_heaviside

@@ -129,8 +129,8 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
         float ca = 0.f, cb = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            ca = fmaf(t.w[k], row[slot][0][lane + k], ca);
-            if (NF == 2) cb = fmaf(t.w[k], row[slot][NF - 1][lane + k], cb);
+            ca = fmaf(tap<R>(t, k), row[slot][0][lane + k], ca);
+            if (NF == 2) cb = fmaf(tap<R>(t, k), row[slot][NF - 1][lane + k], cb);
         }
         __asm__ volatile("" : "+v"(ca), "+v"(cb), "+v"(yv.x), "+v"(yv.y));
         return make_float2(ca, cb);
@@ -223,8 +223,8 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
             float a = 0.f, b = 0.f;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                a = fmaf(t.w[k], ra[(s + k) % M], a);
-                if (NF == 2) b = fmaf(t.w[k], rb[(s + k) % M], b);
+                a = fmaf(tap<R>(t, k), ra[(s + k) % M], a);
+                if (NF == 2) b = fmaf(tap<R>(t, k), rb[(s + k) % M], b);
             }
             return make_float2(a, b);
         };
@@ -353,8 +353,8 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
                 float acc_a = 0.f, acc_b = 0.f;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    acc_a = fmaf(t.w[k], ra[(s + k) % W], acc_a);
-                    if (NF == 2) acc_b = fmaf(t.w[k], rb[(s + k) % W], acc_b);
+                    acc_a = fmaf(tap<R>(t, k), ra[(s + k) % W], acc_a);
+                    if (NF == 2) acc_b = fmaf(tap<R>(t, k), rb[(s + k) % W], acc_b);
                 }
                 epi(z, acc_a, acc_b);
             }
@@ -537,6 +537,17 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             for (int k = 0; k < NLD; ++k) r.v[k] = bld<float>(rb, loff[k]);
             return r;
         };
+        // Fast form (see `fast` below): slice j is in the volume, and its
+        // offset from phi is a 32-bit scalar.
+        const rsrc_t r_phi = rsrc(phi);
+        const uint32_t sxy = (uint32_t)g.sxy;   // voxels per slice (<= kMaxPlane)
+        auto fetch_phi_fast = [&](int j) {
+            PhiRaw r;
+            const uint32_t so = (uint32_t)j * (sxy * 4u);
+#pragma unroll
+            for (int k = 0; k < NLD; ++k) r.v[k] = bld<float>(r_phi, loff[k], so);
+            return r;
+        };
         auto phi_slot = [&](int j) { return sphi[(j + 2 * NPHI) % NPHI]; };
         auto store_phi = [&](const PhiRaw &r, int j) {
             float *dst = phi_slot(j);
@@ -657,23 +668,47 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
             float cz;      // z edge factor of slice z
             IT img;        // FUSE: image of slice z
         };
-        auto stage = [&](int z) {
+        // Fast addressing, for tiles of at most 2^29 voxels (every field then
+        // lies within 4 GiB of its base): one descriptor per field, built
+        // once, and each slice's byte offset as a 32-bit scalar, instead of a
+        // 64-bit slice address and a descriptor per access.  The fast steps
+        // also need every slice they load in the volume (no clamp, no
+        // reflection): the march uses them for whole blocks away from the
+        // volume's far end.
+        const bool fast = (uint64_t)g.nz * (uint64_t)g.sxy <= ((uint64_t)1 << 29);
+        const rsrc_t r_t = rsrc(tp), r_ip = rsrc(ip), r_img = rsrc(imgp);
+        constexpr uint32_t kTB = sizeof(Vec2<ST>), kIB = sizeof(IRaw), kMB = sizeof(IT);
+        auto stage = [&](auto fastc, int z) {
+            constexpr bool F = decltype(fastc)::value;
             Stage st;
-            st.phi = fetch_phi(z + 3);
-            if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
-            st.I = iraw(min(z, zmax));
-            st.cz = PAPER ? 0.f : uniform_ld(czp, min(z, zmax));
-            // (RSF force: the image of slice z is already st.I)
-            if constexpr (FUSE && PAPER)
-                st.img = bld<IT>(rsrc(imgp + (int64_t)min(z, zmax) * g.sxy), col);
+            if constexpr (F) {
+                st.phi = fetch_phi_fast(z + 3);
+                if constexpr (!PAPER)
+                    st.t = bld<Vec2<ST>>(r_t, col, (uint32_t)(z + R) * (sxy * kTB));
+                st.I = bld<IRaw>(r_ip, col, (uint32_t)z * (sxy * kIB));
+                st.cz = PAPER ? 0.f : uniform_ld(czp, z);
+                if constexpr (FUSE && PAPER)
+                    st.img = bld<IT>(r_img, col, (uint32_t)z * (sxy * kMB));
+            } else {
+                st.phi = fetch_phi(z + 3);
+                if constexpr (!PAPER) st.t = pair_at(min(z + R, zmax));
+                st.I = iraw(min(z, zmax));
+                st.cz = PAPER ? 0.f : uniform_ld(czp, min(z, zmax));
+                // (RSF force: the image of slice z is already st.I)
+                if constexpr (FUSE && PAPER)
+                    st.img = bld<IT>(rsrc(imgp + (int64_t)min(z, zmax) * g.sxy), col);
+            }
             return st;
         };
-        Stage sa = stage(z0), sb{};
-        if constexpr (PF == 2) sb = stage(z0 + 1);
+        using Fast = std::true_type;
+        using Slow = std::false_type;
+        Stage sa = stage(Slow{}, z0), sb{};
+        if constexpr (PF == 2) sb = stage(Slow{}, z0 + 1);
         // FUSE: push (H I, H) of slice z (s its index in the unrolled block)
         // and write the stage-1 z Gaussian of slice z - R, taps in the order
         // of z_heaviside
-        auto emit = [&](const int s, const int z, float hi, float h) {
+        const rsrc_t r_tout = rsrc(tout);
+        auto emit = [&](auto fastc, const int s, const int z, float hi, float h) {
             if constexpr (FUSE) {
                 pin(hi);
                 pin(h);
@@ -682,8 +717,8 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 float acc_a = 0.f, acc_b = 0.f;
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
-                    acc_a = fmaf(t.w[k], ha[(s + k) % M], acc_a);
-                    acc_b = fmaf(t.w[k], hb[(s + k) % M], acc_b);
+                    acc_a = fmaf(tap<R>(t, k), ha[(s + k) % M], acc_a);
+                    acc_b = fmaf(tap<R>(t, k), hb[(s + k) % M], acc_b);
                 }
                 // 16-bit storage: opaque sums, so that the compiler cannot
                 // merge the last FMA with the conversion (one rounding to 16
@@ -692,13 +727,19 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                     pin(acc_a);
                     pin(acc_b);
                 }
-                if (z >= R && zt.active)
-                    bst_pair<ST>(rsrc(tout + (int64_t)(z - R) * g.sxy), col, acc_a, acc_b);
+                if (z >= R && zt.active) {
+                    if constexpr (decltype(fastc)::value)
+                        bst_pair<ST>(r_tout, col, acc_a, acc_b, (uint32_t)(z - R) * (sxy * kTB));
+                    else
+                        bst_pair<ST>(rsrc(tout + (int64_t)(z - R) * g.sxy), col, acc_a, acc_b);
+                }
             }
         };
         // step z (s = its index in the unrolled block) consumes stage `cur`
         // and refills it with the loads of step z + PF
-        auto step = [&](Stage &cur, const int s, const int z) {
+        const rsrc_t r_out = rsrc(phi_out);
+        auto step = [&](auto fastc, Stage &cur, const int s, const int z) {
+            constexpr bool F = decltype(fastc)::value;
             float Hs = 0.f, HIs = 0.f;   // FUSE: (H(phi'), H(phi') I) of slice z
             store_phi(cur.phi, z + 3);
             if constexpr (!PAPER) {
@@ -718,7 +759,7 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 if constexpr (PAPER) img_cur = cur.img;
                 else img_cur = I_cur;
             }
-            cur = stage(z + PF);
+            cur = stage(fastc, z + PF);
             __syncthreads();
             float nzpp, vzpp;
             q_phase(z + 2, nzpp, vzpp);
@@ -727,11 +768,11 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
                     if constexpr (PACK) {
-                        KG1 = fmaf(t.w[k], to_f(rv[(s + k) % M].x), KG1);
-                        KG2 = fmaf(t.w[k], to_f(rv[(s + k) % M].y), KG2);
+                        KG1 = fmaf(tap<R>(t, k), to_f(rv[(s + k) % M].x), KG1);
+                        KG2 = fmaf(tap<R>(t, k), to_f(rv[(s + k) % M].y), KG2);
                     } else {
-                        KG1 = fmaf(t.w[k], ra[(s + k) % M], KG1);
-                        KG2 = fmaf(t.w[k], rb[(s + k) % M], KG2);
+                        KG1 = fmaf(tap<R>(t, k), ra[(s + k) % M], KG1);
+                        KG2 = fmaf(tap<R>(t, k), rb[(s + k) % M], KG2);
                     }
                 }
             }
@@ -762,7 +803,8 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 const float delta = ua.eps_over_pi * rcp(ua.eps2 + cphi * cphi);
                 const float E = ua.mu * Rt + delta * (ua.nu * kappa - Fd);
                 const float nxt = cphi + ua.dt * E;
-                bst<float>(rsrc(phi_out + zo), col, nxt);
+                if constexpr (F) bst<float>(r_out, col, nxt, (uint32_t)z * (sxy * 4u));
+                else bst<float>(rsrc(phi_out + zo), col, nxt);
                 acc += fabs((double)nxt - (double)cphi);
                 if constexpr (FUSE) {
                     Hs = heaviside(nxt, ua.eps);
@@ -777,18 +819,50 @@ __global__ __launch_bounds__(kUThreads, 4) void z_update_kernel(Batch bt, Taps t
                 }
             }
             nzm = nz0; vzm = vz0; nz0 = nzp; vz0 = vzp; nzp = nzpp; vzp = vzpp;
-            if constexpr (FUSE) emit(s, z, HIs, Hs);
+            if constexpr (FUSE) emit(fastc, s, z, HIs, Hs);
         };
         const int zend = zt.z1 + (FUSE ? R : 0);
-        for (int zb = z0; zb < zend; zb += M) {
+        int zb = z0;
+        // Whole blocks of M steps inside the chunk run with no branch around
+        // the steps: a step under a branch ends at a join that copies the
+        // stage registers of the skipped path, and that copy waits for every
+        // load in flight, prefetches included.  They use fast addressing
+        // where the tile allows it and the registers are there (the fused
+        // RSF update, with two rings, spills with it), away from the volume's
+        // far end: step z loads up to slice z + PF + max(R, 3).
+        constexpr bool kFastAddr = !(FUSE && !PAPER);
+        constexpr int kAhead = PF + (R > 3 ? R : 3);
+        if constexpr (kFastAddr) {
+            if (fast) {
+                for (; zb + M <= zt.z1 && zb + M + kAhead <= g.nz; zb += M) {
+#pragma unroll
+                    for (int s = 0; s < M; ++s) {
+                        if (PF == 2 && (s & 1)) step(Fast{}, sb, s, zb + s);
+                        else step(Fast{}, sa, s, zb + s);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+        } else {
+            static_assert(PF == 1, "the fused RSF update runs one prefetch stage");
+            for (; zb + M <= zt.z1; zb += M) {
+#pragma unroll
+                for (int s = 0; s < M; ++s) {
+                    step(Slow{}, sa, s, zb + s);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        // the rest of the chunk, then (FUSE) the R steps of zero padding
+        for (; zb < zend; zb += M) {
 #pragma unroll
             for (int s = 0; s < M; ++s) {
                 const int z = zb + s;
                 if (z < zt.z1) {
-                    if (PF == 2 && (s & 1)) step(sb, s, z);
-                    else step(sa, s, z);
+                    if (PF == 2 && (s & 1)) step(Slow{}, sb, s, z);
+                    else step(Slow{}, sa, s, z);
                 } else if (FUSE && z < zend) {
-                    emit(s, z, 0.f, 0.f);   // past the volume: the zero padding
+                    emit(Slow{}, s, z, 0.f, 0.f);   // past the volume: the zero padding
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -903,7 +977,7 @@ hipError_t launch_z_update_fused_r(const Batch &b, int64_t blocks, const Taps &t
         hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, true, true>), dim3((unsigned)blocks),
                            dim3(kUThreads), 0, s, b, t, c);
     } else {
-        if constexpr (R > fuse_max_r_t<ST>) return hipErrorInvalidValue;
+        if constexpr (R > fuse_max_r_t<ST, IT>) return hipErrorInvalidValue;
         else
             hipLaunchKernelGGL((z_update_kernel<R, false, ST, IT, false, true>),
                                dim3((unsigned)blocks), dim3(kUThreads), 0, s, b, t, c);

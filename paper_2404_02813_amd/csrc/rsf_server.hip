@@ -359,7 +359,8 @@ bool launch_chunk(rsf_server *s, std::string &why)
         const Tile *gp = kv.second.front();
         const bool fuse = !s->cfg.separate_passes &&
                           (gp->req.params.force == RSF_FORCE_PAPER ||
-                           gp->R <= rsf::fuse_max_r(gp->req.params.storage));
+                           gp->R <= rsf::fuse_max_r(gp->req.params.storage,
+                                                    gp->req.volume_dtype));
         // splits from each tile's share of the group's running voxels
         double vox = 0.0;
         for (Tile *t : run) vox += (double)t->g.nx * t->g.ny * t->g.nz;

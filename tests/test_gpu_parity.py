@@ -482,14 +482,17 @@ def test_autotune_keeps_results(rsf):
 
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
 # alone fills the resident update workgroups (>= 384 columns of 64 x 8), or
-# tiles of at most 8 slices; with the RSF force only up to radius 10 (12 with
-# FP16 storage).
+# tiles of at most 8 slices; with the RSF force only up to radius 9 (8 with a
+# uint16 image, 12 with FP16 storage).
 RSF_FUSE_CASES = [  # (shape zyx, image, storage, sigma, iters, tol, fused)
     ((40, 770, 256), "f32", "f32", 3.0, 9, 0.0, True),
     ((8, 47, 29), "u16", "f16", 2.0, 12, 0.0, True),
     ((8, 40, 44), "f32", "bf16", 3.0, 6, 0.0, True),
     ((8, 34, 34), "f32", "f32", 3.0, 80, 2e-3, True),
     ((6, 21, 23), "f32", "f32", 1.0, 4, 0.0, True),
+    ((8, 30, 31), "f32", "f32", 3.2, 5, 0.0, False),   # R = 10: separate passes
+    ((8, 31, 30), "u16", "f32", 2.6, 6, 0.0, True),    # R = 8 fuses with a uint16 image
+    ((8, 31, 33), "u16", "f32", 3.0, 5, 0.0, False),   # R = 9, uint16 image: separate
     ((8, 30, 30), "f32", "f32", 3.4, 5, 0.0, False),   # R = 11: separate passes
     ((8, 38, 41), "u16", "f16", 4.0, 7, 0.0, True),    # R = 12 fuses with FP16 storage
     ((8, 36, 33), "u16", "bf16", 4.0, 5, 0.0, False),  # R = 12, BF16: separate passes
@@ -524,6 +527,69 @@ def test_fused_update_is_bitwise_the_separate_passes(rsf, shape, image, storage,
     assert torch.equal(a, b)
     assert run_a == run_b and last_a == last_b
     assert zh_a == iters and zh_b == (1 if fused else iters)
+
+
+# The update marches whole blocks of its unrolled steps without a branch (and
+# with one descriptor per field and 32-bit slice offsets where the tile
+# allows), and the rest of its z chunk with per-step checks.  Long z chunks
+# take the first form and short chunks only the second: each voxel's
+# arithmetic is the same in both, so phi must be bitwise equal whatever the
+# chunking, and both must meet the oracle's bar.
+UPDATE_CHUNK_CASES = [  # (shape zyx, image, storage, sigma, force, iters, fused)
+    ((72, 40, 44), "f32", "f32", 3.0, "rsf", 12, False),
+    ((70, 36, 66), "u16", "f16", 1.4, "rsf", 10, False),
+    ((66, 41, 38), "f32", "f32", 3.0, "paper", 10, False),
+    ((64, 40, 44), "f32", "f32", 3.0, "rsf", 10, True),
+    ((60, 37, 40), "u16", "f16", 4.0, "rsf", 8, True),
+]
+
+
+@pytest.mark.parametrize("shape,image,storage,sigma,force,iters,fused", UPDATE_CHUNK_CASES)
+def test_update_long_and_short_z_chunks_agree(rsf, shape, image, storage, sigma, force, iters,
+                                              fused):
+    mod, ctx = rsf
+    say(f"update z chunks {shape} {image}/{storage} sigma={sigma} {force} fused={fused}")
+    if image == "u16":
+        I = inputs.u16_phantom(shape, 6, 1.0, 3.0, 613)
+        vol = torch.from_numpy(I).cuda()
+        I_o = I.astype(np.float64) / 65535.0
+    else:
+        I = inputs.vessel_phantom(shape, 6, 1.0, 3.0, 613)
+        vol = dev(I)
+        I_o = I
+    phi0 = inputs.box_phi0(shape)
+    extra = {} if force == "rsf" else dict(force=mod.RSF_FORCE_PAPER)
+    p = mod.make_params(sigma, 1.0, 1.0, 0.001, 1.0, 0.1, 1.0, storage=storage, **extra)
+    runs = []
+    # whole-z update chunks (one update workgroup per column tile), then the
+    # shortest chunks the split allows; where the force and radius fuse, the
+    # whole-z run takes the fused update (small planes fuse only when their
+    # splits already march whole z chunks)
+    settings = [(fused, 1), (False, 1 << 20)]
+    for fuse, u_target in settings:
+        ctx.set_fusion(fuse)
+        ctx.set_split_targets(0, 0, u_target)
+        phi = dev(phi0)
+        ctx.profile(True)
+        ctx.evolve_ex(vol, phi, p, iters)
+        ctx.profile(False)
+        prof = ctx.profile_read()
+        _, run, _, hist = ctx.stats(cap=iters)
+        runs.append((phi, hist, prof["z_heaviside"][0]))
+    ctx.set_split_targets(0, 0, 0)
+    ctx.set_fusion(True)
+    torch.cuda.synchronize()
+    (a, ha, za), (b, hb, zb) = runs
+    assert torch.equal(a, b)
+    np.testing.assert_allclose(ha, hb, rtol=1e-12, atol=0.0)
+    if fused:
+        assert za == 1 and zb == iters
+    op = oracle.params_array(sigma, 1.0, 1.0, 0.001, 1.0, 0.1, 1.0, 1e-10,
+                             force=0 if force == "rsf" else 1)
+    want, _ = oracle.evolve(I_o, phi0, op, iters)
+    dmax, agree = parity(host(a), want)
+    say(f"  max|dphi|={dmax:.3e} agree={agree:.6f}")
+    assert dmax <= phi_tol(storage) and agree >= SIGN_AGREE
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
