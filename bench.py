@@ -821,7 +821,7 @@ def main() -> int:
     ap.add_argument("--iters", type=int, default=0,
                     help="override the workload's iteration count (profiling runs)")
     ap.add_argument("--requests", type=int, default=0, help="served workload: stream length")
-    ap.add_argument("--serve-sample", type=int, default=150,
+    ap.add_argument("--serve-sample", type=int, default=400,
                     help="served workload: requests timed for the saturated and FIFO rates")
     ap.add_argument("--chunk-iters", type=int, default=4, help="served workload: server chunk")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served workload: HBM budget")

@@ -47,6 +47,10 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
     // rows are written whole (128 entries, the tail past RW is never read)
     // so that staging has no branch
     __shared__ float row[2][NF][128];
+    // FP16 pairs are staged as they are loaded, both fields in one word, and
+    // converted by the x convolution's mixed-precision FMAs (exactly, as a
+    // conversion at staging would): half the LDS traffic, no conversions
+    constexpr bool PACKROW = NF == 2 && std::is_same<IN, _Float16>::value;
 
     Where wh;
     if (!locate(bt, wh)) return;
@@ -113,7 +117,10 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
             const int gx = x0 - R + j;
             const int keep = (yok && gx >= 0 && gx < g.nx) ? -1 : 0;
             auto masked = [&](float v) { return __int_as_float(__float_as_int(v) & keep); };
-            if (NF == 2) {
+            if constexpr (PACKROW) {
+                const uint32_t bits = __builtin_bit_cast(uint32_t, r.p[h]) & (uint32_t)keep;
+                row[slot][0][j] = __builtin_bit_cast(float, bits);
+            } else if (NF == 2) {
                 row[slot][0][j] = masked(to_f(r.p[h].x));
                 row[slot][NF - 1][j] = masked(to_f(r.p[h].y));
             } else {
@@ -129,8 +136,14 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
         float ca = 0.f, cb = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            ca = fmaf(tap<R>(t, k), row[slot][0][lane + k], ca);
-            if (NF == 2) cb = fmaf(tap<R>(t, k), row[slot][NF - 1][lane + k], cb);
+            if constexpr (PACKROW) {
+                const Vec2<_Float16> v = __builtin_bit_cast(Vec2<_Float16>, row[slot][0][lane + k]);
+                ca = fmaf(tap<R>(t, k), (float)v.x, ca);
+                cb = fmaf(tap<R>(t, k), (float)v.y, cb);
+            } else {
+                ca = fmaf(tap<R>(t, k), row[slot][0][lane + k], ca);
+                if (NF == 2) cb = fmaf(tap<R>(t, k), row[slot][NF - 1][lane + k], cb);
+            }
         }
         __asm__ volatile("" : "+v"(ca), "+v"(cb), "+v"(yv.x), "+v"(yv.y));
         return make_float2(ca, cb);
@@ -284,7 +297,18 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
             bst<ST>(rout, (uint32_t)xc, from_f<ST>(edge(acc_a)), row * (uint32_t)sizeof(ST));
         }
     };
-    for (int yb = y0; yb < y1; yb += M) {
+    // whole blocks of M steps with no branch around the steps (as in the
+    // update pass), then the rest of the chunk with a per-step check
+    int yb = y0;
+    for (; yb + M <= y1; yb += M) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            if (PF == 2 && (s & 1)) step(sb, s, yb + s);
+            else step(sa, s, yb + s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (; yb < y1; yb += M) {
 #pragma unroll
         for (int s = 0; s < M; ++s) {
             const int y = yb + s;

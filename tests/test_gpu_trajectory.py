@@ -8,8 +8,10 @@ oracle element by element (Sec. 2, Eq. 1 iterated; Sec. 3 final energy).
   times).  FP32, FP16 and BF16 storage against one oracle run.
 - The mixed-precision recipe (uint16 detector numbers, sigma = 4, R = 12,
   150 iterations) on a 128 x 256 x 256 volume, the largest the oracle runs in
-  about a minute: radius 12 runs the passes separately, as the
-  1024 x 1024 x 512 volume does.
+  about a minute, on the schedule the 1024 x 1024 x 512 volume runs: with
+  FP16 storage the fused update (its update workgroups set to whole z
+  columns, as the large plane gives them), with BF16 and FP32 storage the
+  separate passes (radius 12 does not fuse there).
 
 Each case prints max|dphi| inside and outside the band |phi_oracle| < 1, the
 Dice of phi > 0 and the sign agreement.
@@ -170,7 +172,15 @@ def test_mixed_precision_recipe_150_iterations(rsf, mixed, storage):
     say(f"uint16 recipe {MIXED}, sigma 4 x 150, {storage} storage")
     vol = torch.from_numpy(u).cuda()
     phi = torch.from_numpy(phi0).cuda()
+    fused = storage == "f16"
+    if fused:
+        ctx.set_split_targets(0, 0, 1)
+    ctx.profile(True)
     ctx.evolve_ex(vol, phi, mod.make_params(**p, storage=storage), 150)
+    ctx.profile(False)
+    stage1 = ctx.profile_read()["z_heaviside"][0]
+    ctx.set_split_targets(0, 0, 0)
     got = phi.cpu().numpy().astype(np.float64)
+    assert stage1 == (1 if fused else 150)
     r = report(got, want)
     assert r["max"] <= phi_tol(storage) and r["agree"] >= SIGN_AGREE
