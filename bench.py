@@ -163,9 +163,15 @@ def ingest_counters(fetch_dir: str, write_dir: str, workload: str, copy_bytes: i
 
     fetch, fcopy = load(fetch_dir, "FETCH_SIZE")
     write, wcopy = load(write_dir, "WRITE_SIZE")
-    # the copy of known size: its counters land nearest to copy_bytes / factor
-    f_fac = max(fcopy) / copy_bytes
-    w_fac = max(wcopy) / copy_bytes
+    # the copy of known size: the copy-bandwidth measurement runs it several
+    # times, while the other device copies (volume and phi clones) vary in
+    # size, so it is the median of the large copies
+    def typical(v):
+        big = sorted(x for x in v if x >= 0.1 * max(v))
+        return big[len(big) // 2]
+
+    f_fac = typical(fcopy) / copy_bytes
+    w_fac = typical(wcopy) / copy_bytes
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(path)) if os.path.exists(path) else {}
     sha = kernel_source_hash()
