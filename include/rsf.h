@@ -376,9 +376,8 @@ typedef struct {
  * the RSF force's radius ceil(3 sigma) is at most 12 with RSF_F16 storage, 9
  * with RSF_F32 or RSF_BF16 storage and an RSF_F32 image, 8 with a uint16
  * image (any radius for the Sec. 4.2 force); every tile's update then marches
- * its whole z extent.  Results are
- * bitwise the same either way; off runs the passes separately.  Affects later
- * rsf_evolve* calls on this context. */
+ * its whole z extent.  Results are bitwise the same either way; off runs the
+ * passes separately.  Affects later rsf_evolve* calls on this context. */
 rsf_status rsf_set_fusion(rsf_context *ctx, int on);
 
 /* Iterations replayed from a captured HIP graph (on != 0, the default): with
