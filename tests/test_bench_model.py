@@ -39,3 +39,41 @@ def test_roofline_prices_the_dominant_pass():
     assert r["avg_launch_ms"] == pytest.approx(0.7)
     assert r["achieved"] == pytest.approx(20 * 1_000_000 / 0.7e-3 / 1e9, rel=1e-3)
     assert r["traffic"] is None
+
+
+def _counter_csv(path, counter, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, kib) in enumerate(rows):
+            w.writerow([i + 1, name, counter, kib])
+
+
+def test_counter_calibration_takes_the_reference_copy(tmp_path, monkeypatch):
+    """The counters are scaled by what they read for the 1 GiB reference copy,
+    which the run repeats; a larger clone of phi (2 GiB here) in the same run
+    must not be taken for it."""
+    gib = 1 << 30
+    copy = "__amd_rocclr_copyBuffer"
+    update = "void rsf::(anonymous namespace)::z_update_kernel<9, false, float, float, false, true>"
+    fetch_dir, write_dir = tmp_path / "f", tmp_path / "w"
+    fetch_dir.mkdir()
+    write_dir.mkdir()
+    # FETCH_SIZE reads half the bytes a copy moves, WRITE_SIZE all of them
+    clone = [(copy, 2 * gib / 1024 * 0.5)]
+    ref = [(copy, gib / 1024 * 0.5)] * 5
+    _counter_csv(fetch_dir / "p_counter_collection.csv", "FETCH_SIZE",
+                 clone + ref + [(copy, 2.0), (update, 3000.0 * 0.5), (update, 3000.0 * 0.5)])
+    clone_w = [(copy, 2 * gib / 1024)]
+    ref_w = [(copy, gib / 1024)] * 5
+    _counter_csv(write_dir / "p_counter_collection.csv", "WRITE_SIZE",
+                 clone_w + ref_w + [(copy, 0.03125), (update, 1000.0), (update, 1000.0)])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "synthetic")
+    data = bench.ingest_counters(str(fetch_dir), str(write_dir), "synthetic", gib)
+    entry = data["z_update@synthetic"]
+    assert entry["fetch_factor"] == pytest.approx(0.5)
+    assert entry["write_factor"] == pytest.approx(1.0)
+    assert entry["bytes_per_launch"] == pytest.approx((3000.0 + 1000.0) * 1024, rel=1e-6)
+    assert (tmp_path / "profiles" / "traffic.json").exists()
