@@ -51,6 +51,11 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
     // converted by the x convolution's mixed-precision FMAs (exactly, as a
     // conversion at staging would): half the LDS traffic, no conversions
     constexpr bool PACKROW = NF == 2 && std::is_same<IN, _Float16>::value;
+    // Other pairs are staged interleaved, (a, b) per column, so one 64-bit
+    // LDS read serves a tap of both fields (and a 128-bit pair read two
+    // taps): half the LDS instructions of two separate rows, the same bytes.
+    constexpr bool PAIRROW = NF == 2 && !PACKROW;
+    __shared__ float2 rowp[2][PAIRROW ? 128 : 1];
 
     Where wh;
     if (!locate(bt, wh)) return;
@@ -120,6 +125,8 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
             if constexpr (PACKROW) {
                 const uint32_t bits = __builtin_bit_cast(uint32_t, r.p[h]) & (uint32_t)keep;
                 row[slot][0][j] = __builtin_bit_cast(float, bits);
+            } else if constexpr (PAIRROW) {
+                rowp[slot][j] = make_float2(masked(to_f(r.p[h].x)), masked(to_f(r.p[h].y)));
             } else if (NF == 2) {
                 row[slot][0][j] = masked(to_f(r.p[h].x));
                 row[slot][NF - 1][j] = masked(to_f(r.p[h].y));
@@ -140,6 +147,10 @@ void xy_kernel(Batch bt, Taps t, Coeffs c)
                 const Vec2<_Float16> v = __builtin_bit_cast(Vec2<_Float16>, row[slot][0][lane + k]);
                 ca = fmaf(tap<R>(t, k), (float)v.x, ca);
                 cb = fmaf(tap<R>(t, k), (float)v.y, cb);
+            } else if constexpr (PAIRROW) {
+                const float2 v = rowp[slot][lane + k];
+                ca = fmaf(tap<R>(t, k), v.x, ca);
+                cb = fmaf(tap<R>(t, k), v.y, cb);
             } else {
                 ca = fmaf(tap<R>(t, k), row[slot][0][lane + k], ca);
                 if (NF == 2) cb = fmaf(tap<R>(t, k), row[slot][NF - 1][lane + k], cb);
