@@ -356,8 +356,10 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
 {
     constexpr int W = 2 * R + 1;
     float ra[W], rb[W];
+    // every fetch is unconditional, with the slice clamped into the volume;
+    // `use` replaces a slice outside it by the zero padding
     using Raw = decltype(fetch(0));
-    auto get = [&](int z) { return (z >= 0 && z < nz) ? fetch(z) : Raw{}; };
+    auto get = [&](int z) { return fetch(min(max(z, 0), nz - 1)); };
     auto use = [&](const Raw &raw, int z) {
         float2 v = (z >= 0 && z < nz) ? cook(raw, z) : make_float2(0.f, 0.f);
         pin(v.x);
@@ -374,27 +376,38 @@ __device__ __forceinline__ void z_march(int nz, int z0, int z1, const Taps &t, F
         rb[j] = v.y;
         __builtin_amdgcn_sched_barrier(0);
     }
-    for (int zb = z0; zb < z1; zb += W) {
+    auto step = [&](const int s, const int z) {
+        const int zn = z + R;
+        const auto cur = nxt;
+        nxt = get(zn + 1);
+        const float2 v = use(cur, zn);
+        ra[(s + 2 * R) % W] = v.x;
+        rb[(s + 2 * R) % W] = v.y;
+        float acc_a = 0.f, acc_b = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            acc_a = fmaf(tap<R>(t, k), ra[(s + k) % W], acc_a);
+            if (NF == 2) acc_b = fmaf(tap<R>(t, k), rb[(s + k) % W], acc_b);
+        }
+        epi(z, acc_a, acc_b);
+    };
+    // Whole blocks of W steps run with no branch around the steps (a step
+    // under a branch ends at a join whose register copies wait for the
+    // prefetch); the rest of the chunk checks each step.  Each step's work
+    // stays inside the step; the one-step prefetch and occupancy hide the
+    // latency.
+    int zb = z0;
+    for (; zb + W <= z1; zb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
-            const int z = zb + s;
-            if (z < z1) {
-                const int zn = z + R;
-                const Raw cur = nxt;
-                nxt = get(zn + 1);
-                const float2 v = use(cur, zn);
-                ra[(s + 2 * R) % W] = v.x;
-                rb[(s + 2 * R) % W] = v.y;
-                float acc_a = 0.f, acc_b = 0.f;
+            step(s, zb + s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    for (; zb < z1; zb += W) {
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    acc_a = fmaf(tap<R>(t, k), ra[(s + k) % W], acc_a);
-                    if (NF == 2) acc_b = fmaf(tap<R>(t, k), rb[(s + k) % W], acc_b);
-                }
-                epi(z, acc_a, acc_b);
-            }
-            // keep each step's work inside the step; the one-step prefetch and
-            // occupancy hide the latency
+        for (int s = 0; s < W; ++s) {
+            if (zb + s < z1) step(s, zb + s);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
