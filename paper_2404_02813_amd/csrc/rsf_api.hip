@@ -1011,13 +1011,16 @@ rsf_status rsf_evolve_noalloc(rsf_context *ctx, const void *volume, int volume_d
         if (!params) return fail(ctx, RSF_ERR_INVALID_ARG, "null params");
         if (!ctx->noalloc_ws) return fail(ctx, RSF_ERR_DEVICE, "no-alloc workspace not found");
         rsf_tile t{volume, phi, nx, ny, nz};
-        // no per-pass events: creating them could allocate
-        const bool prof = ctx->prof;
+        // no per-pass events: creating them could allocate (restored on
+        // every exit, exceptions included)
+        struct ProfOff {
+            rsf_context *c;
+            bool was;
+            ~ProfOff() { c->prof = was; }
+        } off{ctx, ctx->prof};
         ctx->prof = false;
-        const rsf_status st = evolve_impl(ctx, &t, 1, volume_dtype, *params, iters, tol,
-                                          ctx->noalloc_ws, RSF_NOALLOC_MAX_BYTES, stream, true);
-        ctx->prof = prof;
-        return st;
+        return evolve_impl(ctx, &t, 1, volume_dtype, *params, iters, tol, ctx->noalloc_ws,
+                           RSF_NOALLOC_MAX_BYTES, stream, true);
     } catch (const std::bad_alloc &) {
         return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
