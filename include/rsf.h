@@ -279,13 +279,33 @@ rsf_status rsf_get_stats(rsf_context *ctx, rsf_stats *out, double *s_hist, int c
  * Every core must be at least 2 * curtain long (RSF_ERR_INVALID_ARG);
  * a sub-volume larger than the budget gives RSF_ERR_BUDGET.  Allocates an
  * FP32 merge buffer of the volume's size and the sub-volume copies for the
- * duration of the call; synchronises `stream`; phi is untouched on a
- * validation error.  Tolerance-based stopping and statistics are not
- * offered here. */
+ * duration of the call (rsf_evolve_volume_ex takes them from the caller);
+ * synchronises `stream`; phi is untouched on a validation error.
+ * Tolerance-based stopping and statistics are not offered here. */
 rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
                              int64_t nx, int64_t ny, int64_t nz, int64_t block, int64_t curtain,
                              const rsf_params *params, int iters, size_t budget_bytes,
                              void *stream);
+
+/* Device bytes rsf_evolve_volume_ex needs for these arguments on this
+ * context (its split targets size the batch workspace): the FP32 merge
+ * buffer, the sub-volume copies of the largest group and that group's batch
+ * workspace.  0 for invalid arguments. */
+size_t rsf_volume_workspace_bytes(rsf_context *ctx, int volume_dtype, int64_t nx, int64_t ny,
+                                  int64_t nz, int64_t block, int64_t curtain,
+                                  const rsf_params *params, int iters, size_t budget_bytes);
+
+/* rsf_evolve_volume with every device buffer in the caller's workspace
+ * (device, 256-byte aligned, at least rsf_volume_workspace_bytes(...) bytes;
+ * NULL allocates as rsf_evolve_volume does), so that the caller owns all the
+ * device memory the call uses.  RSF_ERR_INVALID_ARG for a workspace that is
+ * too small or misaligned, phi untouched.  The result is bitwise
+ * rsf_evolve_volume's. */
+rsf_status rsf_evolve_volume_ex(rsf_context *ctx, const void *volume, int volume_dtype,
+                                float *phi, int64_t nx, int64_t ny, int64_t nz, int64_t block,
+                                int64_t curtain, const rsf_params *params, int iters,
+                                size_t budget_bytes, void *workspace, size_t workspace_bytes,
+                                void *stream);
 
 /* ------------------------------------------------------------------------
  * Initialisation (Sec. 4.3): seed points from blob detection by the
@@ -322,10 +342,27 @@ rsf_status rsf_fast_sweep(rsf_context *ctx, float *u, int64_t nx, int64_t ny, in
  * distance as rsf_fast_sweep.  With offset 0 the seeds lie on the zero level
  * and the vessels around them grow into phi > 0 (the region H weights).
  * RSF_ERR_INVALID_ARG if no seed is found (phi untouched).  Synchronises
- * `stream`; allocates scratch for the call. */
+ * `stream`; allocates scratch for the call (rsf_init_phi_ex takes it from
+ * the caller). */
 rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
                         int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
                         float offset, int rounds, int64_t *n_seeds, void *stream);
+
+/* Device bytes of rsf_init_phi_ex's workspace for an nx*ny*nz volume: the
+ * seed mask (n bytes), the distance field and three smoothing / Hessian
+ * fields (4n bytes each) and two per-block reduction arrays, each piece
+ * rounded up to 256 bytes.  0 for invalid dimensions. */
+size_t rsf_init_workspace_bytes(int64_t nx, int64_t ny, int64_t nz);
+
+/* rsf_init_phi with its scratch in the caller's workspace (device, 256-byte
+ * aligned, at least rsf_init_workspace_bytes(nx, ny, nz) bytes; NULL
+ * allocates as rsf_init_phi does).  RSF_ERR_INVALID_ARG for a workspace that
+ * is too small or misaligned (phi untouched).  The result is bitwise
+ * rsf_init_phi's; calls that share one workspace must not overlap. */
+rsf_status rsf_init_phi_ex(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                           int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
+                           float offset, int rounds, int64_t *n_seeds, void *workspace,
+                           size_t workspace_bytes, void *stream);
 
 /* One zero-padded Gaussian convolution out = K * in (Sec. 3 kernel), the
  * separable passes the evolution uses.  in, out: device floats, distinct;

@@ -1225,106 +1225,173 @@ void rsf_autotune_reset(rsf_context *ctx)
     ctx->tuned_fuse.clear();
 }
 
-rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
-                             int64_t nx, int64_t ny, int64_t nz, int64_t block, int64_t curtain,
-                             const rsf_params *params, int iters, size_t budget_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// The volume driver's plan: curtained sub-volume boxes, their grouping
+// under the budget, and the device memory one call needs (merge buffer,
+// sub-volume copies of the largest group, batch workspace of the largest
+// group, in that order, each 256-byte aligned).
+struct VolPlan {
+    int C = 0;
+    std::vector<rsf::SubBox> boxes;
+    std::vector<std::pair<size_t, size_t>> groups;   // [first, last)
+    size_t acc_bytes = 0, copy_bytes = 0, ws_bytes = 0;
+    size_t total() const { return acc_bytes + copy_bytes + ws_bytes; }
+};
+
+rsf_status volume_plan(rsf_context *ctx, int volume_dtype, int64_t nx, int64_t ny, int64_t nz,
+                       int64_t block, int64_t curtain, const rsf_params &p, int iters,
+                       size_t budget_bytes, VolPlan &V)
+{
+    rsf_status st = check_dims(ctx, nx, ny, nz);
+    if (st != RSF_OK) return st;
+    st = check_params(ctx, p);
+    if (st != RSF_OK) return st;
+    st = check_types(ctx, p, volume_dtype);
+    if (st != RSF_OK) return st;
+    if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
+    if (block < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "block must be >= 1");
+    if (curtain < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "curtain must be >= 0");
+    V.C = (int)(curtain > 0 ? curtain : std::ceil(3.0 * std::max(p.sigma, p.sigma2) - 1e-9));
+    const int C = V.C;
+    // near-equal cores per axis; neighbours overlap by 2C around each core face
+    const int64_t n3[3] = {nx, ny, nz};
+    std::vector<int64_t> cuts[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t nb = (n3[a] + block - 1) / block;
+        for (int64_t k = 0; k <= nb; ++k) cuts[a].push_back(k * n3[a] / nb);
+        if (nb > 1 && n3[a] / nb < 2 * C)
+            return fail(ctx, RSF_ERR_INVALID_ARG,
+                        "every core must be at least twice the curtain: raise block or lower "
+                        "curtain");
+    }
+    for (size_t kz = 0; kz + 1 < cuts[2].size(); ++kz)
+        for (size_t ky = 0; ky + 1 < cuts[1].size(); ++ky)
+            for (size_t kx = 0; kx + 1 < cuts[0].size(); ++kx) {
+                rsf::SubBox b{};
+                const size_t k[3] = {kx, ky, kz};
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t c0 = cuts[a][k[a]], c1 = cuts[a][k[a] + 1];
+                    const int64_t lo = std::max<int64_t>(0, c0 - C);
+                    const int64_t hi = std::min<int64_t>(n3[a], c1 + C);
+                    b.lo[a] = (int)lo;
+                    b.ext[a] = (int)(hi - lo);
+                    b.core_lo[a] = (int)c0;
+                    b.core_hi[a] = (int)c1;
+                    b.nb_lo[a] = k[a] > 0;
+                    b.nb_hi[a] = k[a] + 2 < cuts[a].size();
+                }
+                V.boxes.push_back(b);
+            }
+    // group the boxes so each group's copies and workspace fit the budget
+    const size_t elem = volume_dtype == RSF_U16 ? 2 : 4;
+    auto copies_of = [&](const rsf::SubBox &b) {
+        const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
+        return align_up(v * elem) + align_up(v * 4);
+    };
+    auto box_bytes = [&](const rsf::SubBox &b) {
+        const Grid3 g = rsf::host::grid_of(b.ext[0], b.ext[1], b.ext[2]);
+        return copies_of(b) +
+               rsf::host::tile_regions(g, iters, p.storage, rsf::host::needs_k2(p)).total +
+               2 * kAlign;
+    };
+    size_t first = 0, sum = 0;
+    for (size_t i = 0; i < V.boxes.size(); ++i) {
+        const size_t bb = box_bytes(V.boxes[i]);
+        if (budget_bytes && bb > budget_bytes)
+            return fail(ctx, RSF_ERR_BUDGET, "one sub-volume alone exceeds the budget");
+        if (budget_bytes && sum + bb > budget_bytes) {
+            V.groups.push_back({first, i});
+            first = i;
+            sum = 0;
+        }
+        sum += bb;
+    }
+    V.groups.push_back({first, V.boxes.size()});
+    V.acc_bytes = align_up((size_t)(nx * ny * nz) * sizeof(float));
+    const int R = radius_of(p.sigma);
+    for (auto &gr : V.groups) {
+        size_t c = 0;
+        std::vector<rsf_tile> tiles;
+        for (size_t i = gr.first; i < gr.second; ++i) {
+            c += copies_of(V.boxes[i]);
+            const rsf::SubBox &b = V.boxes[i];
+            tiles.push_back(rsf_tile{nullptr, nullptr, b.ext[0], b.ext[1], b.ext[2]});
+        }
+        V.copy_bytes = std::max(V.copy_bytes, c);
+        // the batch workspace as evolve_impl sizes it for this context
+        const size_t need = plan_layout(tiles.data(), (int)tiles.size(), iters, p.storage,
+                                        splits_for(ctx, tiles.data(), (int)tiles.size(), R),
+                                        rsf::host::needs_k2(p))
+                                .total;
+        V.ws_bytes = std::max(V.ws_bytes, align_up(need));
+    }
+    return RSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rsf_volume_workspace_bytes(rsf_context *ctx, int volume_dtype, int64_t nx, int64_t ny,
+                                  int64_t nz, int64_t block, int64_t curtain,
+                                  const rsf_params *params, int iters, size_t budget_bytes)
+{
+    try {
+        if (!ctx || !params) return 0;
+        VolPlan V;
+        if (volume_plan(ctx, volume_dtype, nx, ny, nz, block, curtain, *params, iters,
+                        budget_bytes, V) != RSF_OK)
+            return 0;
+        return V.total();
+    } catch (...) {
+        return 0;
+    }
+}
+
+rsf_status rsf_evolve_volume_ex(rsf_context *ctx, const void *volume, int volume_dtype,
+                                float *phi, int64_t nx, int64_t ny, int64_t nz, int64_t block,
+                                int64_t curtain, const rsf_params *params, int iters,
+                                size_t budget_bytes, void *workspace, size_t workspace_bytes,
+                                void *stream)
 {
     std::vector<void *> owned;
     auto release = [&] {
-        for (void *p : owned) (void)hipFree(p);
+        for (void *q : owned) (void)hipFree(q);
         owned.clear();
     };
     try {
         if (!ctx) return RSF_ERR_INVALID_ARG;
         ctx->err.clear();
         if (!volume || !phi || !params) return fail(ctx, RSF_ERR_INVALID_ARG, "null argument");
-        rsf_status st = check_dims(ctx, nx, ny, nz);
+        VolPlan V;
+        rsf_status st = volume_plan(ctx, volume_dtype, nx, ny, nz, block, curtain, *params, iters,
+                                    budget_bytes, V);
         if (st != RSF_OK) return st;
-        st = check_params(ctx, *params);
-        if (st != RSF_OK) return st;
-        st = check_types(ctx, *params, volume_dtype);
-        if (st != RSF_OK) return st;
-        if (iters < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "iters must be >= 0");
-        if (block < 1) return fail(ctx, RSF_ERR_INVALID_ARG, "block must be >= 1");
-        if (curtain < 0) return fail(ctx, RSF_ERR_INVALID_ARG, "curtain must be >= 0");
-        const int C = (int)(curtain > 0 ? curtain
-                                         : std::ceil(3.0 * std::max(params->sigma, params->sigma2) -
-                                                     1e-9));
-        // near-equal cores per axis; neighbours overlap by 2C around each core face
-        const int64_t n3[3] = {nx, ny, nz};
-        std::vector<int64_t> cuts[3];
-        for (int a = 0; a < 3; ++a) {
-            const int64_t nb = (n3[a] + block - 1) / block;
-            for (int64_t k = 0; k <= nb; ++k) cuts[a].push_back(k * n3[a] / nb);
-            if (nb > 1 && n3[a] / nb < 2 * C)
-                return fail(ctx, RSF_ERR_INVALID_ARG,
-                            "every core must be at least twice the curtain: raise block or lower "
-                            "curtain");
-        }
-        std::vector<rsf::SubBox> boxes;
-        for (size_t kz = 0; kz + 1 < cuts[2].size(); ++kz)
-            for (size_t ky = 0; ky + 1 < cuts[1].size(); ++ky)
-                for (size_t kx = 0; kx + 1 < cuts[0].size(); ++kx) {
-                    rsf::SubBox b{};
-                    const size_t k[3] = {kx, ky, kz};
-                    for (int a = 0; a < 3; ++a) {
-                        const int64_t c0 = cuts[a][k[a]], c1 = cuts[a][k[a] + 1];
-                        const int64_t lo = std::max<int64_t>(0, c0 - C);
-                        const int64_t hi = std::min<int64_t>(n3[a], c1 + C);
-                        b.lo[a] = (int)lo;
-                        b.ext[a] = (int)(hi - lo);
-                        b.core_lo[a] = (int)c0;
-                        b.core_hi[a] = (int)c1;
-                        b.nb_lo[a] = k[a] > 0;
-                        b.nb_hi[a] = k[a] + 2 < cuts[a].size();
-                    }
-                    boxes.push_back(b);
-                }
-        // group the boxes so each group's copies and workspace fit the budget
-        const size_t elem = volume_dtype == RSF_U16 ? 2 : 4;
-        auto box_bytes = [&](const rsf::SubBox &b) {
-            const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
-            const Grid3 g = rsf::host::grid_of(b.ext[0], b.ext[1], b.ext[2]);
-            return align_up(v * elem) + align_up(v * 4) +
-                   rsf::host::tile_regions(g, iters, params->storage, rsf::host::needs_k2(*params))
-                       .total +
-                   2 * kAlign;
-        };
-        std::vector<std::pair<size_t, size_t>> groups;   // [first, last)
-        size_t first = 0, sum = 0, largest = 0;
-        for (size_t i = 0; i < boxes.size(); ++i) {
-            const size_t bb = box_bytes(boxes[i]);
-            if (budget_bytes && bb > budget_bytes)
-                return fail(ctx, RSF_ERR_BUDGET, "one sub-volume alone exceeds the budget");
-            if (budget_bytes && sum + bb > budget_bytes) {
-                groups.push_back({first, i});
-                first = i;
-                sum = 0;
-            }
-            sum += bb;
-            largest = std::max(largest, sum);
-        }
-        groups.push_back({first, boxes.size()});
+        if (workspace && workspace_bytes < V.total())
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
         st = set_device(ctx);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
+        const int C = V.C;
+        const size_t elem = volume_dtype == RSF_U16 ? 2 : 4;
         const int64_t nvox = nx * ny * nz;
         float *acc = nullptr;
-        HIP_TRY(hipMalloc(&acc, (size_t)nvox * sizeof(float)), "hipMalloc(merge accumulator)");
-        owned.push_back(acc);
-        // tile copies of the largest group (images then phis)
-        size_t copy_bytes = 0;
-        for (auto &gr : groups) {
-            size_t c = 0;
-            for (size_t i = gr.first; i < gr.second; ++i) {
-                const size_t v = (size_t)boxes[i].ext[0] * boxes[i].ext[1] * boxes[i].ext[2];
-                c += align_up(v * elem) + align_up(v * 4);
-            }
-            copy_bytes = std::max(copy_bytes, c);
-        }
         char *copies = nullptr;
-        {
-            const hipError_t e = hipMalloc(&copies, copy_bytes);
+        void *batch_ws = nullptr;   // null: the context's own workspace
+        if (workspace) {
+            char *w = static_cast<char *>(workspace);
+            acc = reinterpret_cast<float *>(w);
+            copies = w + V.acc_bytes;
+            batch_ws = w + V.acc_bytes + V.copy_bytes;
+        } else {
+            HIP_TRY(hipMalloc(&acc, (size_t)nvox * sizeof(float)), "hipMalloc(merge accumulator)");
+            owned.push_back(acc);
+            const hipError_t e = hipMalloc(&copies, V.copy_bytes);
             if (e != hipSuccess) {
                 release();
                 return hip_fail(ctx, e, "hipMalloc(sub-volume copies)");
@@ -1339,11 +1406,11 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
         };
         st = step(rsf::launch_fill(acc, nvox, 0.f, s), "fill");
         if (st != RSF_OK) return st;
-        for (auto &gr : groups) {
+        for (auto &gr : V.groups) {
             std::vector<rsf_tile> tiles;
             size_t off = 0;
             for (size_t i = gr.first; i < gr.second; ++i) {
-                const rsf::SubBox &b = boxes[i];
+                const rsf::SubBox &b = V.boxes[i];
                 const size_t v = (size_t)b.ext[0] * b.ext[1] * b.ext[2];
                 void *img = copies + off;
                 off += align_up(v * elem);
@@ -1355,14 +1422,14 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
                 tiles.push_back(rsf_tile{img, ph, b.ext[0], b.ext[1], b.ext[2]});
             }
             st = evolve_impl(ctx, tiles.data(), (int)tiles.size(), volume_dtype, *params, iters,
-                             0.0, nullptr, 0, stream);
+                             0.0, batch_ws, batch_ws ? V.ws_bytes : 0, stream);
             if (st != RSF_OK) {
                 (void)hipStreamSynchronize(s);
                 release();
                 return st;
             }
             for (size_t i = gr.first; i < gr.second; ++i) {
-                st = step(rsf::launch_merge(acc, tiles[i - gr.first].phi, nx, ny, boxes[i], C, s),
+                st = step(rsf::launch_merge(acc, tiles[i - gr.first].phi, nx, ny, V.boxes[i], C, s),
                           "merge");
                 if (st != RSF_OK) return st;
             }
@@ -1375,19 +1442,35 @@ rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dt
         ctx->has_last = false;   // per-tile statistics of the groups are not kept
         if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
         return RSF_OK;
+    } catch (const std::bad_alloc &) {
+        release();
+        return fail(ctx, RSF_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
         release();
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
 }
 
+rsf_status rsf_evolve_volume(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                             int64_t nx, int64_t ny, int64_t nz, int64_t block, int64_t curtain,
+                             const rsf_params *params, int iters, size_t budget_bytes, void *stream)
+{
+    return rsf_evolve_volume_ex(ctx, volume, volume_dtype, phi, nx, ny, nz, block, curtain,
+                                params, iters, budget_bytes, nullptr, 0, stream);
+}
+
 }  // extern "C"
 
 namespace {
 
-// Device scratch of one call, freed on every exit.
+// Device scratch of one call: allocated and freed on every exit, or carved
+// (256-byte aligned pieces) from a caller's workspace.
 struct Scratch {
     std::vector<void *> p;
+    char *arena = nullptr;
+    size_t left = 0;
+    Scratch() = default;
+    Scratch(void *base, size_t bytes) : arena(static_cast<char *>(base)), left(bytes) {}
     ~Scratch()
     {
         for (void *q : p) (void)hipFree(q);
@@ -1395,6 +1478,15 @@ struct Scratch {
     template <class T>
     hipError_t get(T **out, size_t bytes)
     {
+        *out = nullptr;
+        if (arena) {
+            const size_t b = align_up(bytes ? bytes : 1);
+            if (b > left) return hipErrorOutOfMemory;
+            *out = reinterpret_cast<T *>(arena);
+            arena += b;
+            left -= b;
+            return hipSuccess;
+        }
         void *q = nullptr;
         const hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
         if (e == hipSuccess) p.push_back(q);
@@ -1402,6 +1494,14 @@ struct Scratch {
         return e;
     }
 };
+
+// Device bytes of the initialisation's scratch (the pieces Scratch::get
+// takes in rsf_init_phi: mask, distance field, then those of seeds_impl).
+size_t init_scratch_bytes(int64_t n)
+{
+    return align_up((size_t)n) + align_up((size_t)n * 4) + 3 * align_up((size_t)n * 4) +
+           align_up(65536 * 4) + align_up(4) + align_up(65536 * 4);
+}
 
 rsf_status check_seed_args(rsf_context *ctx, const void *volume, int vdt, int64_t nx, int64_t ny,
                            int64_t nz, float sigma_b, float threshold)
@@ -1528,9 +1628,24 @@ rsf_status rsf_fast_sweep(rsf_context *ctx, float *u, int64_t nx, int64_t ny, in
     }
 }
 
+size_t rsf_init_workspace_bytes(int64_t nx, int64_t ny, int64_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nx > (int64_t(1) << 40) / ny / nz) return 0;
+    return init_scratch_bytes(nx * ny * nz);
+}
+
 rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
                         int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
                         float offset, int rounds, int64_t *n_seeds, void *stream)
+{
+    return rsf_init_phi_ex(ctx, volume, volume_dtype, phi, nx, ny, nz, sigma_b, threshold, offset,
+                           rounds, n_seeds, nullptr, 0, stream);
+}
+
+rsf_status rsf_init_phi_ex(rsf_context *ctx, const void *volume, int volume_dtype, float *phi,
+                           int64_t nx, int64_t ny, int64_t nz, float sigma_b, float threshold,
+                           float offset, int rounds, int64_t *n_seeds, void *workspace,
+                           size_t workspace_bytes, void *stream)
 {
     try {
         if (!ctx) return RSF_ERR_INVALID_ARG;
@@ -1540,11 +1655,15 @@ rsf_status rsf_init_phi(rsf_context *ctx, const void *volume, int volume_dtype, 
         if (!phi) return fail(ctx, RSF_ERR_INVALID_ARG, "null phi");
         if (!std::isfinite(offset)) return fail(ctx, RSF_ERR_INVALID_ARG, "offset must be finite");
         if (rounds < 1 || rounds > 64) return fail(ctx, RSF_ERR_INVALID_ARG, "rounds must be in 1..64");
+        const int64_t n = nx * ny * nz;
+        if (workspace && workspace_bytes < init_scratch_bytes(n))
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
         st = set_device(ctx);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const int64_t n = nx * ny * nz;
-        Scratch sc;
+        Scratch sc = workspace ? Scratch(workspace, workspace_bytes) : Scratch();
         unsigned char *mask = nullptr;
         float *u = nullptr;
         HIP_TRY(sc.get(&mask, (size_t)n), "hipMalloc(seed scratch)");

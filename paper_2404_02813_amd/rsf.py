@@ -43,7 +43,9 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_batch_workspace_bytes_params", "rsf_seeds", "rsf_fast_sweep", "rsf_init_phi", "rsf_set_fusion",
            "rsf_server_create", "rsf_server_submit", "rsf_server_poll", "rsf_server_wait",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
-           "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe")
+           "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe",
+           "rsf_volume_workspace_bytes", "rsf_evolve_volume_ex", "rsf_init_workspace_bytes",
+           "rsf_init_phi_ex")
 
 RSF_NOALLOC_MAX_BYTES = 128 << 20
 
@@ -179,6 +181,11 @@ def lib() -> ctypes.CDLL:
     L.rsf_fast_sweep.restype = i
     L.rsf_init_phi.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, i, i64p, vp]
     L.rsf_init_phi.restype = i
+    L.rsf_init_phi_ex.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, i, i64p, vp,
+                                  ctypes.c_size_t, vp]
+    L.rsf_init_phi_ex.restype = i
+    L.rsf_init_workspace_bytes.argtypes = [i64, i64, i64]
+    L.rsf_init_workspace_bytes.restype = ctypes.c_size_t
     L.rsf_workspace_bytes_params.argtypes = [i64, i64, i64, i, ctypes.POINTER(rsf_params)]
     L.rsf_workspace_bytes_params.restype = ctypes.c_size_t
     L.rsf_batch_workspace_bytes_params.argtypes = [ctypes.POINTER(rsf_tile), i, i,
@@ -187,6 +194,13 @@ def lib() -> ctypes.CDLL:
     L.rsf_evolve_volume.argtypes = [vp, vp, i, vp, i64, i64, i64, i64, i64,
                                     ctypes.POINTER(rsf_params), i, ctypes.c_size_t, vp]
     L.rsf_evolve_volume.restype = i
+    L.rsf_volume_workspace_bytes.argtypes = [vp, i, i64, i64, i64, i64, i64,
+                                             ctypes.POINTER(rsf_params), i, ctypes.c_size_t]
+    L.rsf_volume_workspace_bytes.restype = ctypes.c_size_t
+    L.rsf_evolve_volume_ex.argtypes = [vp, vp, i, vp, i64, i64, i64, i64, i64,
+                                       ctypes.POINTER(rsf_params), i, ctypes.c_size_t, vp,
+                                       ctypes.c_size_t, vp]
+    L.rsf_evolve_volume_ex.restype = i
     L.rsf_set_split_targets.argtypes = [vp, i64, i64, i64]
     L.rsf_set_split_targets.restype = i
     L.rsf_autotune_reset.argtypes = [vp]
@@ -433,34 +447,95 @@ def rsf_fast_sweep(ctx, u: torch.Tensor, rounds: int = 2, stream=None) -> None:
 
 
 def rsf_init_phi(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma_b: float, threshold: float,
-                 offset: float = 0.0, rounds: int = 2, stream=None) -> int:
-    """phi = offset - distance to the nearest seed; returns the seed count."""
+                 offset: float = 0.0, rounds: int = 2, stream=None,
+                 workspace: torch.Tensor = None) -> int:
+    """phi = offset - distance to the nearest seed; returns the seed count.
+    With `workspace` (a device tensor of at least rsf_init_workspace_bytes
+    bytes) the scratch is the caller's (rsf_init_phi_ex)."""
     _field(volume, "volume", "image")
     _field(phi, "phi")
     if volume.shape != phi.shape:
         raise ValueError("volume and phi must have the same shape")
     nz, ny, nx = phi.shape
     n = ctypes.c_int64(0)
-    _check(ctx, lib().rsf_init_phi(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
-                                   phi.data_ptr(), nx, ny, nz, float(sigma_b), float(threshold),
-                                   float(offset), int(rounds), ctypes.byref(n), _stream(stream)))
+    if workspace is None:
+        _check(ctx, lib().rsf_init_phi(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                       phi.data_ptr(), nx, ny, nz, float(sigma_b),
+                                       float(threshold), float(offset), int(rounds),
+                                       ctypes.byref(n), _stream(stream)))
+        return n.value
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(ctx, lib().rsf_init_phi_ex(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                      phi.data_ptr(), nx, ny, nz, float(sigma_b),
+                                      float(threshold), float(offset), int(rounds),
+                                      ctypes.byref(n), workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(),
+                                      _stream(stream)))
     return n.value
+
+
+def rsf_init_phi_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma_b: float,
+                    threshold: float, offset: float, rounds: int, workspace: torch.Tensor,
+                    stream=None) -> int:
+    """rsf_init_phi with its scratch in `workspace`."""
+    if workspace is None:
+        raise ValueError("rsf_init_phi_ex needs a workspace")
+    return rsf_init_phi(ctx, volume, phi, sigma_b, threshold, offset, rounds, stream, workspace)
+
+
+def rsf_init_workspace_bytes(shape) -> int:
+    """Device bytes rsf_init_phi_ex needs for a volume of shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    return int(lib().rsf_init_workspace_bytes(int(nx), int(ny), int(nz)))
 
 
 def rsf_evolve_volume(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
                       iters: int, block: int, curtain: int = 0, budget_bytes: int = 0,
-                      stream=None) -> None:
+                      stream=None, workspace: torch.Tensor = None) -> None:
     """Sub-volumes with curtains, evolved independently, merged by linear
-    interpolation (phi in place)."""
+    interpolation (phi in place); with `workspace` (a device tensor of at
+    least rsf_volume_workspace_bytes bytes) every device buffer is the
+    caller's (rsf_evolve_volume_ex)."""
     _field(volume, "volume", "image")
     _field(phi, "phi")
     if volume.shape != phi.shape:
         raise ValueError("volume and phi must have the same shape")
     nz, ny, nx = phi.shape
-    _check(ctx, lib().rsf_evolve_volume(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
-                                        phi.data_ptr(), nx, ny, nz, int(block), int(curtain),
-                                        ctypes.byref(params), int(iters), int(budget_bytes),
-                                        _stream(stream)))
+    if workspace is None:
+        _check(ctx, lib().rsf_evolve_volume(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                            phi.data_ptr(), nx, ny, nz, int(block), int(curtain),
+                                            ctypes.byref(params), int(iters), int(budget_bytes),
+                                            _stream(stream)))
+        return
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(ctx, lib().rsf_evolve_volume_ex(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype],
+                                           phi.data_ptr(), nx, ny, nz, int(block), int(curtain),
+                                           ctypes.byref(params), int(iters), int(budget_bytes),
+                                           workspace.data_ptr(),
+                                           workspace.numel() * workspace.element_size(),
+                                           _stream(stream)))
+
+
+def rsf_evolve_volume_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, params: rsf_params,
+                         iters: int, block: int, curtain: int, budget_bytes: int,
+                         workspace: torch.Tensor, stream=None) -> None:
+    """rsf_evolve_volume with every device buffer in `workspace`."""
+    if workspace is None:
+        raise ValueError("rsf_evolve_volume_ex needs a workspace")
+    rsf_evolve_volume(ctx, volume, phi, params, iters, block, curtain, budget_bytes, stream,
+                      workspace)
+
+
+def rsf_volume_workspace_bytes(ctx, volume_dtype, shape, params: rsf_params, iters: int,
+                               block: int, curtain: int = 0, budget_bytes: int = 0) -> int:
+    """Device bytes rsf_evolve_volume_ex needs (0 for invalid arguments);
+    volume_dtype is a torch dtype of the image, shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    return int(lib().rsf_volume_workspace_bytes(ctx, _IMAGE_DTYPES[volume_dtype], nx, ny, nz,
+                                                int(block), int(curtain), ctypes.byref(params),
+                                                int(iters), int(budget_bytes)))
 
 
 def rsf_set_split_targets(ctx, xy_waves: int = 0, z_blocks: int = 0, u_blocks: int = 0) -> None:
@@ -575,9 +650,14 @@ class Context:
         return rsf_autotune(self.handle, volumes, phis, params, trial_iters, stream)
 
     def evolve_volume(self, volume, phi, params, iters, block, curtain=0, budget_bytes=0,
-                      stream=None):
+                      stream=None, workspace=None):
         rsf_evolve_volume(self.handle, volume, phi, params, iters, block, curtain, budget_bytes,
-                          stream)
+                          stream, workspace)
+
+    def volume_workspace_bytes(self, volume_dtype, shape, params, iters, block, curtain=0,
+                               budget_bytes=0):
+        return rsf_volume_workspace_bytes(self.handle, volume_dtype, shape, params, iters, block,
+                                          curtain, budget_bytes)
 
     def set_graphs(self, on: bool) -> None:
         rsf_set_graphs(self.handle, on)
@@ -591,8 +671,10 @@ class Context:
     def fast_sweep(self, u, rounds=2, stream=None):
         rsf_fast_sweep(self.handle, u, rounds, stream)
 
-    def init_phi(self, volume, phi, sigma_b, threshold, offset=0.0, rounds=2, stream=None):
-        return rsf_init_phi(self.handle, volume, phi, sigma_b, threshold, offset, rounds, stream)
+    def init_phi(self, volume, phi, sigma_b, threshold, offset=0.0, rounds=2, stream=None,
+                 workspace=None):
+        return rsf_init_phi(self.handle, volume, phi, sigma_b, threshold, offset, rounds, stream,
+                            workspace)
 
     def set_split_targets(self, xy_waves=0, z_blocks=0, u_blocks=0):
         rsf_set_split_targets(self.handle, xy_waves, z_blocks, u_blocks)

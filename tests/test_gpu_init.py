@@ -172,3 +172,36 @@ def test_init_rejects_bad_arguments(rsf):
         ctx.fast_sweep(phi, 0)
     torch.cuda.synchronize()
     assert torch.all(phi == 7.0)
+
+
+def test_init_phi_caller_workspace_is_bitwise_the_same(rsf):
+    """rsf_init_phi_ex on a reused caller workspace (second call on a smaller
+    volume, the workspace holding the first call's fields) equals
+    rsf_init_phi; a workspace one byte short is refused with phi untouched."""
+    mod, ctx = rsf
+    say("init phi: caller workspace")
+    need = mod.rsf_init_workspace_bytes((16, 52, 60))
+    n = 16 * 52 * 60
+    assert need >= n + 4 * 4 * n + 2 * 65536 * 4
+    big = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    ws = big[:need]
+    for shape, seed in [((16, 52, 60), 44), ((9, 30, 34), 45)]:
+        vol, _ = volume("f32", shape, seed)
+        want = torch.empty(shape, dtype=torch.float32, device="cuda")
+        got = torch.full(shape, 3.0, dtype=torch.float32, device="cuda")
+        k0 = ctx.init_phi(vol, want, 2.0, 0.05, 1.0, 2)
+        k1 = mod.rsf_init_phi_ex(ctx.handle, vol, got, 2.0, 0.05, 1.0, 2, ws)
+        torch.cuda.synchronize()
+        assert k0 == k1 and k0 > 0
+        assert torch.equal(got, want)
+    vol, _ = volume("f32", (16, 52, 60), 46)
+    phi = torch.full((16, 52, 60), 7.0, device="cuda")
+    with pytest.raises(mod.RsfError) as e:
+        mod.rsf_init_phi_ex(ctx.handle, vol, phi, 2.0, 0.05, 1.0, 2, ws[:need - 1])
+    assert e.value.status == mod.RSF_ERR_INVALID_ARG
+    with pytest.raises(mod.RsfError) as e:       # misaligned
+        mod.rsf_init_phi_ex(ctx.handle, vol, phi, 2.0, 0.05, 1.0, 2, big[1:need + 1])
+    assert e.value.status == mod.RSF_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(phi == 7.0)
+    assert mod.rsf_init_workspace_bytes((0, 4, 4)) == 0

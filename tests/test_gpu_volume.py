@@ -131,3 +131,30 @@ def test_volume_driver_rejects_bad_geometry(rsf):
     assert e.value.status == mod.RSF_ERR_BUDGET
     torch.cuda.synchronize()
     assert torch.equal(phi, before)
+
+
+def test_volume_driver_caller_workspace_is_bitwise_the_same(rsf):
+    """rsf_evolve_volume_ex with every device buffer in a caller-owned
+    workspace: bitwise the result of the driver's own allocations, for one
+    group and for several groups under a budget; a workspace one byte short
+    is refused with phi untouched."""
+    mod, ctx = rsf
+    I, phi0 = case((40, 44, 50), seed=95)
+    vol = dev(I)
+    p = mod.make_params(**P)
+    for budget in (0, 3 << 20):
+        say(f"volume driver, caller workspace, budget {budget}")
+        ref = dev(phi0)
+        ctx.evolve_volume(vol, ref, p, 6, 18, 3, budget_bytes=budget)
+        need = ctx.volume_workspace_bytes(torch.float32, I.shape, p, 6, 18, 3, budget)
+        assert need > 0
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        got = dev(phi0)
+        ctx.evolve_volume(vol, got, p, 6, 18, 3, budget_bytes=budget, workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        short = dev(phi0)
+        with pytest.raises(mod.RsfError) as e:
+            ctx.evolve_volume(vol, short, p, 6, 18, 3, budget_bytes=budget, workspace=ws[:need - 1])
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
+        assert torch.equal(short, dev(phi0))
