@@ -444,6 +444,20 @@ rsf_status rsf_profile_enable(rsf_context *ctx, int on);
 /* Wait for the recorded launches, return their totals and clear them. */
 rsf_status rsf_profile_read(rsf_context *ctx, rsf_profile *out);
 
+/* Injected allocation failures, for tests of the error paths.  spec
+ * "alloc_fail:N" or "alloc_fail:N:K" (N, K >= 1, K = 1 if omitted): from
+ * this call on, the library counts every device and pinned host allocation
+ * it attempts (all contexts and servers of the process), and attempts
+ * N .. N+K-1 fail as out of memory (RSF_ERR_OUT_OF_MEMORY from the call that
+ * made them) without allocating.  NULL, "" or "off" disarms.  The same spec
+ * in the environment variable RSF_FAULT arms it when the library is loaded;
+ * a malformed RSF_FAULT makes rsf_create return RSF_ERR_INVALID_ARG.
+ * RSF_ERR_INVALID_ARG for a malformed spec (the current state is kept). */
+rsf_status rsf_set_fault(const char *spec);
+
+/* Allocation attempts counted since the fault was armed; -1 when disarmed. */
+int64_t rsf_fault_allocations(void);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of independent tiles.
  *

@@ -5,8 +5,10 @@
 
 #include <algorithm>
 #include <array>
+#include <cerrno>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <map>
@@ -16,6 +18,7 @@
 #include <vector>
 
 #include "rsf.h"
+#include "rsf_fault.hpp"
 #include "rsf_host.hpp"
 #include "rsf_internal.hpp"
 
@@ -69,6 +72,66 @@ hipError_t scratch_address(int device, void **out)
 }
 
 }  // namespace
+
+namespace rsf {
+namespace {
+
+// The armed fault: attempts first .. first + count - 1 fail; first 0 when
+// disarmed.  Guarded by g_fault_mu (a server's worker thread allocates too).
+std::mutex g_fault_mu;
+int64_t g_fault_first = 0, g_fault_count = 0, g_fault_seen = 0;
+bool g_fault_env_bad = false;
+
+// "alloc_fail:N" or "alloc_fail:N:K" with N, K >= 1; NULL, "" or "off"
+// disarms (first = 0).
+bool parse_fault(const char *spec, int64_t &first, int64_t &count)
+{
+    first = count = 0;
+    if (!spec || !*spec || std::strcmp(spec, "off") == 0) return true;
+    static const char kPrefix[] = "alloc_fail:";
+    if (std::strncmp(spec, kPrefix, sizeof(kPrefix) - 1) != 0) return false;
+    const char *p = spec + sizeof(kPrefix) - 1;
+    char *end = nullptr;
+    errno = 0;
+    const long long n = std::strtoll(p, &end, 10);
+    if (end == p || errno || n < 1) return false;
+    long long k = 1;
+    if (*end == ':') {
+        p = end + 1;
+        k = std::strtoll(p, &end, 10);
+        if (end == p || errno || k < 1) return false;
+    }
+    if (*end != '\0') return false;
+    first = n;
+    count = k;
+    return true;
+}
+
+// RSF_FAULT is read once, when the library is loaded; a malformed value arms
+// nothing and makes rsf_create refuse.
+struct FaultFromEnv {
+    FaultFromEnv()
+    {
+        const char *spec = std::getenv("RSF_FAULT");
+        if (!parse_fault(spec, g_fault_first, g_fault_count)) {
+            g_fault_env_bad = true;
+            std::fprintf(stderr, "librsf: malformed RSF_FAULT=%s (expected alloc_fail:N[:K])\n",
+                         spec);
+        }
+    }
+} g_fault_from_env;
+
+}  // namespace
+
+bool fault_take_alloc()
+{
+    std::lock_guard<std::mutex> lock(g_fault_mu);
+    if (g_fault_first == 0) return false;
+    const int64_t k = ++g_fault_seen;
+    return k >= g_fault_first && k - g_fault_first < g_fault_count;
+}
+
+}  // namespace rsf
 
 struct rsf_context {
     int device = 0;
@@ -268,7 +331,7 @@ rsf_status ensure_ws(rsf_context *ctx, size_t bytes)
         ctx->has_last = false;   // its statistics lived in the freed buffer
     }
     void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, bytes), "hipMalloc(workspace)");
+    HIP_TRY(rsf::dev_alloc(&p, bytes), "hipMalloc(workspace)");
     ctx->ws = p;
     ctx->ws_bytes = bytes;
     return RSF_OK;
@@ -309,7 +372,7 @@ rsf_status ensure_stage(rsf_context *ctx, size_t bytes)
     if (ctx->stage) HIP_TRY(hipHostFree(ctx->stage), "hipHostFree");
     ctx->stage = nullptr;
     ctx->stage_bytes = 0;
-    HIP_TRY(hipHostMalloc(&ctx->stage, bytes, hipHostMallocDefault), "hipHostMalloc(stage)");
+    HIP_TRY(rsf::pinned_alloc(&ctx->stage, bytes), "hipHostMalloc(stage)");
     ctx->stage_bytes = bytes;
     return RSF_OK;
 }
@@ -833,6 +896,7 @@ rsf_status rsf_create(rsf_context **out, int device_ordinal)
 {
     if (!out) return RSF_ERR_INVALID_ARG;
     *out = nullptr;
+    if (rsf::g_fault_env_bad) return RSF_ERR_INVALID_ARG;
     try {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device_ordinal < 0 || device_ordinal >= n)
@@ -848,6 +912,23 @@ rsf_status rsf_create(rsf_context **out, int device_ordinal)
     } catch (...) {
         return RSF_ERR_INTERNAL;
     }
+}
+
+rsf_status rsf_set_fault(const char *spec)
+{
+    int64_t first = 0, count = 0;
+    if (!rsf::parse_fault(spec, first, count)) return RSF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(rsf::g_fault_mu);
+    rsf::g_fault_first = first;
+    rsf::g_fault_count = count;
+    rsf::g_fault_seen = 0;
+    return RSF_OK;
+}
+
+int64_t rsf_fault_allocations(void)
+{
+    std::lock_guard<std::mutex> lock(rsf::g_fault_mu);
+    return rsf::g_fault_first == 0 ? -1 : rsf::g_fault_seen;
 }
 
 void rsf_destroy(rsf_context *ctx)
@@ -1102,7 +1183,7 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
             off.push_back(total);
             total += align_up((size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float));
         }
-        HIP_TRY(hipMalloc(&trial_phi, total), "hipMalloc(autotune trial_phi)");
+        HIP_TRY(rsf::dev_alloc(&trial_phi, total), "hipMalloc(autotune trial_phi)");
         std::vector<rsf_tile> tt(tiles, tiles + n_tiles);
         for (int t = 0; t < n_tiles; ++t) {
             tt[t].phi = reinterpret_cast<float *>(reinterpret_cast<char *>(trial_phi) + off[t]);
@@ -1389,9 +1470,9 @@ rsf_status rsf_evolve_volume_ex(rsf_context *ctx, const void *volume, int volume
             copies = w + V.acc_bytes;
             batch_ws = w + V.acc_bytes + V.copy_bytes;
         } else {
-            HIP_TRY(hipMalloc(&acc, (size_t)nvox * sizeof(float)), "hipMalloc(merge accumulator)");
+            HIP_TRY(rsf::dev_alloc(&acc, (size_t)nvox * sizeof(float)), "hipMalloc(merge accumulator)");
             owned.push_back(acc);
-            const hipError_t e = hipMalloc(&copies, V.copy_bytes);
+            const hipError_t e = rsf::dev_alloc(&copies, V.copy_bytes);
             if (e != hipSuccess) {
                 release();
                 return hip_fail(ctx, e, "hipMalloc(sub-volume copies)");
@@ -1488,7 +1569,7 @@ struct Scratch {
             return hipSuccess;
         }
         void *q = nullptr;
-        const hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+        const hipError_t e = rsf::dev_alloc(&q, bytes ? bytes : 1);
         if (e == hipSuccess) p.push_back(q);
         *out = static_cast<T *>(q);
         return e;

@@ -34,6 +34,7 @@
 
 #include "rsf.h"
 #include "rsf_arena.hpp"
+#include "rsf_fault.hpp"
 #include "rsf_host.hpp"
 #include "rsf_internal.hpp"
 
@@ -220,7 +221,7 @@ bool admit(rsf_server *s)
                 std::string grow_err;
                 const bool ok = s->arena.alloc(head.ws_bytes, b, [&](size_t len) {
                     void *p = nullptr;
-                    const hipError_t e = hipMalloc(&p, len);
+                    const hipError_t e = rsf::dev_alloc(&p, len);
                     if (e != hipSuccess) {
                         grow_err = hipGetErrorString(e);
                         return false;
@@ -731,14 +732,14 @@ rsf_status rsf_server_create(rsf_server **out, const rsf_server_config *cfg)
         for (hipStream_t &gs : s->gstream)
             if (bad(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking))) return RSF_ERR_DEVICE;
         const size_t fbytes = (size_t)s->cfg.max_resident * kSlotBytes;
-        if (bad(hipMalloc(&s->flags_dev, fbytes))) return RSF_ERR_OUT_OF_MEMORY;
+        if (bad(rsf::dev_alloc(&s->flags_dev, fbytes))) return RSF_ERR_OUT_OF_MEMORY;
         if (bad(hipMemset(s->flags_dev, 0, fbytes))) return RSF_ERR_DEVICE;
         const size_t tbytes = table_capacity(s->cfg.max_resident);
         for (RingEntry &re : s->ring) {
             re.bytes = tbytes;
-            if (bad(hipHostMalloc(&re.stage, tbytes, hipHostMallocDefault)) ||
-                bad(hipHostMalloc(&re.flags_host, fbytes, hipHostMallocDefault)) ||
-                bad(hipMalloc(&re.table, tbytes)) ||
+            if (bad(rsf::pinned_alloc(&re.stage, tbytes)) ||
+                bad(rsf::pinned_alloc(&re.flags_host, fbytes)) ||
+                bad(rsf::dev_alloc(&re.table, tbytes)) ||
                 bad(hipEventCreateWithFlags(&re.ev, hipEventDisableTiming)) ||
                 bad(hipEventCreateWithFlags(&re.up_ev, hipEventDisableTiming)))
                 return RSF_ERR_OUT_OF_MEMORY;

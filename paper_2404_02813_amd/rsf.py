@@ -45,7 +45,7 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe",
            "rsf_volume_workspace_bytes", "rsf_evolve_volume_ex", "rsf_init_workspace_bytes",
-           "rsf_init_phi_ex")
+           "rsf_init_phi_ex", "rsf_set_fault", "rsf_fault_allocations")
 
 RSF_NOALLOC_MAX_BYTES = 128 << 20
 
@@ -186,6 +186,10 @@ def lib() -> ctypes.CDLL:
     L.rsf_init_phi_ex.restype = i
     L.rsf_init_workspace_bytes.argtypes = [i64, i64, i64]
     L.rsf_init_workspace_bytes.restype = ctypes.c_size_t
+    L.rsf_set_fault.argtypes = [ctypes.c_char_p]
+    L.rsf_set_fault.restype = i
+    L.rsf_fault_allocations.argtypes = []
+    L.rsf_fault_allocations.restype = ctypes.c_int64
     L.rsf_workspace_bytes_params.argtypes = [i64, i64, i64, i, ctypes.POINTER(rsf_params)]
     L.rsf_workspace_bytes_params.restype = ctypes.c_size_t
     L.rsf_batch_workspace_bytes_params.argtypes = [ctypes.POINTER(rsf_tile), i, i,
@@ -482,6 +486,19 @@ def rsf_init_phi_ex(ctx, volume: torch.Tensor, phi: torch.Tensor, sigma_b: float
     if workspace is None:
         raise ValueError("rsf_init_phi_ex needs a workspace")
     return rsf_init_phi(ctx, volume, phi, sigma_b, threshold, offset, rounds, stream, workspace)
+
+
+def rsf_set_fault(spec) -> None:
+    """Arm ("alloc_fail:N" or "alloc_fail:N:K") or disarm (None, "", "off")
+    injected allocation failures, process-wide."""
+    st = lib().rsf_set_fault(None if spec is None else str(spec).encode())
+    if st != RSF_OK:
+        raise RsfError(st, f"malformed fault spec {spec!r}")
+
+
+def rsf_fault_allocations() -> int:
+    """Allocation attempts counted since the fault was armed; -1 if disarmed."""
+    return int(lib().rsf_fault_allocations())
 
 
 def rsf_init_workspace_bytes(shape) -> int:
