@@ -503,3 +503,52 @@ def test_paper_force_constant_image_and_reversal():
     a, _, _ = oracle.step(I, phi, PP(0.0, sigma=1.5))
     b, _, _ = oracle.step(1.0 - I, phi, PP(0.0, sigma=1.5))
     assert np.max(np.abs(a - b)) < 1e-12
+
+
+# --- The iterated map (Eq. 1 stepped, Sec. 2-3) -------------------------------
+
+def _shrinking_ball(s, eps0=2.0, T0=6.4, dt=0.1, n0=32, r0=8.0):
+    """Oracle trajectory of phi0 = r - |x - c| under curvature flow alone,
+    and the trajectory the continuum equations give it.
+
+    With a constant image both fits equal the image, so e1 = e2 = 0 and
+    F_d = 0 (Sec. 3); with mu = 0 the update is E = nu delta(phi) kappa.  For
+    any profile phi = f(rho, t) decreasing in rho, the unit normal is -rho_hat
+    and kappa = div n = -2 / rho exactly, whatever f is: each voxel then
+    follows its own scalar ODE f' = -nu delta(f) 2 / rho, stepped here with
+    the same explicit Euler step (Eq. 1).  The spatial grid is the only
+    difference between the two, so the gap is the O(h^2) error of the
+    central-difference curvature.  Scaling lengths, phi and eps by s and time
+    by s^3 leaves the continuum problem unchanged (in coarse units)."""
+    n, r, eps, T = n0 * s, r0 * s, eps0 * s, T0 * s ** 3
+    iters = int(round(T / dt))
+    c = (n - 1) / 2.0
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    rho = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    phi0 = r - rho
+    I = np.full((n, n, n), 0.5)
+    got, hist = oracle.evolve(I, phi0, P(sigma=1.0, nu=1.0, mu=0.0, dt=dt, eps=eps), iters)
+    f = phi0.copy()
+    for _ in range(iters):
+        f = f + dt * (eps / math.pi) / (eps * eps + f * f) * (-2.0 / rho)
+    shell = np.abs(rho - r) <= 3 * s
+    gap = np.abs(got - f)[shell] / s            # coarse-grid units
+    moved = np.abs(f - phi0)[shell].max() / s
+    return gap, moved, got, f, hist, rho, r
+
+
+def test_trajectory_converges_to_the_radial_curvature_flow():
+    """Pins the iterated map: the ball's phi follows the per-voxel ODE of the
+    continuum flow, with a gap that shrinks at second order when the grid is
+    refined (observed max-ratio 2.98, RMS-ratio 3.82).  A wrong sign, a
+    dropped or doubled delta, a wrong time step or an iterate read from the
+    wrong buffer changes phi by O(1) of the displacement at every grid."""
+    g1, moved1, got, f, hist, rho, r = _shrinking_ball(1)
+    assert 0.2 < moved1 < 0.3                    # the front really moves (~0.26 voxel)
+    assert g1.max() <= 0.02 * moved1             # 0.0042 observed
+    g2, moved2, *_ = _shrinking_ball(2)
+    assert abs(moved2 - moved1) <= 1e-3          # the same continuum motion
+    assert g1.max() / g2.max() >= 2.5
+    assert math.sqrt((g1 ** 2).mean() / (g2 ** 2).mean()) >= 3.2
+    # every iterate moves phi (kappa < 0 and delta > 0 on the shell): s_n > 0
+    assert np.all(hist > 0)
