@@ -322,10 +322,27 @@ rsf_status rsf_evolve_volume_ex(rsf_context *ctx, const void *volume, int volume
  * is a maximum of the 3x3 in-slice neighbourhood (strictly above the
  * neighbours earlier in raster order, at least the later ones).  *n_seeds
  * (host, may be NULL) receives the count; synchronises `stream`.  volume:
- * RSF_F32 or RSF_U16.  Allocates scratch for the call. */
+ * RSF_F32 or RSF_U16.  Allocates scratch for the call (rsf_seeds_ex takes it
+ * from the caller). */
 rsf_status rsf_seeds(rsf_context *ctx, const void *volume, int volume_dtype, int64_t nx,
                      int64_t ny, int64_t nz, float sigma_b, float threshold, unsigned char *mask,
                      int64_t *n_seeds, void *stream);
+
+/* Device bytes of rsf_seeds_ex's workspace for an nx*ny*nz volume: the
+ * distance field and three smoothing / Hessian fields (4n bytes each) and
+ * two per-block reduction arrays, each piece rounded up to 256 bytes.  0 for
+ * invalid dimensions. */
+size_t rsf_seeds_workspace_bytes(int64_t nx, int64_t ny, int64_t nz);
+
+/* rsf_seeds with its scratch in the caller's workspace (device, 256-byte
+ * aligned, at least rsf_seeds_workspace_bytes(nx, ny, nz) bytes; NULL
+ * allocates as rsf_seeds does).  RSF_ERR_INVALID_ARG for a workspace that is
+ * too small or misaligned (mask untouched).  The result is bitwise
+ * rsf_seeds's; calls that share one workspace must not overlap. */
+rsf_status rsf_seeds_ex(rsf_context *ctx, const void *volume, int volume_dtype, int64_t nx,
+                        int64_t ny, int64_t nz, float sigma_b, float threshold,
+                        unsigned char *mask, int64_t *n_seeds, void *workspace,
+                        size_t workspace_bytes, void *stream);
 
 /* Fast sweeping (Zhao 2005) in place: u (device floats) holds 0 at the
  * seeds and a large value (1e30) elsewhere; `rounds` repetitions of the

@@ -1576,13 +1576,16 @@ struct Scratch {
     }
 };
 
-// Device bytes of the initialisation's scratch (the pieces Scratch::get
-// takes in rsf_init_phi: mask, distance field, then those of seeds_impl).
-size_t init_scratch_bytes(int64_t n)
+// Device bytes of the seed detection's scratch (the pieces Scratch::get
+// takes in rsf_seeds: the distance field, then those of seeds_impl), and of
+// the initialisation's (rsf_init_phi: the mask first).
+size_t seeds_scratch_bytes(int64_t n)
 {
-    return align_up((size_t)n) + align_up((size_t)n * 4) + 3 * align_up((size_t)n * 4) +
-           align_up(65536 * 4) + align_up(4) + align_up(65536 * 4);
+    return align_up((size_t)n * 4) + 3 * align_up((size_t)n * 4) + align_up(65536 * 4) +
+           align_up(4) + align_up(65536 * 4);
 }
+
+size_t init_scratch_bytes(int64_t n) { return align_up((size_t)n) + seeds_scratch_bytes(n); }
 
 rsf_status check_seed_args(rsf_context *ctx, const void *volume, int vdt, int64_t nx, int64_t ny,
                            int64_t nz, float sigma_b, float threshold)
@@ -1669,16 +1672,35 @@ rsf_status rsf_seeds(rsf_context *ctx, const void *volume, int volume_dtype, int
                      int64_t ny, int64_t nz, float sigma_b, float threshold, unsigned char *mask,
                      int64_t *n_seeds, void *stream)
 {
+    return rsf_seeds_ex(ctx, volume, volume_dtype, nx, ny, nz, sigma_b, threshold, mask, n_seeds,
+                        nullptr, 0, stream);
+}
+
+size_t rsf_seeds_workspace_bytes(int64_t nx, int64_t ny, int64_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nx > (int64_t(1) << 40) / ny / nz) return 0;
+    return seeds_scratch_bytes(nx * ny * nz);
+}
+
+rsf_status rsf_seeds_ex(rsf_context *ctx, const void *volume, int volume_dtype, int64_t nx,
+                        int64_t ny, int64_t nz, float sigma_b, float threshold,
+                        unsigned char *mask, int64_t *n_seeds, void *workspace,
+                        size_t workspace_bytes, void *stream)
+{
     try {
         if (!ctx) return RSF_ERR_INVALID_ARG;
         ctx->err.clear();
         rsf_status st = check_seed_args(ctx, volume, volume_dtype, nx, ny, nz, sigma_b, threshold);
         if (st != RSF_OK) return st;
         if (!mask) return fail(ctx, RSF_ERR_INVALID_ARG, "null mask");
+        if (workspace && workspace_bytes < seeds_scratch_bytes(nx * ny * nz))
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
         st = set_device(ctx);
         if (st != RSF_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        Scratch sc;
+        Scratch sc = workspace ? Scratch(workspace, workspace_bytes) : Scratch();
         float *u = nullptr;
         HIP_TRY(sc.get(&u, (size_t)(nx * ny * nz) * 4), "hipMalloc(seed scratch)");
         st = seeds_impl(ctx, sc, volume, volume_dtype, nx, ny, nz, sigma_b, threshold, mask, u,

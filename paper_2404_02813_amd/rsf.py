@@ -45,7 +45,8 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_server_drain", "rsf_server_get_stats", "rsf_server_last_error",
            "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe",
            "rsf_volume_workspace_bytes", "rsf_evolve_volume_ex", "rsf_init_workspace_bytes",
-           "rsf_init_phi_ex", "rsf_set_fault", "rsf_fault_allocations")
+           "rsf_init_phi_ex", "rsf_set_fault", "rsf_fault_allocations", "rsf_seeds_ex",
+           "rsf_seeds_workspace_bytes")
 
 RSF_NOALLOC_MAX_BYTES = 128 << 20
 
@@ -177,6 +178,10 @@ def lib() -> ctypes.CDLL:
     i64p = ctypes.POINTER(ctypes.c_int64)
     L.rsf_seeds.argtypes = [vp, vp, i, i64, i64, i64, f, f, vp, i64p, vp]
     L.rsf_seeds.restype = i
+    L.rsf_seeds_ex.argtypes = [vp, vp, i, i64, i64, i64, f, f, vp, i64p, vp, ctypes.c_size_t, vp]
+    L.rsf_seeds_ex.restype = i
+    L.rsf_seeds_workspace_bytes.argtypes = [i64, i64, i64]
+    L.rsf_seeds_workspace_bytes.restype = ctypes.c_size_t
     L.rsf_fast_sweep.argtypes = [vp, vp, i64, i64, i64, i, vp]
     L.rsf_fast_sweep.restype = i
     L.rsf_init_phi.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, i, i64p, vp]
@@ -429,8 +434,10 @@ def rsf_stream_probe(inp: torch.Tensor, n_read: int, out: torch.Tensor, n_write:
 
 
 def rsf_seeds(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
-              mask: torch.Tensor | None = None, stream=None):
-    """Seed mask (uint8 tensor) and the seed count."""
+              mask: torch.Tensor | None = None, stream=None, workspace: torch.Tensor = None):
+    """Seed mask (uint8 tensor) and the seed count.  With `workspace` (a
+    device tensor of at least rsf_seeds_workspace_bytes bytes) the scratch is
+    the caller's (rsf_seeds_ex)."""
     _field(volume, "volume", "image")
     nz, ny, nx = volume.shape
     if mask is None:
@@ -438,10 +445,32 @@ def rsf_seeds(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
     if mask.dtype != torch.uint8 or mask.shape != volume.shape or not mask.is_contiguous():
         raise ValueError("mask must be a contiguous uint8 tensor of the volume's shape")
     n = ctypes.c_int64(0)
-    _check(ctx, lib().rsf_seeds(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype], nx, ny, nz,
-                                float(sigma_b), float(threshold), mask.data_ptr(), ctypes.byref(n),
-                                _stream(stream)))
+    if workspace is None:
+        _check(ctx, lib().rsf_seeds(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype], nx, ny,
+                                    nz, float(sigma_b), float(threshold), mask.data_ptr(),
+                                    ctypes.byref(n), _stream(stream)))
+        return mask, n.value
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(ctx, lib().rsf_seeds_ex(ctx, volume.data_ptr(), _IMAGE_DTYPES[volume.dtype], nx, ny, nz,
+                                   float(sigma_b), float(threshold), mask.data_ptr(),
+                                   ctypes.byref(n), workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size(), _stream(stream)))
     return mask, n.value
+
+
+def rsf_seeds_ex(ctx, volume: torch.Tensor, sigma_b: float, threshold: float,
+                 mask: torch.Tensor | None, workspace: torch.Tensor, stream=None):
+    """rsf_seeds with its scratch in `workspace`."""
+    if workspace is None:
+        raise ValueError("rsf_seeds_ex needs a workspace")
+    return rsf_seeds(ctx, volume, sigma_b, threshold, mask, stream, workspace)
+
+
+def rsf_seeds_workspace_bytes(shape) -> int:
+    """Device bytes rsf_seeds_ex needs for a volume of shape (nz, ny, nx)."""
+    nz, ny, nx = shape
+    return int(lib().rsf_seeds_workspace_bytes(int(nx), int(ny), int(nz)))
 
 
 def rsf_fast_sweep(ctx, u: torch.Tensor, rounds: int = 2, stream=None) -> None:
@@ -682,8 +711,8 @@ class Context:
     def set_fusion(self, on: bool) -> None:
         rsf_set_fusion(self.handle, on)
 
-    def seeds(self, volume, sigma_b, threshold, mask=None, stream=None):
-        return rsf_seeds(self.handle, volume, sigma_b, threshold, mask, stream)
+    def seeds(self, volume, sigma_b, threshold, mask=None, stream=None, workspace=None):
+        return rsf_seeds(self.handle, volume, sigma_b, threshold, mask, stream, workspace)
 
     def fast_sweep(self, u, rounds=2, stream=None):
         rsf_fast_sweep(self.handle, u, rounds, stream)

@@ -205,3 +205,30 @@ def test_init_phi_caller_workspace_is_bitwise_the_same(rsf):
     torch.cuda.synchronize()
     assert torch.all(phi == 7.0)
     assert mod.rsf_init_workspace_bytes((0, 4, 4)) == 0
+
+
+def test_seeds_caller_workspace_is_bitwise_the_same(rsf):
+    """rsf_seeds_ex on a reused workspace (second call smaller) equals
+    rsf_seeds; a short or misaligned workspace is refused, mask untouched."""
+    mod, ctx = rsf
+    say("seeds: caller workspace")
+    need = mod.rsf_seeds_workspace_bytes((14, 50, 58))
+    assert need == mod.rsf_init_workspace_bytes((14, 50, 58)) - ((14 * 50 * 58 + 255) // 256) * 256
+    big = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    ws = big[:need]
+    for shape, seed in [((14, 50, 58), 47), ((7, 33, 31), 48)]:
+        vol, _ = volume("f32", shape, seed)
+        want, n0 = ctx.seeds(vol, 2.0, 0.05)
+        got, n1 = mod.rsf_seeds_ex(ctx.handle, vol, 2.0, 0.05, None, ws)
+        torch.cuda.synchronize()
+        assert n0 == n1 and n0 > 0
+        assert torch.equal(got, want)
+    vol, _ = volume("f32", (14, 50, 58), 49)
+    mask = torch.full((14, 50, 58), 9, dtype=torch.uint8, device="cuda")
+    for bad in (ws[:need - 1], big[1:need + 1]):
+        with pytest.raises(mod.RsfError) as e:
+            mod.rsf_seeds_ex(ctx.handle, vol, 2.0, 0.05, mask, bad)
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(mask == 9)
+    assert mod.rsf_seeds_workspace_bytes((4, 0, 4)) == 0

@@ -184,3 +184,34 @@ def test_mixed_precision_recipe_150_iterations(rsf, mixed, storage):
     assert stage1 == (1 if fused else 150)
     r = report(got, want)
     assert r["max"] <= phi_tol(storage) and r["agree"] >= SIGN_AGREE
+
+
+def test_shrinking_ball_follows_the_radial_curvature_flow(rsf):
+    """Curvature flow of a ball through the C ABI against the continuum
+    equations directly (no oracle): constant image (F_d = 0), mu = 0, phi0 =
+    r - rho.  kappa = -2/rho for any radially decreasing profile, so each
+    voxel follows f' = -nu delta(f) 2/rho, stepped with the same Euler step;
+    the GPU's gap to it is the grid's O(h^2) curvature error (0.0042 in the
+    oracle at this size, under 2 % of the front's 0.26-voxel displacement),
+    plus FP32 rounding."""
+    mod, ctx = rsf
+    say("shrinking ball: 32^3, eps 2, 64 iterations, against the per-voxel ODE")
+    n, r, eps, dt, iters = 32, 8.0, 2.0, 0.1, 64
+    c = (n - 1) / 2.0
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    rho = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    phi0 = (r - rho).astype(np.float32)
+    vol = torch.full((n, n, n), 0.5, dtype=torch.float32, device="cuda")
+    phi = torch.from_numpy(phi0).cuda()
+    ctx.evolve_ex(vol, phi, mod.make_params(sigma=1.0, lambda1=1.0, lambda2=1.0, nu=1.0,
+                                            mu=0.0, dt=dt, eps=eps), iters)
+    got = phi.cpu().numpy().astype(np.float64)
+    f = phi0.astype(np.float64)
+    for _ in range(iters):
+        f = f + dt * (eps / np.pi) / (eps * eps + f * f) * (-2.0 / rho)
+    shell = np.abs(rho - r) <= 3
+    moved = np.abs(f - phi0)[shell].max()
+    gap = np.abs(got - f)[shell].max()
+    say(f"  front moved {moved:.4f}, max gap {gap:.2e}")
+    assert 0.2 < moved < 0.3
+    assert gap <= 0.02 * moved
