@@ -238,11 +238,31 @@ rsf_status rsf_evolve_batch(rsf_context *ctx, const rsf_tile *tiles, int n_tiles
  * phi after an evolution is bitwise independent of the split and schedule;
  * the FP64 sums of |dphi| are grouped per update workgroup, so they may
  * differ in the last bits.  Synchronises `stream`; allocates a scratch copy
- * of phi for the duration of the call; invalidates the statistics of the
- * last evolution. */
+ * of phi for the duration of the call (rsf_autotune_ex takes it from the
+ * caller); invalidates the statistics of the last evolution. */
 rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, int volume_dtype,
                         const rsf_params *params, int trial_iters, int64_t *chosen,
                         void *stream);
+
+/* Device bytes of rsf_autotune_ex's workspace for these tiles: the copies of
+ * their phi (each rounded up to 256 bytes) and the batch workspace of the
+ * largest trial any candidate split can need (trial_iters + 1 iterations).
+ * Depends on the context's workgroup targets.  0 for invalid arguments. */
+size_t rsf_autotune_workspace_bytes(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                                    const rsf_params *params, int trial_iters);
+
+/* rsf_autotune with the phi copies and every trial's batch workspace in the
+ * caller's workspace (device, 256-byte aligned, at least
+ * rsf_autotune_workspace_bytes(...) bytes; NULL allocates as rsf_autotune
+ * does, the trials then using the context's own workspace), so that the call
+ * allocates no device memory.  RSF_ERR_INVALID_ARG for a workspace that is
+ * too small or misaligned, before anything runs.  The choices and the
+ * statistics of the last evolution follow rsf_autotune, except that the
+ * context's own workspace and its statistics are left alone. */
+rsf_status rsf_autotune_ex(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                           int volume_dtype, const rsf_params *params, int trial_iters,
+                           int64_t *chosen, void *workspace, size_t workspace_bytes,
+                           void *stream);
 
 /* Workgroup targets of a whole batch (xy waves, z-pass workgroups, update-
  * pass workgroups) from which untuned splits are derived, each tile taking

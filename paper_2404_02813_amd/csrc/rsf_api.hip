@@ -463,6 +463,18 @@ bool decide_fuse(const rsf_context *ctx, const rsf_params &p, bool probe, const 
 
 // Tuned split of the shape if there is one, else the default for its share;
 // `whole_z`: one update chunk per tile (the fused update).
+// A tile's split when nothing is tuned for it: a single volume with the
+// built-in targets is split for the resident capacity, anything else by its
+// voxel share of the context's targets.
+Split base_split(const rsf_context *ctx, const Grid3 &g, double share, int n, int R)
+{
+    const rsf::Targets tg = ctx ? ctx->targets : rsf::kDefaultTargets;
+    const bool own_targets = tg.xy != rsf::kDefaultTargets.xy ||
+                             tg.z != rsf::kDefaultTargets.z || tg.u != rsf::kDefaultTargets.u;
+    return n == 1 && !own_targets && R > 0 ? rsf::capacity_split(g, R)
+                                           : rsf::default_split(g, share, tg);
+}
+
 std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, int R,
                               bool whole_z)
 {
@@ -470,12 +482,7 @@ std::vector<Split> splits_for(rsf_context *ctx, const rsf_tile *tiles, int n, in
     std::vector<Split> splits;
     for (int t = 0; t < n; ++t) {
         const Grid3 g = grid_of(tiles[t]);
-        const rsf::Targets tg = ctx ? ctx->targets : rsf::kDefaultTargets;
-        const bool own_targets = tg.xy != rsf::kDefaultTargets.xy ||
-                                 tg.z != rsf::kDefaultTargets.z || tg.u != rsf::kDefaultTargets.u;
-        // a single volume with the built-in targets: split for the resident capacity
-        Split s = n == 1 && !own_targets && R > 0 ? rsf::capacity_split(g, R)
-                                                  : rsf::default_split(g, sh[t], tg);
+        Split s = base_split(ctx, g, sh[t], n, R);
         if (ctx) {
             auto it = ctx->tuned.find({g.nx, g.ny, g.nz, R});
             if (it != ctx->tuned.end() && rsf::split_valid(g, it->second)) s = it->second;
@@ -821,6 +828,57 @@ rsf_status evolve_impl(rsf_context *ctx, const rsf_tile *tiles, int n, int vdt,
     return RSF_OK;
 }
 
+// Candidate workgroup targets of the autotuner's coordinate search.
+constexpr int64_t kCandXy[] = {2048, 4096, 8192, 16384, 32768};
+constexpr int64_t kCandZ[] = {256, 512, 1024, 2048, 4096};
+constexpr int64_t kCandU[] = {128, 256, 512, 1024, 2048};
+
+// Device bytes of the autotuner's copies of the tiles' phi.
+size_t autotune_copy_bytes(const rsf_tile *tiles, int n)
+{
+    size_t total = 0;
+    for (int t = 0; t < n; ++t)
+        total += align_up((size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float));
+    return total;
+}
+
+// Batch workspace of the autotuner's largest trial: every split its
+// coordinate search can set (each target a candidate or the context's own),
+// for trial_iters + 1 iterations.
+size_t autotune_trial_ws(rsf_context *ctx, const rsf_tile *tiles, int n, const rsf_params &p,
+                         int trial_iters)
+{
+    const int R = radius_of(p.sigma);
+    const std::vector<double> sh = shares_of(tiles, n);
+    std::vector<int64_t> xs(std::begin(kCandXy), std::end(kCandXy));
+    std::vector<int64_t> zs(std::begin(kCandZ), std::end(kCandZ));
+    std::vector<int64_t> us(std::begin(kCandU), std::end(kCandU));
+    xs.push_back(ctx->targets.xy);
+    zs.push_back(ctx->targets.z);
+    us.push_back(ctx->targets.u);
+    size_t most = plan_layout(tiles, n, trial_iters + 1, p.storage, splits_for(ctx, tiles, n, R),
+                              rsf::host::needs_k2(p))
+                      .total;
+    std::vector<Split> sp((size_t)n);
+    for (int64_t a : xs)
+        for (int64_t b : zs)
+            for (int64_t c : us) {
+                for (int t = 0; t < n; ++t) {
+                    const Grid3 g = grid_of(tiles[t]);
+                    const auto part = [&](int64_t v) {
+                        return (int64_t)std::max(1.0, std::ceil((double)v * sh[t]));
+                    };
+                    // a candidate the tile cannot take leaves it on its base split
+                    const Split c1 = rsf::make_split(g, part(a), part(b), part(c));
+                    sp[(size_t)t] = rsf::split_valid(g, c1) ? c1 : base_split(ctx, g, sh[t], n, R);
+                }
+                most = std::max(most, plan_layout(tiles, n, trial_iters + 1, p.storage, sp,
+                                                  rsf::host::needs_k2(p))
+                                          .total);
+            }
+    return most;
+}
+
 // Time `iters` iterations of a planned batch (after its prologue) in ms.
 rsf_status time_iterations(rsf_context *ctx, const Plan &P, int iters, hipStream_t s, float *ms,
                            bool fused)
@@ -1160,7 +1218,30 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                         const rsf_params *params, int trial_iters, int64_t *chosen,
                         void *stream)
 {
-    float *trial_phi = nullptr;
+    return rsf_autotune_ex(ctx, tiles, n_tiles, volume_dtype, params, trial_iters, chosen,
+                           nullptr, 0, stream);
+}
+
+size_t rsf_autotune_workspace_bytes(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                                    const rsf_params *params, int trial_iters)
+{
+    try {
+        if (!ctx || !params || trial_iters < 1) return 0;
+        if (check_tiles(nullptr, tiles, n_tiles, false) != RSF_OK) return 0;
+        if (check_params(nullptr, *params) != RSF_OK) return 0;
+        return autotune_copy_bytes(tiles, n_tiles) +
+               autotune_trial_ws(ctx, tiles, n_tiles, *params, trial_iters);
+    } catch (...) {
+        return 0;
+    }
+}
+
+rsf_status rsf_autotune_ex(rsf_context *ctx, const rsf_tile *tiles, int n_tiles,
+                           int volume_dtype, const rsf_params *params, int trial_iters,
+                           int64_t *chosen, void *workspace, size_t workspace_bytes,
+                           void *stream)
+{
+    float *trial_phi = nullptr;   // owned (freed here) unless in the caller's workspace
     try {
         if (!ctx) return RSF_ERR_INVALID_ARG;
         ctx->err.clear();
@@ -1183,22 +1264,33 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
             off.push_back(total);
             total += align_up((size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float));
         }
-        HIP_TRY(rsf::dev_alloc(&trial_phi, total), "hipMalloc(autotune trial_phi)");
+        const size_t trial_ws = workspace ? autotune_trial_ws(ctx, tiles, n_tiles, *params,
+                                                              trial_iters)
+                                          : 0;
+        if (workspace && workspace_bytes < total + trial_ws)
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace too small");
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+            return fail(ctx, RSF_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        char *const trial_base = workspace ? static_cast<char *>(workspace) + total : nullptr;
+        if (workspace) trial_phi = static_cast<float *>(workspace);
+        else HIP_TRY(rsf::dev_alloc(&trial_phi, total), "hipMalloc(autotune trial_phi)");
+        auto release = [&] {
+            if (!workspace && trial_phi) (void)hipFree(trial_phi);
+            trial_phi = nullptr;
+        };
         std::vector<rsf_tile> tt(tiles, tiles + n_tiles);
         for (int t = 0; t < n_tiles; ++t) {
             tt[t].phi = reinterpret_cast<float *>(reinterpret_cast<char *>(trial_phi) + off[t]);
             const size_t bytes = (size_t)tiles[t].nx * tiles[t].ny * tiles[t].nz * sizeof(float);
             hipError_t e = hipMemcpyAsync(tt[t].phi, tiles[t].phi, bytes, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) {
-                (void)hipFree(trial_phi);
+                release();
                 return hip_fail(ctx, e, "autotune copy");
             }
         }
         // coordinate search over the three per-pass workgroup targets,
         // starting from the context's
-        const int64_t cand_xy[] = {2048, 4096, 8192, 16384, 32768};
-        const int64_t cand_z[] = {256, 512, 1024, 2048, 4096};
-        const int64_t cand_u[] = {128, 256, 512, 1024, 2048};
+        const int64_t *const cand_xy = kCandXy, *const cand_z = kCandZ, *const cand_u = kCandU;
         int64_t best[3] = {ctx->targets.xy, ctx->targets.z, ctx->targets.u};
         // targets are for the whole batch; each tile gets its voxel share
         const std::vector<double> sh = shares_of(tiles, n_tiles);
@@ -1220,19 +1312,24 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                                             splits_for(ctx, tt.data(), n_tiles, R),
                                             rsf::host::needs_k2(*params))
                                     .total;
-            rsf_status r = ensure_ws(ctx, need);
-            if (r == RSF_OK) r = ws_enter(ctx, s);
-            if (r != RSF_OK) return r;
-            ctx->has_last = false;   // the trials overwrite the workspace
+            rsf_status r = RSF_OK;
+            if (!workspace) {
+                r = ensure_ws(ctx, need);
+                if (r == RSF_OK) r = ws_enter(ctx, s);
+                if (r != RSF_OK) return r;
+                ctx->has_last = false;   // the trials overwrite the workspace
+            } else if (need > trial_ws) {
+                return fail(ctx, RSF_ERR_INTERNAL, "autotune trial outgrew its workspace");
+            }
             Plan P;
             r = make_plan(ctx, P, tt.data(), n_tiles, volume_dtype, *params, 0.0, runs,
-                          static_cast<char *>(ctx->ws), s);
+                          workspace ? trial_base : static_cast<char *>(ctx->ws), s);
             if (r == RSF_OK) r = prologue(ctx, P, s);
             const bool fused = P.fuse && ctx->fuse;
             if (r == RSF_OK && fused) r = stage1(ctx, P, false, s);
             if (r == RSF_OK) r = iteration(ctx, P, false, s, fused);   // warm-up
             if (r == RSF_OK) r = time_iterations(ctx, P, trial_iters, s, &ms, fused);
-            if (r == RSF_OK) r = ws_leave(ctx, s);
+            if (r == RSF_OK && !workspace) r = ws_leave(ctx, s);
             return r;
         };
         // The splits are searched with the passes separate (all three
@@ -1290,11 +1387,11 @@ rsf_status rsf_autotune(rsf_context *ctx, const rsf_tile *tiles, int n_tiles, in
                 ctx->tuned.erase({tiles[t].nx, tiles[t].ny, tiles[t].nz, R});
         }
         (void)hipStreamSynchronize(s);
-        (void)hipFree(trial_phi);
+        release();
         return st;
     } catch (...) {
         if (ctx) ctx->force_schedule = -1;
-        if (trial_phi) (void)hipFree(trial_phi);
+        if (trial_phi && !workspace) (void)hipFree(trial_phi);
         return fail(ctx, RSF_ERR_INTERNAL, "internal error");
     }
 }

@@ -46,7 +46,7 @@ EXPORTS = ("rsf_create", "rsf_destroy", "rsf_last_error", "rsf_workspace_bytes",
            "rsf_server_destroy", "rsf_evolve_noalloc", "rsf_set_graphs", "rsf_stream_probe",
            "rsf_volume_workspace_bytes", "rsf_evolve_volume_ex", "rsf_init_workspace_bytes",
            "rsf_init_phi_ex", "rsf_set_fault", "rsf_fault_allocations", "rsf_seeds_ex",
-           "rsf_seeds_workspace_bytes")
+           "rsf_seeds_workspace_bytes", "rsf_autotune_ex", "rsf_autotune_workspace_bytes")
 
 RSF_NOALLOC_MAX_BYTES = 128 << 20
 
@@ -182,6 +182,12 @@ def lib() -> ctypes.CDLL:
     L.rsf_seeds_ex.restype = i
     L.rsf_seeds_workspace_bytes.argtypes = [i64, i64, i64]
     L.rsf_seeds_workspace_bytes.restype = ctypes.c_size_t
+    L.rsf_autotune_ex.argtypes = [vp, ctypes.POINTER(rsf_tile), i, i, ctypes.POINTER(rsf_params),
+                                  i, ctypes.POINTER(ctypes.c_int64), vp, ctypes.c_size_t, vp]
+    L.rsf_autotune_ex.restype = i
+    L.rsf_autotune_workspace_bytes.argtypes = [vp, ctypes.POINTER(rsf_tile), i,
+                                               ctypes.POINTER(rsf_params), i]
+    L.rsf_autotune_workspace_bytes.restype = ctypes.c_size_t
     L.rsf_fast_sweep.argtypes = [vp, vp, i64, i64, i64, i, vp]
     L.rsf_fast_sweep.restype = i
     L.rsf_init_phi.argtypes = [vp, vp, i, vp, i64, i64, i64, f, f, f, i, i64p, vp]
@@ -393,6 +399,29 @@ def rsf_autotune(ctx, volumes, phis, params: rsf_params, trial_iters: int = 3,
     _check(ctx, lib().rsf_autotune(ctx, arr, len(volumes), vdt, ctypes.byref(params),
                                    int(trial_iters), chosen, _stream(stream)))
     return tuple(chosen)
+
+
+def rsf_autotune_ex(ctx, volumes, phis, params: rsf_params, trial_iters: int,
+                    workspace: torch.Tensor, stream=None) -> tuple:
+    """rsf_autotune with the phi copies and trial workspaces in `workspace`."""
+    if workspace is None or not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    arr, vdt = _tiles(volumes, phis)
+    chosen = (ctypes.c_int64 * 4)()
+    _check(ctx, lib().rsf_autotune_ex(ctx, arr, len(volumes), vdt, ctypes.byref(params),
+                                      int(trial_iters), chosen, workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(),
+                                      _stream(stream)))
+    return tuple(chosen)
+
+
+def rsf_autotune_workspace_bytes(ctx, shapes, params: rsf_params, trial_iters: int = 3) -> int:
+    """Device bytes rsf_autotune_ex needs; shapes: list of (nz, ny, nx)."""
+    arr = (rsf_tile * len(shapes))()
+    for k, (nz, ny, nx) in enumerate(shapes):
+        arr[k] = rsf_tile(None, None, nx, ny, nz)
+    return int(lib().rsf_autotune_workspace_bytes(ctx, arr, len(shapes), ctypes.byref(params),
+                                                  int(trial_iters)))
 
 
 def rsf_workspace_bytes_params(nx: int, ny: int, nz: int, iters: int, params: rsf_params) -> int:

@@ -478,6 +478,60 @@ def test_autotune_keeps_results(rsf):
         ctx.autotune_reset()
 
 
+def test_autotune_on_caller_workspace(rsf):
+    """rsf_autotune_ex keeps the caller's phi and the context's last
+    statistics, allocates no device memory (on a fresh context its only
+    allocation is the pinned staging of the tile table), and the evolution
+    after it is bitwise the untuned one; a short workspace is refused."""
+    mod, ctx = rsf
+    say("autotune on a caller workspace")
+    vols, phis = batch_inputs(82)
+    p = params(mod, sigma=3.0)
+    dv = [dev(v) for v in vols]
+    ref = [dev(q) for q in phis]
+    ctx.evolve_batch(dv, ref, p, 10)
+    torch.cuda.synchronize()
+    fresh = mod.Context(0)
+    try:
+        shapes = [tuple(v.shape) for v in vols]
+        need = mod.rsf_autotune_workspace_bytes(fresh.handle, shapes, p, 2)
+        assert need > sum(v.size * 4 for v in vols)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        probe = [dev(q) for q in phis]
+        with pytest.raises(mod.RsfError) as e:
+            mod.rsf_autotune_ex(fresh.handle, dv, probe, p, 2, ws[:need - 1])
+        assert e.value.status == mod.RSF_ERR_INVALID_ARG
+        fresh.evolve_batch(dv, probe, p, 10)
+        torch.cuda.synchronize()
+        before = fresh.stats(cap=0)
+        for k in range(len(vols)):
+            probe[k].copy_(dev(phis[k]))
+        torch.cuda.synchronize()
+        mod.rsf_set_fault("alloc_fail:1000000000")
+        try:
+            fresh2 = mod.Context(0)
+            try:
+                mod.rsf_autotune_ex(fresh2.handle, dv, probe, p, 2, ws)
+                torch.cuda.synchronize()
+                assert mod.rsf_fault_allocations() == 1      # the pinned table staging
+            finally:
+                fresh2.close()
+        finally:
+            mod.rsf_set_fault(None)
+        chosen = mod.rsf_autotune_ex(fresh.handle, dv, probe, p, 2, ws)
+        torch.cuda.synchronize()
+        assert len(chosen) == 4
+        assert fresh.stats(cap=0) == before
+        for k in range(len(vols)):
+            assert torch.equal(probe[k], dev(phis[k])), k
+        fresh.evolve_batch(dv, probe, p, 10)
+        torch.cuda.synchronize()
+        for k in range(len(vols)):
+            assert torch.equal(probe[k], ref[k]), k
+    finally:
+        fresh.close()
+
+
 # --- the update fused with the next iteration's stage-1 z pass -----------------------
 
 # Fusion needs every tile's update marched whole in z: volumes whose xy plane
